@@ -1,0 +1,184 @@
+/*
+ * mpo.h - C ABI of libmpo, an MI355X (gfx950) engine for simulating noisy
+ * one-dimensional random circuits with matrix product operators.
+ *
+ * Method: K. Noh, L. Jiang, B. Fefferman, "Efficient classical simulation of
+ * noisy random quantum circuits in one dimension", Quantum 4, 318 (2020).
+ * The density matrix is vectorised site by site (Sec. III.A: merged index
+ * I = 2 i + i' for |i><i'|) and held as an MPS with physical dimension 4
+ * (Eq. "MPO") in mixed canonical form.  A noisy two-qubit gate is one 16x16
+ * superoperator M = N . U (Sec. III.B) applied to two neighbouring sites,
+ * after which the bond is re-split by a truncated SVD (App. A; "Note added":
+ * orthogonality centre moved locally, then a local truncation).
+ *
+ * Conventions for every entry point:
+ *   - sites are 0-based, s in [0, n-1]; a gate acts on (s, s+1); bond b sits
+ *     between sites b and b+1 (the paper's 1-based l is b+1);
+ *   - host complex numbers are interleaved (re, im) float64, host matrices are
+ *     row-major;
+ *   - superoperator element [row][col] with row = 4*I_s + I_{s+1},
+ *     col = 4*J_s + J_{s+1} (App. A, definition of M); in the Pauli basis the
+ *     site index is P in {I,X,Y,Z} = {0,1,2,3} for the normalised operator
+ *     sigma_P/sqrt(2);
+ *   - the caller owns the device arena, the HIP stream and every host buffer;
+ *     the library never allocates or frees device memory;
+ *   - errors are returned as mpo_status with a message from mpo_last_error();
+ *     an argument error leaves the state untouched; a numeric fault (non-finite
+ *     values, SVD not converged) poisons the handle until mpo_init_product or
+ *     mpo_import succeeds;
+ *   - a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef MPO_H
+#define MPO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpo_handle mpo_handle;
+
+typedef enum {
+    MPO_OK = 0,
+    MPO_ERR_ARG = 1,      /* invalid argument; nothing changed               */
+    MPO_ERR_ARENA = 2,    /* device arena too small                          */
+    MPO_ERR_HIP = 3,      /* HIP runtime error                               */
+    MPO_ERR_NUMERIC = 4,  /* NaN/Inf met; handle poisoned                    */
+    MPO_ERR_NOCONV = 5,   /* SVD sweep limit reached; handle poisoned        */
+    MPO_ERR_STATE = 6     /* handle poisoned by an earlier numeric fault     */
+} mpo_status;
+
+typedef enum {
+    MPO_FP64 = 0,       /* complex128 tensors, FP64 MFMA contractions        */
+    MPO_FP32_MFMA = 1   /* complex64 tensors and contractions on FP32 MFMA;
+                           truncation weights and entropy in FP64            */
+} mpo_precision;
+
+typedef enum { MPO_BASIS_PAULI = 0, MPO_BASIS_COMPUTATIONAL = 1 } mpo_basis;
+
+/* Result of one truncated split (App. A: keep the largest singular values).
+ * kept: number of singular values kept, k = max(1, min(chi_max,
+ *       #{alpha : lambda_alpha / ||lambda||_2 > cutoff})), norm over the full
+ *       pre-truncation spectrum;
+ * discarded_weight: sum of lambda^2 over the dropped values;
+ * total_weight: sum of lambda^2 over all values (= ||theta'||_F^2);
+ * entropy: MPO entanglement entropy of the kept values (Sec. III.C, Eq. S_l),
+ *          -sum w log2 w with w = lambda^2 / sum_kept lambda^2.            */
+typedef struct {
+    int kept;
+    double discarded_weight;
+    double total_weight;
+    double entropy;
+} mpo_trunc_info;
+
+/* Device bytes needed for a chain of n sites with bond cap chi_cap.  The arena
+ * holds n+2 site slots of 4*chi_cap^2 complex values plus the SVD workspace. */
+mpo_status mpo_workspace_bytes(int n, int chi_cap, mpo_precision prec, size_t *bytes);
+
+/* Create a handle over a caller-owned device arena (256-byte aligned, at
+ * least mpo_workspace_bytes) and HIP stream (NULL = default stream).
+ * n even and >= 2 (Sec. II.A), 1 <= chi_cap <= 1024.  The state starts as
+ * |0..0><0..0| (Sec. IV.A initial MPO).                                      */
+mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis,
+                      void *dev_arena, size_t arena_bytes, void *hip_stream,
+                      mpo_handle **out);
+void mpo_destroy(mpo_handle *h);
+
+/* Product state |x><x| with x given as n bytes in {0,1}; NULL = all zero
+ * (Sec. IV.A: lambda = (1,0,...), Gamma = 1 at alpha = I = 0).  All bond
+ * dimensions become 1, the orthogonality centre is site 0.                   */
+mpo_status mpo_init_product(mpo_handle *h, const unsigned char *bits);
+
+/* Apply a 16x16 complex superoperator (host, row-major, interleaved, in the
+ * handle's basis) to sites (site, site+1): move the orthogonality centre to
+ * `site` (exact), contract the two sites, apply the map, split by a truncated
+ * SVD (App. A truncation; "Note added" local update).  Afterwards site is a
+ * left isometry and site+1 the centre.  info != NULL synchronises the stream
+ * and fills it; info == NULL leaves the call stream-ordered except for one
+ * small device-to-host read of the kept count.                              */
+mpo_status mpo_apply_2q_channel(mpo_handle *h, int site, const double *superop,
+                                int chi_max, double cutoff, mpo_trunc_info *info);
+
+/* Move the orthogonality centre to `center` by exact re-gauging (no
+ * truncation beyond singular values below the working precision).            */
+mpo_status mpo_canonicalize(mpo_handle *h, int center);
+
+/* MPO entanglement entropy S_b (Sec. III.C, Eq. S_l, log base 2) from the
+ * Schmidt values of the current state at bond b in [0, n-2]; bond = -1 writes
+ * all n-1 values (one canonical sweep).  Synchronises.                       */
+mpo_status mpo_bond_entropy(mpo_handle *h, int bond, double *S);
+
+/* Schmidt values at bond b, descending, at most cap of them; *count = number
+ * available.  Synchronises.                                                  */
+mpo_status mpo_singular_values(mpo_handle *h, int bond, double *lam, int cap, int *count);
+
+/* Tr[P rho] / Tr[rho] for a Pauli string (n codes 0=I 1=X 2=Y 3=Z) by
+ * transfer contraction (Sec. III.D); im is a Hermiticity diagnostic.        */
+mpo_status mpo_expect_pauli(mpo_handle *h, const unsigned char *pauli, double *re, double *im);
+
+/* Total probability Tr[rho] (Sec. III.D); below 1 after truncation.          */
+mpo_status mpo_trace(mpo_handle *h, double *re, double *im);
+
+/* All <Z_i> = Tr[Z_i rho]/Tr[rho] (n values) and Tr[rho].                    */
+mpo_status mpo_expect_z_all(mpo_handle *h, double *z, double *trace);
+
+/* Current bond dimensions (n-1 values) and orthogonality centre.            */
+mpo_status mpo_bond_dims(mpo_handle *h, int *dims, int *center);
+
+/* Brickwork evolution (Sec. II.A, Sec. IV.A): time step t = 1..depth puts a
+ * gate on (0,1),(2,3),... for odd t and on (1,2),(3,4),... for even t, applied
+ * in ascending site order.  superops: n_gates x 16 x 16 complex in schedule
+ * order, n_gates = ceil(D/2) n/2 + floor(D/2) (n/2-1), else MPO_ERR_ARG.
+ * record_mask bit 0: after every time step write S_b for all n-1 bonds to
+ * S_out[t*(n-1)+b], <Z_i> to Z_out[t*n+i] and Tr rho to trace_out[t];
+ * bit 1: the same only after the last time step (index 0).  Outputs may be
+ * NULL when not recorded.  discarded_out (n_gates values or NULL) receives
+ * the discarded weight of every gate.  Evolution continues from the current
+ * state.                                                                     */
+mpo_status run_brickwork(mpo_handle *h, int depth, const double *superops, int n_gates,
+                         int chi_max, double cutoff, int record_mask,
+                         double *S_out, double *Z_out, double *trace_out,
+                         double *discarded_out);
+
+/* Host snapshot of the state.  Format: int64 header {magic 0x4d504f31, n,
+ * basis, center, chi_0 .. chi_{n-2}} then per site the (chi_l, 4, chi_r)
+ * tensor, row-major, complex128.  host_buf may be NULL to query *used.       */
+mpo_status mpo_export(mpo_handle *h, void *host_buf, size_t cap, size_t *used);
+/* Load a snapshot (any gauge); it is brought into canonical form.            */
+mpo_status mpo_import(mpo_handle *h, const void *host_buf, size_t len);
+
+/* Noisy Haar gate superoperator, host only: U = Haar unitary from one complex
+ * Ginibre draw (re, im: 4x4 row-major float64; Q of a QR with positive R
+ * diagonal, Mezzadri 2007), M = N2[p] . U in the given basis (Sec. II.B
+ * depolarizing channel, Sec. III.B M = N . U, App. A element definition).
+ * out: 16x16 complex interleaved row-major.  Also writes U (4x4 complex
+ * interleaved) to u_out unless NULL.                                         */
+mpo_status mpo_build_superop(const double *re, const double *im, double p, mpo_basis basis,
+                             double *out, double *u_out);
+
+/* Instrumentation: per-kernel-class timing with HIP events recorded on the
+ * handle's stream around every launch, plus the algorithmic flop and byte
+ * counts of those launches (real flops; complex MAC = 8).  Enabling resets
+ * the counters.  Timing adds two event records per launch.                   */
+typedef struct {
+    char name[24];      /* theta_channel, jacobi_gram, jacobi_eig64, ...      */
+    long long launches;
+    double ms;          /* summed event-measured duration                    */
+    double flops;       /* algorithmic real flops of those launches          */
+    double bytes;       /* algorithmic HBM bytes of those launches           */
+} mpo_kernel_stat;
+mpo_status mpo_profile_enable(mpo_handle *h, int on);
+/* Synchronises.  Writes up to cap entries; *count = number of kernel classes.
+ * svd_counters (4 values or NULL): splits, Jacobi sweeps, Jacobi rounds,
+ * rotated block pairs.                                                      */
+mpo_status mpo_profile_read(mpo_handle *h, mpo_kernel_stat *out, int cap, int *count,
+                            long long *svd_counters);
+
+/* Last error message of the calling thread ("" if none).                     */
+const char *mpo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPO_H */

@@ -1,0 +1,800 @@
+// libmpo C ABI: handle, arena layout and the host sequencing of the kernels.
+//
+// State: the vectorised density matrix (Sec. III.A) as an MPS with physical
+// dimension 4 in mixed canonical form; site s holds A[a, I, c] at
+// a + chiL*(I + 4c) in its own arena slot.  A gate follows the "Note added"
+// update: exact centre moves, then contraction + channel + truncated SVD of the
+// two-site block (App. A truncation).  Bond dimensions live on the host; the
+// kept count of every split is read back once per split.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpo.h"
+#include "common.h"
+
+using namespace mpo;
+
+namespace {
+
+thread_local std::string g_err;
+
+mpo_status fail(mpo_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+mpo_status fail(mpo_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define HIPCHK(x)                                              \
+    do {                                                       \
+        hipError_t _e = (x);                                   \
+        if (_e != hipSuccess) throw HipError{_e, #x};          \
+    } while (0)
+
+struct NumericError { const char* what; };
+struct NoConvError { const char* what; };
+
+constexpr int kMaxSuper = 1024;     // superoperators resident per upload
+constexpr int kSplitsMax = 16;
+constexpr int kMaxSweeps = 60;
+constexpr int kRightChunksMax = 64;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t slot_bytes, slots, x_bytes, r_bytes, partial_bytes, w_bytes, skip_bytes, vecN_bytes,
+        info_bytes, env_bytes, tscr_bytes, vec_bytes, dot_bytes, super_bytes, total;
+    int max_pairs;
+};
+
+Layout make_layout(int n, int chi_cap, mpo_precision prec) {
+    Layout L{};
+    const size_t csz = prec == MPO_FP64 ? 16 : 8;
+    const size_t cc = (size_t)chi_cap * chi_cap;
+    L.slot_bytes = align256(4 * cc * csz);
+    L.slots = (size_t)n + 2;
+    L.x_bytes = align256(16 * cc * csz);
+    L.r_bytes = align256(cc * csz);
+    int nb = (4 * chi_cap + 31) / 32;
+    if (nb < 2) nb = 2;
+    if (nb & 1) ++nb;
+    L.max_pairs = nb / 2;
+    L.partial_bytes = align256((size_t)L.max_pairs * kSplitsMax * 4096 * csz);
+    L.w_bytes = align256((size_t)L.max_pairs * 4096 * csz);
+    L.skip_bytes = align256((size_t)L.max_pairs * sizeof(int));
+    L.vecN_bytes = align256((size_t)4 * chi_cap * sizeof(double));
+    L.info_bytes = align256(sizeof(DevInfo));
+    L.env_bytes = align256((size_t)(n + 1) * chi_cap * sizeof(double2));
+    L.tscr_bytes = align256((size_t)kRightChunksMax * chi_cap * sizeof(double2));
+    L.vec_bytes = align256((size_t)(n + 2) * 4 * sizeof(double2));
+    L.dot_bytes = align256((size_t)(n + 2) * sizeof(double2));
+    L.super_bytes = align256((size_t)kMaxSuper * 256 * csz);
+    L.total = L.slot_bytes * L.slots + 2 * L.x_bytes + L.r_bytes + L.partial_bytes + L.w_bytes +
+              L.skip_bytes + 3 * L.vecN_bytes + L.info_bytes + 2 * L.env_bytes + L.tscr_bytes +
+              align256((size_t)chi_cap * sizeof(double2)) + L.vec_bytes + L.dot_bytes +
+              L.super_bytes;
+    return L;
+}
+
+}  // namespace
+
+struct mpo_handle {
+    int n = 0, chi_cap = 0;
+    mpo_precision prec = MPO_FP64;
+    mpo_basis basis = MPO_BASIS_PAULI;
+    hipStream_t st = nullptr;
+    size_t csz = 16;
+    std::vector<char*> slot;     // slot base addresses
+    std::vector<int> site_slot;  // slot index of every site
+    std::vector<int> spare;      // free slot indices
+    std::vector<int> dims;       // bond b in [0, n-2]
+    int centre = 0;
+    bool poisoned = false;
+    char *X = nullptr, *X2 = nullptr, *R = nullptr, *Mdev = nullptr;
+    JacobiWork jw{};
+    double2 *envL = nullptr, *envR = nullptr, *tscr = nullptr, *tmp = nullptr, *vecs = nullptr,
+            *dots = nullptr;
+    double* sig2_all = nullptr;  // copy of the last split's sorted squared values
+    // pinned host staging
+    DevInfo* info_host = nullptr;
+    void* super_stage = nullptr;
+    double2* small_host = nullptr;   // >= n+2 values
+    double* sig_host = nullptr;      // 4*chi_cap
+    Profiler prof;
+    std::vector<double> last_S;      // per bond, filled by sweeps
+    std::vector<std::vector<double>> last_lam;
+
+    int chiL(int s) const { return s == 0 ? 1 : dims[s - 1]; }
+    int chiR(int s) const { return s == n - 1 ? 1 : dims[s]; }
+    char* site(int s) const { return slot[site_slot[s]]; }
+    int take_spare() { int k = spare.back(); spare.pop_back(); return k; }
+    void give_spare(int k) { spare.push_back(k); }
+};
+
+namespace {
+
+double eps_of(size_t csz) { return csz == 16 ? 2.220446049250313e-16 : 1.1920928955078125e-07; }
+
+double jacobi_tol(const mpo_handle* h, int m) {
+    const double e = eps_of(h->csz);
+    const double floor = h->csz == 16 ? 1e-14 : 1e-6;
+    return std::fmax(floor, 8.0 * std::sqrt((double)m) * e);
+}
+// singular values at or below this fraction of ||lambda||_2 carry no weight
+// above rounding and are dropped by exact re-gauging moves
+double regauge_cut(const mpo_handle* h) { return h->csz == 16 ? 1e-15 : 1e-7; }
+
+// Site dual vectors v[J] = Tr[P B_J] for the basis operators B_J.
+void dual_vector(mpo_basis basis, int code, double2 v[4]) {
+    for (int k = 0; k < 4; ++k) v[k] = make_double2(0.0, 0.0);
+    if (basis == MPO_BASIS_PAULI) {
+        v[code] = make_double2(std::sqrt(2.0), 0.0);
+        return;
+    }
+    // computational: B_{2i+i'} = |i><i'|, Tr[P |i><i'|] = P[i'][i]
+    switch (code) {
+        case 0: v[0] = make_double2(1, 0); v[3] = make_double2(1, 0); break;
+        case 1: v[1] = make_double2(1, 0); v[2] = make_double2(1, 0); break;
+        case 2: v[1] = make_double2(0, 1); v[2] = make_double2(0, -1); break;
+        case 3: v[0] = make_double2(1, 0); v[3] = make_double2(-1, 0); break;
+    }
+}
+
+// Coefficients of |x><x| in the site basis.
+void product_site(mpo_basis basis, int bit, double v[8]) {
+    for (int k = 0; k < 8; ++k) v[k] = 0.0;
+    if (basis == MPO_BASIS_COMPUTATIONAL) {
+        v[2 * (3 * bit)] = 1.0;
+    } else {
+        const double s = 1.0 / std::sqrt(2.0);
+        v[0] = s;                      // I component
+        v[2 * 3] = bit ? -s : s;       // Z component
+    }
+}
+
+template <typename T>
+struct Engine {
+    using C = C2<T>;
+    static C* site(mpo_handle* h, int s) { return (C*)h->site(s); }
+
+    static DevInfo read_info(mpo_handle* h) {
+        HIPCHK(hipMemcpyAsync(h->info_host, h->jw.info, sizeof(DevInfo), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+        return *h->info_host;
+    }
+
+    // Orthogonalise the columns of X (m x N); truncation with (chi_max, cutoff).
+    static DevInfo split(mpo_handle* h, int m, int N, int chi_max, double cutoff) {
+        const int sw = jacobi_orthogonalize<T>((C*)h->X, m, N, jacobi_tol(h, m), kMaxSweeps, h->jw, h->st);
+        if (sw == -2) HIPCHK(hipGetLastError());
+        if (sw == -3) throw HipError{hipErrorInvalidValue, "jacobi pair capacity"};
+        if (sw < 0) throw NoConvError{"one-sided Jacobi SVD did not converge"};
+        h->prof.begin(h->st);
+        launch_truncate(h->jw.sig2, N, chi_max, cutoff, jacobi_zero_rel2<T>(), h->jw.info, h->st);
+        h->prof.end(h->st, K_TRUNC, 0.0, 8.0 * N);
+        HIPCHK(hipGetLastError());
+        DevInfo inf = read_info(h);
+        if (inf.numeric_error) throw NumericError{"non-finite singular values"};
+        return inf;
+    }
+
+    // Centre c -> c+1: L(A_c) = U R exactly; A_c <- U, A_{c+1} <- R A_{c+1}.
+    static void move_right(mpo_handle* h, int c) {
+        const int chiL = h->chiL(c), chiR = h->dims[c], chiR2 = h->chiR(c + 1);
+        const int m = 4 * chiL, N = chiR;
+        h->prof.begin(h->st);
+        launch_copy<T>(site(h, c), (C*)h->X, (size_t)m * N, h->st);
+        h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * N);
+        DevInfo inf = split(h, m, N, N, regauge_cut(h));
+        const int r = inf.kept;
+        const int s1 = h->take_spare(), s2 = h->take_spare();
+        C* U = (C*)h->slot[s1];
+        C* Anext = (C*)h->slot[s2];
+        h->prof.begin(h->st);
+        launch_gather_cols<T>((C*)h->X, m, h->jw.colmap, h->jw.sig2, r, U, m, h->st);
+        h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * r);
+        h->prof.begin(h->st);
+        launch_cgemm<T>(1, 0, r, chiR, m, U, m, site(h, c), m, (C*)h->R, r, h->st);
+        launch_cgemm<T>(0, 0, r, 4 * chiR2, chiR, (C*)h->R, r, site(h, c + 1), chiR, Anext, r, h->st);
+        h->prof.end(h->st, K_GEMM, 8.0 * r * chiR * m + 8.0 * r * 4.0 * chiR2 * chiR,
+                    (double)sizeof(C) * (2.0 * m * chiR + (double)m * r + 8.0 * chiR * chiR2 + 4.0 * r * chiR2));
+        HIPCHK(hipGetLastError());
+        h->give_spare(h->site_slot[c]);
+        h->give_spare(h->site_slot[c + 1]);
+        h->site_slot[c] = s1;
+        h->site_slot[c + 1] = s2;
+        h->dims[c] = r;
+        h->centre = c + 1;
+    }
+
+    // Centre c -> c-1: R(A_c) = L Q exactly; the singular values found on the
+    // way are the Schmidt values of bond c-1 (all other sites are isometries).
+    static DevInfo move_left(mpo_handle* h, int c, bool keep_values) {
+        const int chiL = h->dims[c - 1], chiR = h->chiR(c), chiLL = h->chiL(c - 1);
+        const int m = 4 * chiR, N = chiL;
+        h->prof.begin(h->st);
+        launch_conj_transpose<T>(site(h, c), chiL, m, (C*)h->X, h->st);
+        h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * chiL);
+        DevInfo inf = split(h, m, N, N, regauge_cut(h));
+        const int r = inf.kept;
+        if (keep_values) {
+            HIPCHK(hipMemcpyAsync(h->sig_host, h->jw.sig2, sizeof(double) * r, hipMemcpyDeviceToHost, h->st));
+            HIPCHK(hipStreamSynchronize(h->st));
+            std::vector<double>& lam = h->last_lam[c - 1];
+            lam.resize(r);
+            for (int i = 0; i < r; ++i) lam[i] = std::sqrt(std::fmax(h->sig_host[i], 0.0));
+        }
+        h->last_S[c - 1] = inf.entropy;
+        const int s1 = h->take_spare(), s2 = h->take_spare();
+        C* Q = (C*)h->slot[s1];
+        C* Aprev = (C*)h->slot[s2];
+        h->prof.begin(h->st);
+        launch_gather_rows_conj<T>((C*)h->X, m, h->jw.colmap, h->jw.sig2, r, Q, h->st);
+        h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * r);
+        h->prof.begin(h->st);
+        launch_cgemm<T>(0, 1, chiL, r, m, site(h, c), chiL, Q, r, (C*)h->R, chiL, h->st);
+        launch_cgemm<T>(0, 0, 4 * chiLL, r, chiL, site(h, c - 1), 4 * chiLL, (C*)h->R, chiL, Aprev,
+                        4 * chiLL, h->st);
+        h->prof.end(h->st, K_GEMM, 8.0 * chiL * r * m + 8.0 * 4.0 * chiLL * r * chiL,
+                    (double)sizeof(C) * ((double)chiL * m + (double)r * m + 8.0 * chiLL * chiL + 4.0 * chiLL * r));
+        HIPCHK(hipGetLastError());
+        h->give_spare(h->site_slot[c]);
+        h->give_spare(h->site_slot[c - 1]);
+        h->site_slot[c] = s1;
+        h->site_slot[c - 1] = s2;
+        h->dims[c - 1] = r;
+        h->centre = c - 1;
+        return inf;
+    }
+
+    static void move_centre(mpo_handle* h, int target) {
+        while (h->centre < target) move_right(h, h->centre);
+        while (h->centre > target) move_left(h, h->centre, false);
+    }
+
+    // Gate on (s, s+1) with superoperator already on the device at Mg.
+    static mpo_trunc_info apply(mpo_handle* h, int s, const C* Mg, int chi_max, double cutoff) {
+        move_centre(h, s);
+        const int chiL = h->chiL(s), chiM = h->dims[s], chiR = h->chiR(s + 1);
+        const int m = 4 * chiL, N = 4 * chiR;
+        h->prof.begin(h->st);
+        launch_theta_channel<T>(chiL, chiM, chiR, site(h, s), site(h, s + 1), Mg, (C*)h->X,
+                                (C*)h->X2, h->st);
+        h->prof.end(h->st, K_THETA, 8.0 * m * chiM * N + 2048.0 * chiL * chiR,
+                    (double)sizeof(C) * (4.0 * chiL * chiM + 4.0 * chiM * chiR + 2.0 * m * N));
+        HIPCHK(hipGetLastError());
+        DevInfo inf = split(h, m, N, chi_max, cutoff);
+        const int k = inf.kept;
+        // A_s <- U_k (left isometry, in place); A_{s+1} <- U_k^H theta' (new centre)
+        h->prof.begin(h->st);
+        launch_gather_cols<T>((C*)h->X, m, h->jw.colmap, h->jw.sig2, k, site(h, s), m, h->st);
+        h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * k);
+        h->prof.begin(h->st);
+        launch_cgemm<T>(1, 0, k, N, m, site(h, s), m, (C*)h->X2, m, site(h, s + 1), k, h->st);
+        h->prof.end(h->st, K_GEMM, 8.0 * k * N * m, (double)sizeof(C) * ((double)m * k + (double)m * N + (double)k * N));
+        HIPCHK(hipGetLastError());
+        h->dims[s] = k;
+        h->centre = s + 1;
+        mpo_trunc_info out;
+        out.kept = k;
+        out.discarded_weight = inf.discarded;
+        out.total_weight = inf.total;
+        out.entropy = inf.entropy;
+        return out;
+    }
+
+    static void upload_super(mpo_handle* h, const double* superops, int count) {
+        T* stage = (T*)h->super_stage;
+        for (size_t i = 0; i < (size_t)count * 512; ++i) stage[i] = (T)superops[i];
+        HIPCHK(hipMemcpyAsync(h->Mdev, stage, (size_t)count * 256 * sizeof(C), hipMemcpyHostToDevice, h->st));
+    }
+
+    // Canonical sweep: centre to n-1, then to 0, recording every bond.
+    static void sweep_all(mpo_handle* h, bool keep_values) {
+        move_centre(h, h->n - 1);
+        for (int c = h->n - 1; c > 0; --c) move_left(h, c, keep_values);
+    }
+
+    // Tr rho and all <Z_i> numerators by transfer contraction (Sec. III.D).
+    static void observables(mpo_handle* h, double* z, double* trace_re, double* trace_im) {
+        const int n = h->n, cap = h->chi_cap;
+        double2 hv[8];
+        dual_vector(h->basis, 0, hv);
+        dual_vector(h->basis, 3, hv + 4);
+        HIPCHK(hipMemcpyAsync(h->vecs, hv, sizeof(hv), hipMemcpyHostToDevice, h->st));
+        const double2 one = make_double2(1.0, 0.0);
+        HIPCHK(hipMemcpyAsync(h->envL, &one, sizeof(one), hipMemcpyHostToDevice, h->st));
+        HIPCHK(hipMemcpyAsync(h->envR + (size_t)n * cap, &one, sizeof(one), hipMemcpyHostToDevice, h->st));
+        for (int s = 0; s < n; ++s)
+            launch_transfer_left<T>(site(h, s), h->chiL(s), h->chiR(s), h->envL + (size_t)s * cap,
+                                    h->vecs, h->envL + (size_t)(s + 1) * cap, h->st);
+        if (z) {
+            for (int s = n - 1; s >= 0; --s)
+                launch_transfer_right<T>(site(h, s), h->chiL(s), h->chiR(s),
+                                         h->envR + (size_t)(s + 1) * cap, h->vecs,
+                                         h->envR + (size_t)s * cap, h->tscr, h->st);
+            for (int i = 0; i < n; ++i) {
+                launch_transfer_left<T>(site(h, i), h->chiL(i), h->chiR(i), h->envL + (size_t)i * cap,
+                                        h->vecs + 4, h->tmp, h->st);
+                launch_dot(h->tmp, h->envR + (size_t)(i + 1) * cap, h->chiR(i), h->dots + i, h->st);
+            }
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(h->small_host, h->envL + (size_t)n * cap, sizeof(double2),
+                              hipMemcpyDeviceToHost, h->st));
+        if (z)
+            HIPCHK(hipMemcpyAsync(h->small_host + 1, h->dots, sizeof(double2) * n,
+                                  hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+        const double2 tr = h->small_host[0];
+        if (trace_re) *trace_re = tr.x;
+        if (trace_im) *trace_im = tr.y;
+        if (z) {
+            const double den = tr.x * tr.x + tr.y * tr.y;
+            for (int i = 0; i < n; ++i) {
+                const double2 v = h->small_host[1 + i];
+                z[i] = (v.x * tr.x + v.y * tr.y) / den;   // Re(v / tr)
+            }
+        }
+    }
+
+    static void pauli(mpo_handle* h, const unsigned char* codes, double* re, double* im) {
+        const int n = h->n, cap = h->chi_cap;
+        std::vector<double2> hv((size_t)(n + 1) * 4);
+        for (int s = 0; s < n; ++s) dual_vector(h->basis, codes[s], &hv[(size_t)4 * s]);
+        dual_vector(h->basis, 0, &hv[(size_t)4 * n]);
+        HIPCHK(hipMemcpyAsync(h->vecs, hv.data(), sizeof(double2) * hv.size(), hipMemcpyHostToDevice, h->st));
+        const double2 one = make_double2(1.0, 0.0);
+        HIPCHK(hipMemcpyAsync(h->envL, &one, sizeof(one), hipMemcpyHostToDevice, h->st));
+        HIPCHK(hipMemcpyAsync(h->envR, &one, sizeof(one), hipMemcpyHostToDevice, h->st));
+        for (int s = 0; s < n; ++s) {
+            launch_transfer_left<T>(site(h, s), h->chiL(s), h->chiR(s), h->envL + (size_t)s * cap,
+                                    h->vecs + 4 * s, h->envL + (size_t)(s + 1) * cap, h->st);
+            launch_transfer_left<T>(site(h, s), h->chiL(s), h->chiR(s), h->envR + (size_t)s * cap,
+                                    h->vecs + 4 * n, h->envR + (size_t)(s + 1) * cap, h->st);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(h->small_host, h->envL + (size_t)n * cap, sizeof(double2), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipMemcpyAsync(h->small_host + 1, h->envR + (size_t)n * cap, sizeof(double2), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+        const double2 num = h->small_host[0], tr = h->small_host[1];
+        const double den = tr.x * tr.x + tr.y * tr.y;
+        *re = (num.x * tr.x + num.y * tr.y) / den;
+        *im = (num.y * tr.x - num.x * tr.y) / den;
+    }
+
+    static void init_product(mpo_handle* h, const unsigned char* bits) {
+        for (int b = 0; b < h->n - 1; ++b) h->dims[b] = 1;
+        std::vector<T> buf(8);
+        for (int s = 0; s < h->n; ++s) {
+            double v[8];
+            product_site(h->basis, bits ? bits[s] : 0, v);
+            for (int k = 0; k < 8; ++k) buf[k] = (T)v[k];
+            HIPCHK(hipMemcpyAsync(site(h, s), buf.data(), sizeof(T) * 8, hipMemcpyHostToDevice, h->st));
+            HIPCHK(hipStreamSynchronize(h->st));
+        }
+        h->centre = 0;
+    }
+
+    static size_t export_size(const mpo_handle* h) {
+        size_t bytes = (size_t)(4 + h->n - 1) * 8;
+        for (int s = 0; s < h->n; ++s) bytes += (size_t)h->chiL(s) * 4 * h->chiR(s) * 16;
+        return bytes;
+    }
+
+    static void do_export(mpo_handle* h, char* out) {
+        int64_t* hdr = (int64_t*)out;
+        hdr[0] = 0x4d504f31;
+        hdr[1] = h->n;
+        hdr[2] = h->basis;
+        hdr[3] = h->centre;
+        for (int b = 0; b < h->n - 1; ++b) hdr[4 + b] = h->dims[b];
+        double* dst = (double*)(out + (size_t)(4 + h->n - 1) * 8);
+        std::vector<C> tmp;
+        for (int s = 0; s < h->n; ++s) {
+            const int cl = h->chiL(s), cr = h->chiR(s);
+            tmp.resize((size_t)cl * 4 * cr);
+            HIPCHK(hipMemcpyAsync(tmp.data(), site(h, s), sizeof(C) * tmp.size(), hipMemcpyDeviceToHost, h->st));
+            HIPCHK(hipStreamSynchronize(h->st));
+            for (int a = 0; a < cl; ++a)
+                for (int I = 0; I < 4; ++I)
+                    for (int c = 0; c < cr; ++c) {
+                        const C v = tmp[(size_t)a + (size_t)cl * (I + 4 * c)];
+                        const size_t o = ((size_t)(a * 4 + I) * cr + c) * 2;
+                        dst[o] = (double)v.x;
+                        dst[o + 1] = (double)v.y;
+                    }
+            dst += (size_t)cl * 4 * cr * 2;
+        }
+    }
+
+    static void do_import(mpo_handle* h, const char* in) {
+        const int64_t* hdr = (const int64_t*)in;
+        for (int b = 0; b < h->n - 1; ++b) h->dims[b] = (int)hdr[4 + b];
+        const double* src = (const double*)(in + (size_t)(4 + h->n - 1) * 8);
+        std::vector<C> tmp;
+        for (int s = 0; s < h->n; ++s) {
+            const int cl = h->chiL(s), cr = h->chiR(s);
+            tmp.resize((size_t)cl * 4 * cr);
+            for (int a = 0; a < cl; ++a)
+                for (int I = 0; I < 4; ++I)
+                    for (int c = 0; c < cr; ++c) {
+                        const size_t o = ((size_t)(a * 4 + I) * cr + c) * 2;
+                        C v;
+                        v.x = (T)src[o];
+                        v.y = (T)src[o + 1];
+                        tmp[(size_t)a + (size_t)cl * (I + 4 * c)] = v;
+                    }
+            HIPCHK(hipMemcpyAsync(site(h, s), tmp.data(), sizeof(C) * tmp.size(), hipMemcpyHostToDevice, h->st));
+            HIPCHK(hipStreamSynchronize(h->st));
+            src += (size_t)cl * 4 * cr * 2;
+        }
+        // any gauge: a left-to-right sweep of exact QR-type moves canonicalises
+        h->centre = 0;
+        move_centre(h, h->n - 1);
+    }
+};
+
+template <typename F>
+mpo_status guarded(mpo_handle* h, F&& f) {
+    try {
+        f();
+        return MPO_OK;
+    } catch (const HipError& e) {
+        return fail(MPO_ERR_HIP, "HIP error %s in %s", hipGetErrorString(e.e), e.what);
+    } catch (const NumericError& e) {
+        if (h) h->poisoned = true;
+        return fail(MPO_ERR_NUMERIC, "%s", e.what);
+    } catch (const NoConvError& e) {
+        if (h) h->poisoned = true;
+        return fail(MPO_ERR_NOCONV, "%s", e.what);
+    }
+}
+
+#define DISPATCH(h, ...)                                                 \
+    do {                                                                 \
+        if ((h)->prec == MPO_FP64) { using E = Engine<double>; __VA_ARGS__; } \
+        else { using E = Engine<float>; __VA_ARGS__; }                   \
+    } while (0)
+
+mpo_status check_live(mpo_handle* h) {
+    if (!h) return fail(MPO_ERR_ARG, "null handle");
+    if (h->poisoned) return fail(MPO_ERR_STATE, "handle poisoned by an earlier numeric fault");
+    return MPO_OK;
+}
+
+bool finite_all(const double* v, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+extern "C" {
+
+const char* mpo_last_error(void) { return g_err.c_str(); }
+
+mpo_status mpo_workspace_bytes(int n, int chi_cap, mpo_precision prec, size_t* bytes) {
+    if (!bytes) return fail(MPO_ERR_ARG, "bytes is NULL");
+    if (n < 2 || (n & 1)) return fail(MPO_ERR_ARG, "n must be even and >= 2 (got %d)", n);
+    if (chi_cap < 1 || chi_cap > 1024) return fail(MPO_ERR_ARG, "chi_cap must be in [1, 1024] (got %d)", chi_cap);
+    if (prec != MPO_FP64 && prec != MPO_FP32_MFMA) return fail(MPO_ERR_ARG, "unknown precision %d", (int)prec);
+    *bytes = make_layout(n, chi_cap, prec).total;
+    return MPO_OK;
+}
+
+mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis, void* dev_arena,
+                      size_t arena_bytes, void* hip_stream, mpo_handle** out) {
+    if (!out) return fail(MPO_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    mpo_status st = mpo_workspace_bytes(n, chi_cap, prec, &need);
+    if (st != MPO_OK) return st;
+    if (basis != MPO_BASIS_PAULI && basis != MPO_BASIS_COMPUTATIONAL)
+        return fail(MPO_ERR_ARG, "unknown basis %d", (int)basis);
+    if (!dev_arena) return fail(MPO_ERR_ARG, "dev_arena is NULL");
+    if (((uintptr_t)dev_arena) & 255) return fail(MPO_ERR_ARG, "dev_arena must be 256-byte aligned");
+    if (arena_bytes < need)
+        return fail(MPO_ERR_ARENA, "arena has %zu bytes, %zu needed", arena_bytes, need);
+    mpo_handle* h = new mpo_handle();
+    h->n = n;
+    h->chi_cap = chi_cap;
+    h->prec = prec;
+    h->basis = basis;
+    h->st = (hipStream_t)hip_stream;
+    h->csz = prec == MPO_FP64 ? 16 : 8;
+    const Layout L = make_layout(n, chi_cap, prec);
+    char* p = (char*)dev_arena;
+    h->slot.resize(L.slots);
+    for (size_t k = 0; k < L.slots; ++k) { h->slot[k] = p; p += L.slot_bytes; }
+    h->site_slot.resize(n);
+    for (int s = 0; s < n; ++s) h->site_slot[s] = s;
+    h->spare = {n, n + 1};
+    h->X = p; p += L.x_bytes;
+    h->X2 = p; p += L.x_bytes;
+    h->R = p; p += L.r_bytes;
+    h->jw.gram_partials = p; p += L.partial_bytes;
+    h->jw.w = p; p += L.w_bytes;
+    h->jw.skip = (int*)p; p += L.skip_bytes;
+    h->jw.nrm2 = (double*)p; p += L.vecN_bytes;
+    h->jw.sig2 = (double*)p; p += L.vecN_bytes;
+    h->jw.colmap = (int*)p; p += L.vecN_bytes;
+    h->jw.info = (DevInfo*)p; p += L.info_bytes;
+    h->jw.max_pairs = L.max_pairs;
+    h->jw.splits = kSplitsMax;
+    h->jw.prof = &h->prof;
+    h->envL = (double2*)p; p += L.env_bytes;
+    h->envR = (double2*)p; p += L.env_bytes;
+    h->tscr = (double2*)p; p += L.tscr_bytes;
+    h->tmp = (double2*)p; p += align256((size_t)chi_cap * sizeof(double2));
+    h->vecs = (double2*)p; p += L.vec_bytes;
+    h->dots = (double2*)p; p += L.dot_bytes;
+    h->Mdev = p; p += L.super_bytes;
+    h->dims.assign(n - 1, 1);
+    h->last_S.assign(n - 1, 0.0);
+    h->last_lam.assign(n - 1, std::vector<double>());
+    if (hipHostMalloc((void**)&h->info_host, sizeof(DevInfo)) != hipSuccess ||
+        hipHostMalloc(&h->super_stage, (size_t)kMaxSuper * 256 * h->csz) != hipSuccess ||
+        hipHostMalloc((void**)&h->small_host, sizeof(double2) * (n + 4)) != hipSuccess ||
+        hipHostMalloc((void**)&h->sig_host, sizeof(double) * 4 * chi_cap) != hipSuccess) {
+        mpo_destroy(h);
+        return fail(MPO_ERR_HIP, "pinned host allocation failed");
+    }
+    h->jw.info_host = h->info_host;
+    st = guarded(h, [&] { DISPATCH(h, E::init_product(h, nullptr)); });
+    if (st != MPO_OK) { mpo_destroy(h); return st; }
+    *out = h;
+    return MPO_OK;
+}
+
+void mpo_destroy(mpo_handle* h) {
+    if (!h) return;
+    if (h->st) (void)hipStreamSynchronize(h->st); else (void)hipDeviceSynchronize();
+    if (h->info_host) (void)hipHostFree(h->info_host);
+    if (h->super_stage) (void)hipHostFree(h->super_stage);
+    if (h->small_host) (void)hipHostFree(h->small_host);
+    if (h->sig_host) (void)hipHostFree(h->sig_host);
+    delete h;
+}
+
+mpo_status mpo_init_product(mpo_handle* h, const unsigned char* bits) {
+    if (!h) return fail(MPO_ERR_ARG, "null handle");
+    if (bits)
+        for (int s = 0; s < h->n; ++s)
+            if (bits[s] > 1) return fail(MPO_ERR_ARG, "bits[%d] = %d is not 0/1", s, bits[s]);
+    mpo_status st = guarded(h, [&] { DISPATCH(h, E::init_product(h, bits)); });
+    if (st == MPO_OK) h->poisoned = false;
+    return st;
+}
+
+mpo_status mpo_apply_2q_channel(mpo_handle* h, int site, const double* superop, int chi_max,
+                                double cutoff, mpo_trunc_info* info) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    if (site < 0 || site > h->n - 2) return fail(MPO_ERR_ARG, "site %d out of [0, %d]", site, h->n - 2);
+    if (!superop) return fail(MPO_ERR_ARG, "superop is NULL");
+    if (chi_max < 1 || chi_max > h->chi_cap)
+        return fail(MPO_ERR_ARG, "chi_max %d out of [1, %d]", chi_max, h->chi_cap);
+    if (!(cutoff >= 0.0) || !std::isfinite(cutoff)) return fail(MPO_ERR_ARG, "cutoff must be finite and >= 0");
+    if (!finite_all(superop, 512)) {
+        h->poisoned = true;
+        return fail(MPO_ERR_NUMERIC, "non-finite superoperator entry");
+    }
+    return guarded(h, [&] {
+        DISPATCH(h, {
+            E::upload_super(h, superop, 1);
+            mpo_trunc_info r = E::apply(h, site, (const typename E::C*)h->Mdev, chi_max, cutoff);
+            if (info) *info = r;
+        });
+    });
+}
+
+mpo_status mpo_canonicalize(mpo_handle* h, int center) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    if (center < 0 || center >= h->n) return fail(MPO_ERR_ARG, "center %d out of range", center);
+    return guarded(h, [&] { DISPATCH(h, E::move_centre(h, center)); });
+}
+
+mpo_status mpo_bond_entropy(mpo_handle* h, int bond, double* S) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    if (!S) return fail(MPO_ERR_ARG, "S is NULL");
+    if (bond < -1 || bond > h->n - 2) return fail(MPO_ERR_ARG, "bond %d out of range", bond);
+    return guarded(h, [&] {
+        DISPATCH(h, {
+            if (bond < 0) {
+                E::sweep_all(h, false);
+                for (int b = 0; b < h->n - 1; ++b) S[b] = h->last_S[b];
+            } else {
+                E::move_centre(h, bond + 1);
+                E::move_left(h, bond + 1, false);
+                *S = h->last_S[bond];
+            }
+        });
+    });
+}
+
+mpo_status mpo_singular_values(mpo_handle* h, int bond, double* lam, int cap, int* count) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    if (bond < 0 || bond > h->n - 2) return fail(MPO_ERR_ARG, "bond %d out of range", bond);
+    if (!count || (cap > 0 && !lam)) return fail(MPO_ERR_ARG, "null output");
+    return guarded(h, [&] {
+        DISPATCH(h, {
+            E::move_centre(h, bond + 1);
+            E::move_left(h, bond + 1, true);
+            const std::vector<double>& v = h->last_lam[bond];
+            *count = (int)v.size();
+            for (int i = 0; i < cap && i < (int)v.size(); ++i) lam[i] = v[i];
+        });
+    });
+}
+
+mpo_status mpo_expect_pauli(mpo_handle* h, const unsigned char* pauli, double* re, double* im) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    if (!pauli || !re || !im) return fail(MPO_ERR_ARG, "null argument");
+    for (int s = 0; s < h->n; ++s)
+        if (pauli[s] > 3) return fail(MPO_ERR_ARG, "pauli[%d] = %d not in 0..3", s, pauli[s]);
+    return guarded(h, [&] { DISPATCH(h, E::pauli(h, pauli, re, im)); });
+}
+
+mpo_status mpo_trace(mpo_handle* h, double* re, double* im) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    if (!re || !im) return fail(MPO_ERR_ARG, "null argument");
+    return guarded(h, [&] { DISPATCH(h, E::observables(h, nullptr, re, im)); });
+}
+
+mpo_status mpo_expect_z_all(mpo_handle* h, double* z, double* trace) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    if (!z) return fail(MPO_ERR_ARG, "z is NULL");
+    return guarded(h, [&] { DISPATCH(h, E::observables(h, z, trace, nullptr)); });
+}
+
+mpo_status mpo_bond_dims(mpo_handle* h, int* dims, int* center) {
+    if (!h) return fail(MPO_ERR_ARG, "null handle");
+    if (dims)
+        for (int b = 0; b < h->n - 1; ++b) dims[b] = h->dims[b];
+    if (center) *center = h->centre;
+    return MPO_OK;
+}
+
+mpo_status run_brickwork(mpo_handle* h, int depth, const double* superops, int n_gates, int chi_max,
+                         double cutoff, int record_mask, double* S_out, double* Z_out,
+                         double* trace_out, double* discarded_out) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    const int n = h->n;
+    if (depth < 0) return fail(MPO_ERR_ARG, "depth must be >= 0");
+    const long expect = (long)((depth + 1) / 2) * (n / 2) + (long)(depth / 2) * (n / 2 - 1);
+    if (n_gates != expect)
+        return fail(MPO_ERR_ARG, "n_gates = %d but a depth-%d brickwork on %d qubits has %ld", n_gates, depth, n, expect);
+    if (n_gates > 0 && !superops) return fail(MPO_ERR_ARG, "superops is NULL");
+    if (chi_max < 1 || chi_max > h->chi_cap) return fail(MPO_ERR_ARG, "chi_max %d out of [1, %d]", chi_max, h->chi_cap);
+    if (!(cutoff >= 0.0) || !std::isfinite(cutoff)) return fail(MPO_ERR_ARG, "cutoff must be finite and >= 0");
+    if (record_mask & ~3) return fail(MPO_ERR_ARG, "record_mask has unknown bits");
+    if (!finite_all(superops, (size_t)n_gates * 512)) {
+        h->poisoned = true;
+        return fail(MPO_ERR_NUMERIC, "non-finite superoperator entry");
+    }
+    return guarded(h, [&] {
+        DISPATCH(h, {
+            using C = typename E::C;
+            int g = 0, resident0 = 0, resident = 0;
+            for (int t = 0; t < depth; ++t) {
+                const int first = (t % 2 == 0) ? 0 : 1;
+                for (int s = first; s + 1 < n; s += 2) {
+                    if (g >= resident0 + resident) {
+                        resident0 = g;
+                        resident = std::min(kMaxSuper, n_gates - g);
+                        HIPCHK(hipStreamSynchronize(h->st));
+                        E::upload_super(h, superops + (size_t)g * 512, resident);
+                    }
+                    const C* Mg = (const C*)h->Mdev + (size_t)(g - resident0) * 256;
+                    mpo_trunc_info inf = E::apply(h, s, Mg, chi_max, cutoff);
+                    if (discarded_out) discarded_out[g] = inf.discarded_weight;
+                    ++g;
+                }
+                const bool rec_all = record_mask & 1;
+                const bool rec_last = (record_mask & 2) && t == depth - 1;
+                if (rec_all || rec_last) {
+                    const int row = rec_all ? t : 0;
+                    E::sweep_all(h, false);
+                    if (S_out)
+                        for (int b = 0; b < n - 1; ++b) S_out[(size_t)row * (n - 1) + b] = h->last_S[b];
+                    double tr = 0.0;
+                    E::observables(h, Z_out ? Z_out + (size_t)row * n : nullptr, &tr, nullptr);
+                    if (trace_out) trace_out[row] = tr;
+                }
+            }
+        });
+    });
+}
+
+mpo_status mpo_profile_enable(mpo_handle* h, int on) {
+    if (!h) return fail(MPO_ERR_ARG, "null handle");
+    h->prof.reset();
+    h->prof.on = on != 0;
+    h->jw.n_splits = h->jw.n_sweeps = h->jw.n_rounds = h->jw.n_rotations = 0;
+    return MPO_OK;
+}
+
+mpo_status mpo_profile_read(mpo_handle* h, mpo_kernel_stat* out, int cap, int* count,
+                            long long* svd_counters) {
+    if (!h || !count) return fail(MPO_ERR_ARG, "null argument");
+    if (cap > 0 && !out) return fail(MPO_ERR_ARG, "out is NULL");
+    h->prof.collect();
+    *count = K_COUNT;
+    for (int k = 0; k < K_COUNT && k < cap; ++k) {
+        std::snprintf(out[k].name, sizeof(out[k].name), "%s", kernel_name(k));
+        out[k].launches = h->prof.launches[k];
+        out[k].ms = h->prof.ms[k];
+        out[k].flops = h->prof.flops[k];
+        out[k].bytes = h->prof.bytes[k];
+    }
+    if (svd_counters) {
+        svd_counters[0] = h->jw.n_splits;
+        svd_counters[1] = h->jw.n_sweeps;
+        svd_counters[2] = h->jw.n_rounds;
+        svd_counters[3] = h->jw.n_rotations;
+    }
+    return MPO_OK;
+}
+
+mpo_status mpo_export(mpo_handle* h, void* host_buf, size_t cap, size_t* used) {
+    if (!h || !used) return fail(MPO_ERR_ARG, "null argument");
+    mpo_status st = MPO_OK;
+    DISPATCH(h, { *used = E::export_size(h); });
+    if (!host_buf) return MPO_OK;
+    if (cap < *used) return fail(MPO_ERR_ARG, "buffer has %zu bytes, %zu needed", cap, *used);
+    st = guarded(h, [&] { DISPATCH(h, E::do_export(h, (char*)host_buf)); });
+    return st;
+}
+
+mpo_status mpo_import(mpo_handle* h, const void* host_buf, size_t len) {
+    if (!h || !host_buf) return fail(MPO_ERR_ARG, "null argument");
+    const int n = h->n;
+    const size_t hdr_bytes = (size_t)(4 + n - 1) * 8;
+    if (len < hdr_bytes) return fail(MPO_ERR_ARG, "snapshot too short");
+    const int64_t* hdr = (const int64_t*)host_buf;
+    if (hdr[0] != 0x4d504f31) return fail(MPO_ERR_ARG, "bad snapshot magic");
+    if (hdr[1] != n) return fail(MPO_ERR_ARG, "snapshot has n = %lld, handle has %d", (long long)hdr[1], n);
+    if (hdr[2] != h->basis) return fail(MPO_ERR_ARG, "snapshot basis differs from the handle's");
+    size_t need = hdr_bytes;
+    for (int b = 0; b < n - 1; ++b)
+        if (hdr[4 + b] < 1 || hdr[4 + b] > h->chi_cap)
+            return fail(MPO_ERR_ARG, "bond %d dimension %lld out of [1, %d]", b, (long long)hdr[4 + b], h->chi_cap);
+    for (int s = 0; s < n; ++s) {
+        const size_t cl = s == 0 ? 1 : hdr[4 + s - 1], cr = s == n - 1 ? 1 : hdr[4 + s];
+        need += cl * 4 * cr * 16;
+    }
+    if (len < need) return fail(MPO_ERR_ARG, "snapshot has %zu bytes, %zu needed", len, need);
+    if (!finite_all((const double*)((const char*)host_buf + hdr_bytes), (need - hdr_bytes) / 8))
+        return fail(MPO_ERR_ARG, "snapshot holds non-finite values");
+    mpo_status st = guarded(h, [&] { DISPATCH(h, E::do_import(h, (const char*)host_buf)); });
+    if (st == MPO_OK) h->poisoned = false;
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Shared device/host definitions for libmpo (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "profiler.h"
+
+namespace mpo {
+
+// Interleaved complex value of the working precision (double2 / float2).
+template <typename T> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+template <typename T> using C2 = typename cvec<T>::type;
+
+// 4-wide accumulator of one 16x16x4 MFMA (one lane's share of a 16x16 tile).
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct accv;
+template <> struct accv<double> { using type = d4; };
+template <> struct accv<float> { using type = f4; };
+template <typename T> using A4 = typename accv<T>::type;
+
+// D(16x16) += A(16x4) * B(4x16).  Operand layout (wave64): lane l supplies
+// A[l%16][l/16] and B[l/16][l%16].  Result element r of lane l is
+// D[acc_row<T>(l, r)][l%16]: rows 4*(l/16)+r for f32, but interleaved rows
+// (l/16)+4*r for f64 (both checked on gfx950).
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+template <typename T> __device__ __forceinline__ C2<T> cmake(T re, T im) {
+    C2<T> v; v.x = re; v.y = im; return v;
+}
+template <typename T> __device__ __forceinline__ C2<T> czero() { return cmake<T>(T(0), T(0)); }
+template <typename T> __device__ __forceinline__ C2<T> cconj(C2<T> a) { return cmake<T>(a.x, -a.y); }
+template <typename T> __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+    return cmake<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T> __device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) {
+    return cmake<T>(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+template <typename T> __device__ __forceinline__ C2<T> from_d2(double2 v) {
+    return cmake<T>(T(v.x), T(v.y));
+}
+
+// Device-side per-split result (one truncated SVD).
+struct DevInfo {
+    int kept;
+    int numeric_error;     // non-finite values met
+    double discarded;
+    double total;
+    double entropy;
+    unsigned long long offmax_bits;  // max relative off-diagonal of the sweep (bits of a double >= 0)
+    int rotations;         // pairs rotated in the sweep
+    int pad;
+};
+
+}  // namespace mpo
+
+// ----------------------------------------------------------------- launchers
+// Column-major storage everywhere.  op = 0: as stored; op = 1: conjugate transpose.
+namespace mpo {
+template <typename T>
+void launch_cgemm(int opa, int opb, int M, int N, int K, const C2<T>* A, int lda,
+                  const C2<T>* B, int ldb, C2<T>* C, int ldc, hipStream_t st);
+
+// X[(a + chiL*I) + m*(J + 4c)] = sum M[4I+J][4I'+J'] * theta[(I',a),(J',c)],
+// theta = L(As) * R(Bs); also written to X2 when non-null.
+template <typename T>
+void launch_theta_channel(int chiL, int chiM, int chiR, const C2<T>* As, const C2<T>* Bs,
+                          const C2<T>* Mdev, C2<T>* X, C2<T>* X2, hipStream_t st);
+
+struct JacobiWork {
+    void* gram_partials;   // P_max * splits * 64*64 complex (T)
+    void* w;               // P_max * 64*64 complex (T)
+    int* skip;             // P_max
+    double* nrm2;          // N
+    int* colmap;           // N (padded)
+    double* sig2;          // N, sorted descending
+    DevInfo* info;
+    DevInfo* info_host;    // pinned
+    int max_pairs;
+    int splits;
+    Profiler* prof;        // may be off
+    long long n_splits, n_sweeps, n_rounds, n_rotations;   // running counters
+};
+
+// One-sided block Jacobi on the columns of X (m x N, ld = m).  On return
+// work.colmap[0..N) lists columns by decreasing norm and work.sig2 holds the
+// sorted squared norms.  Returns the number of sweeps, or -1 if the sweep
+// limit was reached, -2 on a HIP error.
+template <typename T>
+int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps,
+                         JacobiWork& w, hipStream_t st);
+
+// Columns whose squared norm is at most this fraction of ||X||_F^2 are at the
+// rounding floor of the working precision: the sweep never rotates them and
+// the truncation never keeps them.
+template <typename T> constexpr double jacobi_zero_rel2() { return sizeof(T) == 8 ? 1e-30 : 1e-14; }
+
+// Truncation + entropy from the sorted squared norms (single work-group).
+void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,
+                     DevInfo* info, hipStream_t st);
+
+// dst[i + ldd*b] = X[i + m*colmap[b]] / sqrt(sig2[b]) for b < k  (left factor)
+template <typename T>
+void launch_gather_cols(const C2<T>* X, int m, const int* colmap, const double* sig2, int k,
+                        C2<T>* dst, int ldd, hipStream_t st);
+// dst[b + k*i] = conj(X[i + m*colmap[b]]) / sqrt(sig2[b]) for b < k  (right factor, rows)
+template <typename T>
+void launch_gather_rows_conj(const C2<T>* X, int m, const int* colmap, const double* sig2,
+                             int k, C2<T>* dst, hipStream_t st);
+// Y[j + cols*i] = conj(A[i + rows*j])  (Y is cols x rows)
+template <typename T>
+void launch_conj_transpose(const C2<T>* A, int rows, int cols, C2<T>* Y, hipStream_t st);
+template <typename T>
+void launch_copy(const C2<T>* src, C2<T>* dst, size_t count, hipStream_t st);
+
+// Transfer contraction (Sec. III.D): env_out[b] = sum_{a,I} env_in[a] v[I] A[a,I,b]
+template <typename T>
+void launch_transfer_left(const C2<T>* A, int chiL, int chiR, const double2* env_in,
+                          const double2* v, double2* env_out, hipStream_t st);
+// env_out[a] = sum_{I,b} A[a,I,b] v[I] env_in[b]; partial: scratch >= chiL*chunks
+template <typename T>
+void launch_transfer_right(const C2<T>* A, int chiL, int chiR, const double2* env_in,
+                           const double2* v, double2* env_out, double2* scratch, hipStream_t st);
+// out[slot] = sum_a x[a] * y[a]
+void launch_dot(const double2* x, const double2* y, int len, double2* out, hipStream_t st);
+}  // namespace mpo

@@ -1,0 +1,655 @@
+// Blocked one-sided Jacobi SVD for the truncated split (App. A: SVD of the
+// two-site block, keep the largest singular values).
+//
+// The columns of X (m x N, column-major) are orthogonalised by right-
+// multiplication with unitary matrices: blocks of 32 columns are paired in a
+// round-robin tournament; for a pair the 64x64 Gram matrix is formed on MFMA,
+// diagonalised by a cyclic two-sided Jacobi sweep in FP64 inside one
+// work-group, and the resulting 64x64 unitary is applied to the pair's
+// columns on MFMA.  At convergence X V = U Sigma with orthogonal columns, so
+// the left singular vectors are the normalised columns and the singular
+// values their norms.  Columns are re-ordered by decreasing norm before each
+// sweep through an index map (no data movement).
+#include "common.h"
+#include <cstring>
+
+namespace mpo {
+
+constexpr int JB = 32;         // columns per block
+constexpr int JP = 2 * JB;     // columns per pair
+
+// Round-robin tournament (circle method) over nb players (nb even):
+// pair 0 of round r is (r, nb-1); pair i > 0 is (r+i, r-i) mod (nb-1).
+__host__ __device__ __forceinline__ void pair_of(int round, int i, int nb, int& p, int& q) {
+    const int M = nb - 1;
+    if (i == 0) { p = round; q = M; }
+    else { p = (round + i) % M; q = (round - i + M) % M; }
+}
+
+// ------------------------------------------------------------- column norms
+template <typename T>
+__global__ __launch_bounds__(256) void k_colnorm2(const C2<T>* __restrict__ X, int m, int N,
+                                                  double* __restrict__ out) {
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (col >= N) return;
+    const C2<T>* x = X + (size_t)col * m;
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) {
+        const double2 v = to_d2(x[i]);
+        s += v.x * v.x + v.y * v.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) out[col] = s;
+}
+
+// ------------------------------------------- sort by decreasing norm (bitonic)
+// Ties keep ascending column index, so the order is deterministic.
+__global__ __launch_bounds__(1024) void k_sort_desc(const double* __restrict__ nrm2, int N,
+                                                    int* __restrict__ colmap,
+                                                    double* __restrict__ sig2,
+                                                    double* __restrict__ fro2) {
+    __shared__ double key[4096];
+    __shared__ int idx[4096];
+    __shared__ double red[1024];
+    const int t = threadIdx.x;
+    int P2 = 1;
+    while (P2 < N) P2 <<= 1;
+    double part = 0.0;
+    for (int e = t; e < P2; e += 1024) {
+        const double v = e < N ? nrm2[e] : -1.0;
+        key[e] = v;
+        idx[e] = e;
+        if (e < N) part += v;
+    }
+    red[t] = part;
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int e = t; e < P2; e += 1024) {
+                const int f = e ^ j;
+                if (f > e) {
+                    const double ke = key[e], kf = key[f];
+                    const int ie = idx[e], jf = idx[f];
+                    const bool e_less = (ke < kf) || (ke == kf && ie > jf);
+                    const bool f_less = (kf < ke) || (kf == ke && jf > ie);
+                    const bool swap = ((e & k) == 0) ? e_less : f_less;
+                    if (swap) { key[e] = kf; key[f] = ke; idx[e] = jf; idx[f] = ie; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = t; e < N; e += 1024) { colmap[e] = idx[e]; sig2[e] = key[e]; }
+    for (int o = 512; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    if (t == 0 && fro2) *fro2 = red[0];
+}
+
+// ------------------------------------------------------------- pair Gram
+// partials[(pair*splits + split)*4096 + i + 64*j] = sum_rows conj(x_i) x_j over
+// this split's row range, for the 64 columns of the pair.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, int m, int N,
+                                                   const int* __restrict__ colmap, int nb,
+                                                   int round, int splits, int chunk,
+                                                   C2<T>* __restrict__ partials) {
+    __shared__ C2<T> Xs[16][JP + 1];
+    __shared__ int cols[JP];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int pair = blockIdx.x, split = blockIdx.y;
+    int p, q;
+    pair_of(round, pair, nb, p, q);
+    if (t < JP) {
+        const int lj = (t < JB) ? p * JB + t : q * JB + (t - JB);
+        cols[t] = (lj < N) ? colmap[lj] : -1;
+    }
+    __syncthreads();
+    const int r0 = split * chunk;
+    const int r1 = min(m, r0 + chunk);
+    A4<T> accR[2][2], accI[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
+    for (int k0 = r0; k0 < r1; k0 += 16) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = t + 256 * r;
+            const int row = e & 15, col = e >> 4;
+            const int c = cols[col];
+            C2<T> v = czero<T>();
+            if (c >= 0 && k0 + row < r1) v = X[(size_t)(k0 + row) + (size_t)m * c];
+            Xs[row][col] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            C2<T> a[2], b[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                a[s] = Xs[kk + (lane >> 4)][wm * 32 + s * 16 + (lane & 15)];
+                b[s] = Xs[kk + (lane >> 4)][wn * 32 + s * 16 + (lane & 15)];
+            }
+            // A[i][k] = conj(X[k][i]): (ar - i ai)(br + i bi)
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    accR[bi][bj] = mfma16(a[bi].x, b[bj].x, accR[bi][bj]);
+                    accR[bi][bj] = mfma16(a[bi].y, b[bj].y, accR[bi][bj]);
+                    accI[bi][bj] = mfma16(a[bi].x, b[bj].y, accI[bi][bj]);
+                    accI[bi][bj] = mfma16(-a[bi].y, b[bj].x, accI[bi][bj]);
+                }
+        }
+        __syncthreads();
+    }
+    C2<T>* out = partials + (size_t)(pair * splits + split) * (JP * JP);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = wm * 32 + bi * 16 + acc_row<T>(lane, r);
+                const int j = wn * 32 + bj * 16 + (lane & 15);
+                out[i + JP * j] = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
+            }
+}
+
+// ------------------------------------------------- 64x64 Hermitian eigen (FP64)
+// Sums the Gram partials, measures the largest relative off-diagonal element
+// |g_ij| / sqrt(g_ii g_jj), and if it exceeds tol runs up to inner_max cyclic
+// Jacobi sweeps (parallel ordering, 32 disjoint rotations per step), giving a
+// unitary W with W^H G W close to diagonal.  Columns whose squared norm is at
+// most zthr2 * ||X||_F^2 are treated as zero and never rotated.
+__device__ __forceinline__ double2 dmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ double block_off(const double2 (*G)[JP + 1], double zthr, double* red) {
+    const int t = threadIdx.x;
+    double mx = 0.0;
+    for (int e = t; e < JP * JP; e += 256) {
+        const int i = e & (JP - 1), j = e >> 6;
+        if (i < j) {
+            const double a = G[i][i].x, d = G[j][j].x;
+            if (a > zthr && d > zthr) {
+                const double2 g = G[i][j];
+                const double r = sqrt(g.x * g.x + g.y * g.y) / sqrt(a * d);
+                mx = fmax(mx, r);
+            }
+        }
+    }
+    red[t] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[t] = fmax(red[t], red[t + o]);
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_eig(const C2<T>* __restrict__ partials, int splits,
+                                                  double tol, double zrel2,
+                                                  const double* __restrict__ fro2, int inner_max,
+                                                  C2<T>* __restrict__ Wout, int* __restrict__ skip,
+                                                  DevInfo* info) {
+    __shared__ double2 G[JP][JP + 1];
+    __shared__ double2 W[JP][JP + 1];
+    __shared__ double red[256];
+    __shared__ double rc[JB], rs[JB];
+    __shared__ double2 rph[JB];
+    __shared__ int ri[JB], rj[JB], ract[JB];
+    const int t = threadIdx.x, pair = blockIdx.x;
+    for (int e = t; e < JP * JP; e += 256) {
+        const int i = e & (JP - 1), j = e >> 6;
+        double2 s = make_double2(0.0, 0.0);
+        for (int sp = 0; sp < splits; ++sp) {
+            const double2 v = to_d2(partials[(size_t)(pair * splits + sp) * (JP * JP) + i + JP * j]);
+            s.x += v.x;
+            s.y += v.y;
+        }
+        G[i][j] = s;
+    }
+    __syncthreads();
+    // exact Hermitian symmetry and real diagonal
+    for (int e = t; e < JP * JP; e += 256) {
+        const int i = e & (JP - 1), j = e >> 6;
+        if (i < j) {
+            const double2 a = G[i][j], b = G[j][i];
+            const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+            G[i][j] = h;
+            G[j][i] = make_double2(h.x, -h.y);
+        } else if (i == j) {
+            G[i][i].y = 0.0;
+        }
+    }
+    __syncthreads();
+    const double zthr = zrel2 * (*fro2);
+    const double off0 = block_off(G, zthr, red);
+    if (off0 <= tol) {
+        if (t == 0) skip[pair] = 1;
+        return;
+    }
+    for (int e = t; e < JP * JP; e += 256) {
+        const int i = e & (JP - 1), j = e >> 6;
+        W[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < inner_max; ++sweep) {
+        for (int step = 0; step < JP - 1; ++step) {
+            if (t < JB) {
+                int i, j;
+                pair_of(step, t, JP, i, j);
+                const double a = G[i][i].x, d = G[j][j].x;
+                const double2 g = G[i][j];
+                const double ag = sqrt(g.x * g.x + g.y * g.y);
+                int act = (a > zthr && d > zthr && ag > tol * sqrt(a * d)) ? 1 : 0;
+                double c = 1.0, s = 0.0;
+                double2 ph = make_double2(1.0, 0.0);
+                if (act) {
+                    ph = make_double2(g.x / ag, g.y / ag);
+                    const double tau = (d - a) / (2.0 * ag);
+                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    s = tt * c;
+                }
+                ri[t] = i; rj[t] = j; ract[t] = act; rc[t] = c; rs[t] = s; rph[t] = ph;
+            }
+            __syncthreads();
+            // G <- G J and W <- W J (columns i, j)
+            for (int e = t; e < JB * JP; e += 256) {
+                const int pr = e >> 6, row = e & (JP - 1);
+                if (!ract[pr]) continue;
+                const int i = ri[pr], j = rj[pr];
+                const double c = rc[pr], s = rs[pr];
+                const double2 phc = make_double2(rph[pr].x, -rph[pr].y);
+                double2 gi = G[row][i], gj = G[row][j];
+                double2 pg = dmul(phc, gj);
+                G[row][i] = make_double2(c * gi.x - s * pg.x, c * gi.y - s * pg.y);
+                G[row][j] = make_double2(s * gi.x + c * pg.x, s * gi.y + c * pg.y);
+                gi = W[row][i]; gj = W[row][j];
+                pg = dmul(phc, gj);
+                W[row][i] = make_double2(c * gi.x - s * pg.x, c * gi.y - s * pg.y);
+                W[row][j] = make_double2(s * gi.x + c * pg.x, s * gi.y + c * pg.y);
+            }
+            __syncthreads();
+            // G <- J^H G (rows i, j)
+            for (int e = t; e < JB * JP; e += 256) {
+                const int pr = e >> 6, col = e & (JP - 1);
+                if (!ract[pr]) continue;
+                const int i = ri[pr], j = rj[pr];
+                const double c = rc[pr], s = rs[pr];
+                const double2 ph = rph[pr];
+                const double2 gi = G[i][col], gj = G[j][col];
+                const double2 pg = dmul(ph, gj);
+                G[i][col] = make_double2(c * gi.x - s * pg.x, c * gi.y - s * pg.y);
+                G[j][col] = make_double2(s * gi.x + c * pg.x, s * gi.y + c * pg.y);
+            }
+            __syncthreads();
+        }
+        if (sweep + 1 < inner_max && block_off(G, zthr, red) <= tol) break;
+    }
+    C2<T>* wo = Wout + (size_t)pair * (JP * JP);
+    for (int e = t; e < JP * JP; e += 256) {
+        const int i = e & (JP - 1), j = e >> 6;
+        wo[i + JP * j] = from_d2<T>(W[i][j]);
+    }
+    if (t == 0) {
+        skip[pair] = 0;
+        atomicMax(&info->offmax_bits, (unsigned long long)__double_as_longlong(off0));
+        atomicAdd(&info->rotations, 1);
+    }
+}
+
+// ------------------------------------------------------------- pair update
+// [x_p x_q] <- [x_p x_q] W for one 64-row slab of the pair's columns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int m, int N,
+                                                     const int* __restrict__ colmap, int nb,
+                                                     int round, const C2<T>* __restrict__ Wm,
+                                                     const int* __restrict__ skip) {
+    const int pair = blockIdx.x;
+    if (skip[pair]) return;
+    __shared__ C2<T> Ws[JP][JP + 1];   // Ws[k][j] = W[k][j]
+    __shared__ C2<T> Xt[JP][JP + 1];   // Xt[col][row]
+    __shared__ int cols[JP];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    int p, q;
+    pair_of(round, pair, nb, p, q);
+    if (t < JP) {
+        const int lj = (t < JB) ? p * JB + t : q * JB + (t - JB);
+        cols[t] = (lj < N) ? colmap[lj] : -1;
+    }
+    const C2<T>* wsrc = Wm + (size_t)pair * (JP * JP);
+    for (int e = t; e < JP * JP; e += 256) Ws[e & (JP - 1)][e >> 6] = wsrc[e];
+    __syncthreads();
+    const int r0 = blockIdx.y * 64;
+    for (int e = t; e < JP * 64; e += 256) {
+        const int row = e & 63, col = e >> 6;
+        const int c = cols[col];
+        C2<T> v = czero<T>();
+        if (c >= 0 && r0 + row < m) v = X[(size_t)(r0 + row) + (size_t)m * c];
+        Xt[col][row] = v;
+    }
+    __syncthreads();
+    A4<T> accR[2][2], accI[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
+#pragma unroll 4
+    for (int kk = 0; kk < JP; kk += 4) {
+        C2<T> a[2], b[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            a[s] = Xt[kk + (lane >> 4)][wm * 32 + s * 16 + (lane & 15)];
+            b[s] = Ws[kk + (lane >> 4)][wn * 32 + s * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                accR[bi][bj] = mfma16(a[bi].x, b[bj].x, accR[bi][bj]);
+                accR[bi][bj] = mfma16(-a[bi].y, b[bj].y, accR[bi][bj]);
+                accI[bi][bj] = mfma16(a[bi].x, b[bj].y, accI[bi][bj]);
+                accI[bi][bj] = mfma16(a[bi].y, b[bj].x, accI[bi][bj]);
+            }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wm * 32 + bi * 16 + acc_row<T>(lane, r);
+                const int col = wn * 32 + bj * 16 + (lane & 15);
+                Xt[col][row] = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
+            }
+    __syncthreads();
+    for (int e = t; e < JP * 64; e += 256) {
+        const int row = e & 63, col = e >> 6;
+        const int c = cols[col];
+        if (c >= 0 && r0 + row < m) X[(size_t)(r0 + row) + (size_t)m * c] = Xt[col][row];
+    }
+}
+
+// ------------------------------------------------------- truncation/entropy
+// App. A truncation with a relative cutoff; entropy of Sec. III.C over the kept
+// values.  Single work-group, FP64.
+__global__ __launch_bounds__(256) void k_truncate(const double* __restrict__ sig2, int N,
+                                                  int chi_max, double cutoff, double floor_rel2,
+                                                  DevInfo* info) {
+    __shared__ double red[256];
+    __shared__ int cnt[256];
+    __shared__ double s_total, s_kept;
+    __shared__ int s_k;
+    const int t = threadIdx.x;
+    double part = 0.0;
+    for (int e = t; e < N; e += 256) part += sig2[e];
+    red[t] = part;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    if (t == 0) s_total = red[0];
+    __syncthreads();
+    const double total = s_total;
+    // values the sweep treated as zero are never kept
+    const double thr = fmax(cutoff * cutoff, floor_rel2) * total;
+    int c = 0;
+    for (int e = t; e < N; e += 256) c += (sig2[e] > thr) ? 1 : 0;
+    cnt[t] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) cnt[t] += cnt[t + o];
+        __syncthreads();
+    }
+    if (t == 0) {
+        int k = cnt[0];
+        if (k > chi_max) k = chi_max;
+        if (k > N) k = N;
+        if (k < 1) k = 1;
+        s_k = k;
+    }
+    __syncthreads();
+    const int k = s_k;
+    double kp = 0.0, dp = 0.0;
+    for (int e = t; e < N; e += 256) {
+        if (e < k) kp += sig2[e]; else dp += sig2[e];
+    }
+    red[t] = kp;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    if (t == 0) s_kept = red[0];
+    __syncthreads();
+    const double kept = s_kept;
+    __syncthreads();
+    red[t] = dp;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    const double disc = red[0];
+    __syncthreads();
+    double ent = 0.0;
+    if (kept > 0.0) {
+        for (int e = t; e < k; e += 256) {
+            const double w = sig2[e] / kept;
+            if (w > 0.0) ent -= w * log2(w);
+        }
+    }
+    red[t] = ent;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    if (t == 0) {
+        info->kept = k;
+        info->total = total;
+        info->discarded = disc;
+        info->entropy = red[0];
+        info->numeric_error = (isfinite(total) && isfinite(red[0])) ? 0 : 1;
+    }
+}
+
+// ------------------------------------------------------------------ gathers
+template <typename T>
+__global__ void k_gather_cols(const C2<T>* __restrict__ X, int m, const int* __restrict__ colmap,
+                              const double* __restrict__ sig2, int k, C2<T>* __restrict__ dst,
+                              int ldd) {
+    const int b = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= k || i >= m) return;
+    const double s2 = sig2[b];
+    C2<T> v;
+    if (s2 > 0.0) {
+        const double inv = 1.0 / sqrt(s2);
+        const double2 x = to_d2(X[(size_t)i + (size_t)m * colmap[b]]);
+        v = cmake<T>(T(x.x * inv), T(x.y * inv));
+    } else {
+        v = cmake<T>(T(i == b ? 1 : 0), T(0));
+    }
+    dst[(size_t)i + (size_t)ldd * b] = v;
+}
+
+template <typename T>
+__global__ void k_gather_rows_conj(const C2<T>* __restrict__ X, int m,
+                                   const int* __restrict__ colmap,
+                                   const double* __restrict__ sig2, int k,
+                                   C2<T>* __restrict__ dst) {
+    __shared__ C2<T> tile[32][33];
+    const int i0 = blockIdx.x * 32, b0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: ty 0..7
+    for (int r = ty; r < 32; r += 8) {
+        const int b = b0 + r, i = i0 + tx;
+        C2<T> v = czero<T>();
+        if (b < k && i < m) {
+            const double s2 = sig2[b];
+            if (s2 > 0.0) {
+                const double inv = 1.0 / sqrt(s2);
+                const double2 x = to_d2(X[(size_t)i + (size_t)m * colmap[b]]);
+                v = cmake<T>(T(x.x * inv), T(-x.y * inv));
+            } else {
+                v = cmake<T>(T(i == b ? 1 : 0), T(0));
+            }
+        }
+        tile[r][tx] = v;   // tile[b][i]
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = i0 + r, b = b0 + tx;
+        if (b < k && i < m) dst[(size_t)b + (size_t)k * i] = tile[tx][r];
+    }
+}
+
+template <typename T>
+__global__ void k_conj_transpose(const C2<T>* __restrict__ A, int rows, int cols,
+                                 C2<T>* __restrict__ Y) {
+    __shared__ C2<T> tile[32][33];
+    const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = r0 + tx, j = c0 + r;
+        if (i < rows && j < cols) tile[r][tx] = cconj<T>(A[(size_t)i + (size_t)rows * j]);
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int j = c0 + tx, i = r0 + r;
+        if (i < rows && j < cols) Y[(size_t)j + (size_t)cols * i] = tile[tx][r];
+    }
+}
+
+template <typename T>
+__global__ void k_copy(const C2<T>* __restrict__ s, C2<T>* __restrict__ d, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+
+// ------------------------------------------------------------------- host side
+template <typename T>
+int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, JacobiWork& w,
+                         hipStream_t st) {
+    int nb = (N + JB - 1) / JB;
+    if (nb < 2) nb = 2;
+    if (nb & 1) ++nb;
+    const int P = nb / 2;
+    if (P > w.max_pairs) return -3;
+    int splits = (512 + P - 1) / P;
+    if (splits > w.splits) splits = w.splits;
+    int chunk = (m + splits - 1) / splits;
+    chunk = (chunk + 15) / 16 * 16;
+    splits = (m + chunk - 1) / chunk;
+    if (splits < 1) splits = 1;
+    const double zrel2 = jacobi_zero_rel2<T>();
+    double* fro2 = &w.info->total;   // scratch slot reused for ||X||_F^2
+    const dim3 gnorm((N + 3) / 4);
+    Profiler& pf = *w.prof;
+    const double csz = 2.0 * sizeof(T);
+    const double pair_flops = 8.0 * m * JP * JP;       // one 64x64 complex product over m rows
+    const double pair_bytes = (double)m * JP * csz;
+    w.n_splits += 1;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        pf.begin(st);
+        hipLaunchKernelGGL((k_colnorm2<T>), gnorm, dim3(256), 0, st, X, m, N, w.nrm2);
+        hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, w.nrm2, N, w.colmap, w.sig2, fro2);
+        pf.end(st, K_NORMSORT, 8.0 * m * N, (double)m * N * csz);
+        (void)hipMemsetAsync(&w.info->offmax_bits, 0, sizeof(unsigned long long) + 2 * sizeof(int), st);
+        for (int r = 0; r < nb - 1; ++r) {
+            pf.begin(st);
+            hipLaunchKernelGGL((k_pair_gram<T>), dim3(P, splits), dim3(256), 0, st, X, m, N,
+                               w.colmap, nb, r, splits, chunk, (C2<T>*)w.gram_partials);
+            pf.end(st, K_GRAM, P * pair_flops, P * pair_bytes + (double)P * splits * JP * JP * csz);
+            pf.begin(st);
+            hipLaunchKernelGGL((k_pair_eig<T>), dim3(P), dim3(256), 0, st,
+                               (const C2<T>*)w.gram_partials, splits, tol, zrel2, fro2, 3,
+                               (C2<T>*)w.w, w.skip, w.info);
+            pf.end(st, K_EIG, 0.0, (double)P * splits * JP * JP * csz);
+            pf.begin(st);
+            hipLaunchKernelGGL((k_pair_update<T>), dim3(P, (m + 63) / 64), dim3(256), 0, st, X, m, N,
+                               w.colmap, nb, r, (const C2<T>*)w.w, w.skip);
+            pf.end(st, K_UPDATE, 0.0, 0.0);
+        }
+        w.n_rounds += nb - 1;
+        w.n_sweeps += 1;
+        if (hipMemcpyAsync(w.info_host, w.info, sizeof(DevInfo), hipMemcpyDeviceToHost, st) != hipSuccess)
+            return -2;
+        if (hipStreamSynchronize(st) != hipSuccess) return -2;
+        const unsigned long long bits = w.info_host->offmax_bits;
+        double off;
+        std::memcpy(&off, &bits, sizeof(off));
+        const int rot = w.info_host->rotations;
+        w.n_rotations += rot;
+        pf.add_work(K_UPDATE, rot * pair_flops, rot * 2.0 * pair_bytes);
+        if (rot == 0 || off <= tol) {
+            pf.begin(st);
+            hipLaunchKernelGGL((k_colnorm2<T>), gnorm, dim3(256), 0, st, X, m, N, w.nrm2);
+            hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, w.nrm2, N, w.colmap, w.sig2, fro2);
+            pf.end(st, K_NORMSORT, 8.0 * m * N, (double)m * N * csz);
+            return sweep + 1;
+        }
+    }
+    return -1;
+}
+
+void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,
+                     DevInfo* info, hipStream_t st) {
+    hipLaunchKernelGGL(k_truncate, dim3(1), dim3(256), 0, st, sig2, N, chi_max, cutoff, floor_rel2,
+                       info);
+}
+
+template <typename T>
+void launch_gather_cols(const C2<T>* X, int m, const int* colmap, const double* sig2, int k,
+                        C2<T>* dst, int ldd, hipStream_t st) {
+    hipLaunchKernelGGL((k_gather_cols<T>), dim3((m + 255) / 256, k), dim3(256), 0, st, X, m, colmap,
+                       sig2, k, dst, ldd);
+}
+template <typename T>
+void launch_gather_rows_conj(const C2<T>* X, int m, const int* colmap, const double* sig2, int k,
+                             C2<T>* dst, hipStream_t st) {
+    hipLaunchKernelGGL((k_gather_rows_conj<T>), dim3((m + 31) / 32, (k + 31) / 32), dim3(256), 0, st,
+                       X, m, colmap, sig2, k, dst);
+}
+template <typename T>
+void launch_conj_transpose(const C2<T>* A, int rows, int cols, C2<T>* Y, hipStream_t st) {
+    hipLaunchKernelGGL((k_conj_transpose<T>), dim3((rows + 31) / 32, (cols + 31) / 32), dim3(256), 0,
+                       st, A, rows, cols, Y);
+}
+template <typename T>
+void launch_copy(const C2<T>* src, C2<T>* dst, size_t count, hipStream_t st) {
+    if (!count) return;
+    hipLaunchKernelGGL((k_copy<T>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, src, dst, count);
+}
+
+#define INST(T)                                                                                  \
+    template int jacobi_orthogonalize<T>(C2<T>*, int, int, double, int, JacobiWork&, hipStream_t); \
+    template void launch_gather_cols<T>(const C2<T>*, int, const int*, const double*, int, C2<T>*,  \
+                                        int, hipStream_t);                                         \
+    template void launch_gather_rows_conj<T>(const C2<T>*, int, const int*, const double*, int,     \
+                                             C2<T>*, hipStream_t);                                 \
+    template void launch_conj_transpose<T>(const C2<T>*, int, int, C2<T>*, hipStream_t);           \
+    template void launch_copy<T>(const C2<T>*, C2<T>*, size_t, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace mpo

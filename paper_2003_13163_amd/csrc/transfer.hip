@@ -1,0 +1,128 @@
+// Transfer contraction of the vectorised MPO with one 4-vector per site
+// (Sec. III.D: total probability and output probabilities as a chain of
+// vector-matrix products).  Environments are FP64 complex in every precision.
+#include "common.h"
+
+namespace mpo {
+
+// env_out[b] = sum_{I,a} env_in[a] v[I] A[a + chiL*(I + 4b)]: one work-group
+// per output b, reducing over the contiguous 4*chiL entries of column b.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transfer_left(const C2<T>* __restrict__ A, int chiL,
+                                                       int chiR, const double2* __restrict__ env,
+                                                       const double2* __restrict__ v,
+                                                       double2* __restrict__ out) {
+    __shared__ double2 red[256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int len = 4 * chiL;
+    const C2<T>* col = A + (size_t)len * b;
+    double sr = 0.0, si = 0.0;
+    for (int e = t; e < len; e += 256) {
+        const int a = e % chiL, I = e / chiL;
+        const double2 x = to_d2(col[e]);
+        const double2 ev = env[a], vv = v[I];
+        const double2 w = make_double2(ev.x * vv.x - ev.y * vv.y, ev.x * vv.y + ev.y * vv.x);
+        sr += w.x * x.x - w.y * x.y;
+        si += w.x * x.y + w.y * x.x;
+    }
+    red[t] = make_double2(sr, si);
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) { red[t].x += red[t + o].x; red[t].y += red[t + o].y; }
+        __syncthreads();
+    }
+    if (t == 0) out[b] = red[0];
+}
+
+// Partial right transfer: scratch[chunk*chiL + a] = sum over this chunk's
+// (I, b) of A[a + chiL*(I + 4b)] v[I] env_in[b]; thread per a (coalesced).
+template <typename T>
+__global__ __launch_bounds__(256) void k_transfer_right_part(const C2<T>* __restrict__ A, int chiL,
+                                                             int chiR, const double2* __restrict__ env,
+                                                             const double2* __restrict__ v,
+                                                             int per_chunk,
+                                                             double2* __restrict__ scratch) {
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    const int chunk = blockIdx.y;
+    if (a >= chiL) return;
+    const int j0 = chunk * per_chunk, j1 = min(4 * chiR, j0 + per_chunk);
+    double sr = 0.0, si = 0.0;
+    for (int j = j0; j < j1; ++j) {      // j = I + 4b
+        const int I = j & 3, b = j >> 2;
+        const double2 x = to_d2(A[(size_t)a + (size_t)chiL * j]);
+        const double2 ev = env[b], vv = v[I];
+        const double2 w = make_double2(ev.x * vv.x - ev.y * vv.y, ev.x * vv.y + ev.y * vv.x);
+        sr += w.x * x.x - w.y * x.y;
+        si += w.x * x.y + w.y * x.x;
+    }
+    scratch[(size_t)chunk * chiL + a] = make_double2(sr, si);
+}
+
+__global__ void k_sum_chunks(const double2* __restrict__ scratch, int chiL, int chunks,
+                             double2* __restrict__ out) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= chiL) return;
+    double sr = 0.0, si = 0.0;
+    for (int c = 0; c < chunks; ++c) {
+        sr += scratch[(size_t)c * chiL + a].x;
+        si += scratch[(size_t)c * chiL + a].y;
+    }
+    out[a] = make_double2(sr, si);
+}
+
+__global__ __launch_bounds__(256) void k_dot(const double2* __restrict__ x,
+                                             const double2* __restrict__ y, int len,
+                                             double2* __restrict__ out) {
+    __shared__ double2 red[256];
+    const int t = threadIdx.x;
+    double sr = 0.0, si = 0.0;
+    for (int e = t; e < len; e += 256) {
+        const double2 a = x[e], b = y[e];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+    }
+    red[t] = make_double2(sr, si);
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) { red[t].x += red[t + o].x; red[t].y += red[t + o].y; }
+        __syncthreads();
+    }
+    if (t == 0) *out = red[0];
+}
+
+template <typename T>
+void launch_transfer_left(const C2<T>* A, int chiL, int chiR, const double2* env_in,
+                          const double2* v, double2* env_out, hipStream_t st) {
+    hipLaunchKernelGGL((k_transfer_left<T>), dim3(chiR), dim3(256), 0, st, A, chiL, chiR, env_in, v,
+                       env_out);
+}
+
+constexpr int kRightChunks = 64;
+
+template <typename T>
+void launch_transfer_right(const C2<T>* A, int chiL, int chiR, const double2* env_in,
+                           const double2* v, double2* env_out, double2* scratch, hipStream_t st) {
+    const int total = 4 * chiR;
+    int chunks = total < kRightChunks ? total : kRightChunks;
+    const int per = (total + chunks - 1) / chunks;
+    chunks = (total + per - 1) / per;
+    hipLaunchKernelGGL((k_transfer_right_part<T>), dim3((chiL + 255) / 256, chunks), dim3(256), 0, st,
+                       A, chiL, chiR, env_in, v, per, scratch);
+    hipLaunchKernelGGL(k_sum_chunks, dim3((chiL + 255) / 256), dim3(256), 0, st, scratch, chiL, chunks,
+                       env_out);
+}
+
+void launch_dot(const double2* x, const double2* y, int len, double2* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot, dim3(1), dim3(256), 0, st, x, y, len, out);
+}
+
+template void launch_transfer_left<double>(const double2*, int, int, const double2*, const double2*,
+                                           double2*, hipStream_t);
+template void launch_transfer_left<float>(const float2*, int, int, const double2*, const double2*,
+                                          double2*, hipStream_t);
+template void launch_transfer_right<double>(const double2*, int, int, const double2*,
+                                            const double2*, double2*, double2*, hipStream_t);
+template void launch_transfer_right<float>(const float2*, int, int, const double2*, const double2*,
+                                           double2*, double2*, hipStream_t);
+
+}  // namespace mpo

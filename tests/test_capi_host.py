@@ -1,0 +1,86 @@
+"""Host-side checks of libmpo that need no GPU: every entry point declared in
+include/mpo.h is exported, host-only argument validation, and the library's
+own superoperator builder against the oracle's (Sec. II.B, Sec. III.B)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import mpo_inputs as mi
+from oracle import gates
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import paper_2003_13163_amd as pm
+    try:
+        pm.library()
+    except ImportError:
+        from paper_2003_13163_amd import build
+        build.build()
+        pm.library()
+    return pm
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mpo.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:mpo_status|void|const char \*)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(pm):
+    names = declared_functions()
+    assert "run_brickwork" in names and "mpo_apply_2q_channel" in names
+    lib = pm.library()
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_workspace_bytes_validation(pm):
+    lib = pm.library()
+    out = ctypes.c_size_t()
+    assert lib.mpo_workspace_bytes(8, 256, 0, ctypes.byref(out)) == 0
+    small = out.value
+    assert lib.mpo_workspace_bytes(8, 256, 1, ctypes.byref(out)) == 0
+    assert out.value < small                       # complex64 tensors take half
+    assert lib.mpo_workspace_bytes(7, 256, 0, ctypes.byref(out)) == 1   # odd n
+    assert lib.mpo_workspace_bytes(8, 0, 0, ctypes.byref(out)) == 1
+    assert lib.mpo_workspace_bytes(8, 2048, 0, ctypes.byref(out)) == 1
+    assert b"chi_cap" in lib.mpo_last_error()
+
+
+def test_create_rejects_bad_arena_without_touching_device(pm):
+    lib = pm.library()
+    h = ctypes.c_void_p()
+    assert lib.mpo_create(8, 16, 0, 0, None, 1 << 30, None, ctypes.byref(h)) == 1
+    assert lib.mpo_create(8, 16, 0, 0, ctypes.c_void_p(256 + 8), 1 << 30, None, ctypes.byref(h)) == 1
+    need = ctypes.c_size_t()
+    lib.mpo_workspace_bytes(8, 16, 0, ctypes.byref(need))
+    assert lib.mpo_create(8, 16, 0, 0, ctypes.c_void_p(4096), need.value - 1, None, ctypes.byref(h)) == 2
+    assert lib.mpo_create(8, 16, 0, 5, ctypes.c_void_p(4096), need.value, None, ctypes.byref(h)) == 1
+
+
+@pytest.mark.parametrize("basis", ["pauli", "computational"])
+@pytest.mark.parametrize("p", [0.0, 0.01, 0.2])
+def test_superop_builder_matches_oracle(pm, basis, p):
+    draws = mi.ginibre_draws(6, 4, seed=12)
+    got = pm.build_superops(draws, p, basis)
+    want = gates.circuit_superops(draws, p, basis)
+    assert np.abs(got - want).max() < 1e-14
+    u = pm.build_superop(draws[0, 0], draws[0, 1], p, basis)[1]
+    assert np.abs(u - gates.haar_unitary(draws[0, 0], draws[0, 1])).max() < 1e-14
+
+
+def test_superop_builder_rejects_bad_p(pm):
+    lib = pm.library()
+    z = np.zeros(16)
+    out = np.zeros(512)
+    ptr = z.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    optr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.mpo_build_superop(ptr, ptr, -0.1, 0, optr, None) == 1
+    assert lib.mpo_build_superop(ptr, ptr, float("nan"), 0, optr, None) == 1

@@ -1,0 +1,288 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: FP64 mode |dS| <= 1e-10 and |d<Z>| <= 1e-6 (the stated targets
+for entropies and expectation values); FP32-MFMA mode |dS| <= 1e-4.  Raw
+tensors are compared only through gauge-invariant quantities (dense states,
+singular values, entropies, expectation values).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import mpo_inputs as mi
+from oracle import dense, gates, mpo as omp
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2003_13163_amd as pm
+    pm.library()
+    return pm
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def random_mps(n, dims, seed):
+    rng = np.random.default_rng(seed)
+    ts = []
+    for s in range(n):
+        cl = 1 if s == 0 else dims[s - 1]
+        cr = 1 if s == n - 1 else dims[s]
+        t = rng.standard_normal((cl, 4, cr)) + 1j * rng.standard_normal((cl, 4, cr))
+        ts.append(t / np.linalg.norm(t))
+    return ts
+
+
+def oracle_from(tensors, basis="pauli"):
+    return omp.MPO.from_tensors([t.copy() for t in tensors], basis)
+
+
+def gpu_dense(pm, state, basis="pauli"):
+    n, b, c, ts = pm.snapshot_to_tensors(state.export())
+    m = omp.MPO.__new__(omp.MPO)
+    m.n, m.basis, m.A, m.centre = n, basis, ts, c
+    return m.to_dense()
+
+
+# --------------------------------------------------------------- exact regime
+@pytest.mark.parametrize("basis", ["pauli", "computational"])
+def test_n8_exact_fp64_vs_dense(pm, basis):
+    n, depth, p = 8, 8, 0.02
+    say(f"case n8 exact fp64 basis={basis}")
+    draws = mi.ginibre_draws(n, depth, seed=0)
+    sup = pm.build_superops(draws, p, basis)
+    st = pm.Mpo(n, 256, "fp64", basis)
+    res = st.run_brickwork(depth, sup, 256, 1e-12, record="all")
+    _, s_ref, z_ref, tr_ref = dense.run_dense(n, depth, gates.circuit_superops(draws, p, "computational"),
+                                              mi.brickwork_sites(n, depth))
+    dS = np.abs(res["S"] - s_ref).max()
+    dZ = np.abs(res["Z"] - z_ref).max()
+    say(f"  max|dS| {dS:.3e} max|dZ| {dZ:.3e} trace {res['trace'][-1]!r}")
+    assert dS <= 1e-10
+    assert dZ <= 1e-6
+    assert np.abs(res["trace"] - 1.0).max() <= 1e-10
+    st.close()
+
+
+def test_n8_exact_fp32_vs_dense(pm):
+    n, depth, p = 8, 8, 0.02
+    say("case n8 exact fp32")
+    draws = mi.ginibre_draws(n, depth, seed=0)
+    sup = pm.build_superops(draws, p, "pauli")
+    st = pm.Mpo(n, 256, "fp32", "pauli")
+    res = st.run_brickwork(depth, sup, 256, 1e-12, record="all")
+    _, s_ref, z_ref, _ = dense.run_dense(n, depth, gates.circuit_superops(draws, p, "computational"),
+                                         mi.brickwork_sites(n, depth))
+    dS = np.abs(res["S"] - s_ref).max()
+    dZ = np.abs(res["Z"] - z_ref).max()
+    say(f"  fp32 max|dS| {dS:.3e} max|dZ| {dZ:.3e}")
+    assert dS <= 1e-4
+    assert dZ <= 1e-4
+    st.close()
+
+
+# ---------------------------------------------------------- single truncated gate
+@pytest.mark.parametrize("site,chi_max", [(4, 40), (0, 8), (8, 12), (3, 2000 // 50)])
+def test_single_gate_ragged_vs_oracle(pm, site, chi_max):
+    # bonds that span several 64-wide tiles with ragged tails; truncation active
+    n = 10
+    dims = [4, 16, 37, 50, 61, 50, 23, 16, 4]
+    say(f"case single gate n={n} site={site} chi_max={chi_max} dims={dims}")
+    ts = random_mps(n, dims, seed=site + 1)
+    draws = mi.ginibre_draws(2, 1, seed=77 + site)
+    sup = gates.circuit_superops(draws, 0.03, "pauli")[0]
+    ref = oracle_from(ts)
+    st = pm.Mpo(n, 128, "fp64", "pauli")
+    st.import_state(pm.tensors_to_snapshot(ts))
+    # normalise both the same way: compare relative to the total weight
+    info = st.apply(site, sup, chi_max, 1e-12)
+    rinfo = ref.apply_gate(site, sup, chi_max, 1e-12)
+    assert info.kept == rinfo.kept
+    assert abs(info.total_weight - rinfo.total_weight) <= 1e-12 * rinfo.total_weight
+    assert abs(info.discarded_weight - rinfo.discarded_weight) <= 1e-11 * rinfo.total_weight
+    assert abs(info.entropy - rinfo.entropy) <= 1e-10
+    rho_g = gpu_dense(pm, st)
+    rho_r = ref.to_dense()
+    rel = np.linalg.norm(rho_g - rho_r) / np.linalg.norm(rho_r)
+    say(f"  kept {info.kept} rel state diff {rel:.3e}")
+    assert rel <= 1e-11
+    st.close()
+
+
+@pytest.mark.parametrize("chi,prec,tol", [(128, "fp64", 1e-10), (512, "fp64", 1e-10), (128, "fp32", 1e-4)])
+def test_bulk_gate_singular_values(pm, chi, prec, tol):
+    # a saturated bulk gate: chi_L = chi_M = chi_R = chi, theta' is (4 chi) x (4 chi)
+    n = 12
+    dims = [min(chi, 4 ** min(b + 1, n - b - 1)) for b in range(n - 1)]
+    say(f"case bulk gate chi={chi} {prec} dims={dims}")
+    ts = random_mps(n, dims, seed=chi)
+    # decaying spectrum on the middle bonds, like an in-situ state
+    for s in range(n):
+        ts[s] *= np.exp(-0.01 * np.arange(ts[s].shape[2]))[None, None, :]
+    s0 = n // 2 - 1
+    draws = mi.ginibre_draws(2, 1, seed=5)
+    sup = gates.circuit_superops(draws, 0.01, "pauli")[0]
+    ref = oracle_from(ts)
+    st = pm.Mpo(n, chi, prec, "pauli")
+    st.import_state(pm.tensors_to_snapshot(ts))
+    info = st.apply(s0, sup, chi, 1e-12)
+    rinfo = ref.apply_gate(s0, sup, chi, 1e-12)
+    lam_ref = ref.schmidt_sweep()[s0]
+    lam_gpu = st.singular_values(s0)
+    k = min(lam_ref.size, lam_gpu.size)
+    say(f"  kept {info.kept}/{rinfo.kept} dS {info.entropy - rinfo.entropy:.3e}")
+    assert info.kept == rinfo.kept
+    assert abs(info.entropy - rinfo.entropy) <= tol
+    assert np.abs(lam_gpu[:k] - lam_ref[:k]).max() <= tol * lam_ref[0]
+    st.close()
+
+
+# -------------------------------------------------------- truncating circuit n=32
+def test_n32_truncating_fp64_vs_oracle(pm):
+    path = os.path.join(HERE, "golden", "oracle_n32_d32_p0.01_chi256.json")
+    gold = json.load(open(path))
+    w = gold["workload"]
+    n, depth = w["n"], w["depth"]
+    say(f"case n32 truncating fp64 chi={w['chi_max']}")
+    draws = mi.ginibre_draws(n, depth, seed=w["seed"])
+    sup = pm.build_superops(draws, w["p"], "pauli")
+    st = pm.Mpo(n, w["chi_max"], "fp64", "pauli")
+    res = st.run_brickwork(depth, sup, w["chi_max"], w["cutoff"], record="all")
+    S_ref, Z_ref = np.array(gold["S"]), np.array(gold["Z"])
+    dS = np.abs(res["S"] - S_ref).max()
+    dZ = np.abs(res["Z"] - Z_ref).max()
+    dmid = np.abs(res["S"][:, n // 2 - 1] - S_ref[:, n // 2 - 1]).max()
+    say(f"  max|dS| {dS:.3e} (mid-chain {dmid:.3e}) max|dZ| {dZ:.3e} "
+        f"trace {res['trace'][-1]:.12f} vs {gold['trace'][-1]:.12f}")
+    assert dS <= 1e-10
+    assert dZ <= 1e-6
+    assert np.abs(res["discarded"] - np.array(gold["discarded"])).max() <= 1e-12
+    st.close()
+
+
+# ----------------------------------------------------------------- observables
+@pytest.mark.parametrize("basis", ["pauli", "computational"])
+def test_observables_vs_oracle(pm, basis):
+    n = 8
+    dims = [4, 9, 13, 17, 13, 9, 4]
+    say(f"case observables basis={basis}")
+    ts = random_mps(n, dims, seed=3)
+    ref = oracle_from(ts, basis)
+    st = pm.Mpo(n, 32, "fp64", basis)
+    st.import_state(pm.tensors_to_snapshot(ts, basis))
+    tr = st.trace()
+    assert abs(tr - ref.trace()) <= 1e-12 * abs(ref.trace())
+    z, trz = st.expect_z_all()
+    assert np.abs(z - ref.expect_z_all()).max() <= 1e-10
+    rng = np.random.default_rng(1)
+    for _ in range(4):
+        codes = rng.integers(0, 4, n)
+        got = st.expect(codes)
+        want = ref.pauli_expectation(codes)
+        assert abs(got - want) <= 1e-10 * max(1.0, abs(want))
+    S = st.entropy(-1)
+    assert np.abs(S - ref.bond_entropies()).max() <= 1e-10
+    for b in (0, 3, 6):
+        assert abs(st.entropy(b) - S[b]) <= 1e-12
+    lam = st.singular_values(3)
+    lam_ref = ref.schmidt_sweep()[3]
+    k = min(lam.size, lam_ref.size)
+    assert np.abs(lam[:k] - lam_ref[:k]).max() <= 1e-12 * lam_ref[0]
+    st.close()
+
+
+def test_export_import_roundtrip(pm):
+    n = 6
+    ts = random_mps(n, [4, 7, 9, 7, 4], seed=11)
+    st = pm.Mpo(n, 16, "fp64", "pauli")
+    st.import_state(pm.tensors_to_snapshot(ts))
+    rho1 = gpu_dense(pm, st)
+    st.canonicalize(2)
+    assert st.bond_dims()[1] == 2
+    data = st.export()
+    st2 = pm.Mpo(n, 16, "fp64", "pauli")
+    st2.import_state(data)
+    rho2 = gpu_dense(pm, st2)
+    ref = oracle_from(ts).to_dense()
+    assert np.linalg.norm(rho1 - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.linalg.norm(rho2 - ref) <= 1e-12 * np.linalg.norm(ref)
+    st.close()
+    st2.close()
+
+
+def test_product_states_and_edges(pm):
+    n = 4
+    st = pm.Mpo(n, 16, "fp64", "pauli")
+    st.init_product([1, 0, 1, 1])
+    z, tr = st.expect_z_all()
+    np.testing.assert_allclose(z, [-1, 1, -1, -1], atol=1e-14)
+    assert abs(tr - 1) < 1e-14
+    assert np.abs(st.entropy(-1)).max() < 1e-14
+    # chi_max = 1 keeps a single value; discarded weight is reported
+    draws = mi.ginibre_draws(2, 1, seed=2)
+    sup = pm.build_superops(draws, 0.05, "pauli")[0]
+    info = st.apply(1, sup, 1, 1e-12)
+    ref = omp.MPO(n, "pauli", bits=[1, 0, 1, 1])
+    rinfo = ref.apply_gate(1, sup, 1, 1e-12)
+    assert info.kept == 1 and rinfo.kept == 1
+    assert abs(info.discarded_weight - rinfo.discarded_weight) < 1e-13
+    # n = 2: the whole chain is one gate
+    st2 = pm.Mpo(2, 16, "fp64", "pauli")
+    info = st2.apply(0, sup, 16, 1e-12)
+    r2 = omp.MPO(2, "pauli")
+    rinfo = r2.apply_gate(0, sup, 16, 1e-12)
+    assert info.kept == rinfo.kept
+    assert abs(info.entropy - rinfo.entropy) < 1e-12
+    st.close()
+    st2.close()
+
+
+def test_error_paths(pm):
+    st = pm.Mpo(4, 8, "fp64", "pauli")
+    eye = np.eye(16, dtype=complex)
+    with pytest.raises(pm.MpoError) as e:
+        st.apply(3, eye, 4)
+    assert e.value.status == 1
+    with pytest.raises(pm.MpoError) as e:
+        st.apply(0, eye, 9)
+    assert e.value.status == 1
+    with pytest.raises(pm.MpoError) as e:
+        st.run_brickwork(2, np.stack([eye] * 2), 4)    # 3 gates expected
+    assert e.value.status == 1
+    bad = eye.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(pm.MpoError) as e:
+        st.apply(0, bad, 4)
+    assert e.value.status == 4
+    with pytest.raises(pm.MpoError) as e:
+        st.trace()
+    assert e.value.status == 6
+    st.init_product()
+    assert abs(st.trace() - 1) < 1e-14
+    st.close()
+
+
+def test_deterministic(pm):
+    n, depth, p = 10, 6, 0.01
+    draws = mi.ginibre_draws(n, depth, seed=9)
+    sup = pm.build_superops(draws, p, "pauli")
+    outs = []
+    for _ in range(2):
+        st = pm.Mpo(n, 32, "fp64", "pauli")
+        outs.append(st.run_brickwork(depth, sup, 32, 1e-12, record="all"))
+        st.close()
+    assert np.array_equal(outs[0]["S"], outs[1]["S"])
+    assert np.array_equal(outs[0]["Z"], outs[1]["Z"])
