@@ -1,0 +1,201 @@
+"""Benchmark: two-qubit-gate MPO updates per second at bond dimension 1024.
+
+A step is one noisy two-qubit gate update (centre move + contraction + 16x16
+channel + truncated SVD + entropy) on a saturated bulk bond,
+chi_L = chi_M = chi_R = 1024, theta' of size 4096 x 4096.  The state is an
+in-situ one: a 16-qubit chain evolved from |0..0> (in FP64) by a depth-10
+brickwork of Haar gates with two-qubit depolarizing noise p = 0.01 (seeded),
+which saturates bonds 4..10 at chi = 1024.  Timed gates then continue the brickwork
+on sites 5..9 (odd time steps 5, 7, 9; even time steps 6, 8) with fresh Haar
+gates, so every timed gate has the full 4096 x 4096 split and the centre
+moves a real brickwork needs.  Inputs are resident in HBM before timing.
+
+The FP32-MFMA path is the headline `value`; the FP64 path on the same gates
+and snapshot is reported beside it, with the entropy error between the two
+and against the CPU oracle on the first timed gate.  `roofline` is for the
+kernel class with the largest event-measured time in the FP32 timed region;
+`cpu_baseline` times the oracle on one bulk gate of the same snapshot.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--chi 1024]
+                       [--no-cpu-baseline] [--profile-only]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "2q-gate MPO updates/sec at chi=1024 (FP32-MFMA vs FP64) + entropy err vs oracle"
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}   # dense MFMA (= vector) peaks of MI355X
+HBM_PEAK = 8.0e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def bulk_schedule(lo, hi, count, start_parity=1):
+    """Sites of `count` gates of a brickwork restricted to sites lo..hi."""
+    out, t = [], start_parity
+    while len(out) < count:
+        first = lo if (t % 2) == (lo % 2) else lo + 1
+        for s in range(first, hi + 1, 2):
+            if len(out) < count:
+                out.append(s)
+        t += 1
+    return out
+
+
+def build_snapshot(pm, mi, n, depth, p, chi, seed):
+    draws = mi.ginibre_draws(n, depth, seed=seed)
+    sup = pm.build_superops(draws, p, "pauli")
+    st = pm.Mpo(n, chi, "fp64", "pauli")
+    t0 = time.time()
+    st.run_brickwork(depth, sup, chi, 1e-12, record=None)
+    dims, centre = st.bond_dims()
+    snap = st.export()
+    st.close()
+    return snap, dims, time.time() - t0
+
+
+def timed_run(pm, torch, snap, n, chi, prec, sites, sups, warmup, steps):
+    st = pm.Mpo(n, chi, prec, "pauli")
+    st.import_state(snap)
+    ent = []
+    for g in range(warmup):
+        ent.append(st.apply(sites[g], sups[g], chi, 1e-12).entropy)
+    torch.cuda.synchronize()
+    st.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(warmup, warmup + steps):
+        ent.append(st.apply(sites[g], sups[g], chi, 1e-12).entropy)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = st.profile_read()
+    dims = st.bond_dims()[0]
+    st.close()
+    return dt, np.array(ent), prof, dims
+
+
+def roofline(prof, prec):
+    """Roofline object for the kernel class with the largest measured time."""
+    ks = prof["kernels"]
+    name, k = max(ks.items(), key=lambda kv: kv[1]["ms"])
+    t = k["ms"] * 1e-3
+    launches = max(1, k["launches"])
+    ach = k["flops"] / t if t > 0 else 0.0
+    if name == "jacobi_eig64":
+        # FP64 two-sided rotations on vector ALUs (the eigen core runs in FP64 in every mode)
+        bound, peak = "alu", PEAK["fp64"]
+    else:
+        bound, peak = "mfma", PEAK[prec]
+    return name, {"bound": bound, "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                  "frac": ach / peak, "traffic": None, "kernel": name, "launches": k["launches"],
+                  "avg_us": 1e3 * k["ms"] / launches, "flops_per_launch": k["flops"] / launches,
+                  "share_of_timed_region": k["ms"] / sum(v["ms"] for v in ks.values())}
+
+
+def cpu_baseline(snap_bytes, pm, site, sup, chi):
+    """Oracle (numpy complex128) on one bulk gate of the same snapshot."""
+    from oracle import mpo as omp
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    n, basis, centre, tensors = pm.snapshot_to_tensors(snap_bytes)
+    m = omp.MPO.__new__(omp.MPO)
+    m.n, m.basis, m.A, m.centre = n, "pauli", tensors, centre
+    t0 = time.perf_counter()
+    info = m.apply_gate(site, sup, chi, 1e-12)
+    dt = time.perf_counter() - t0
+    return dt, info, cores
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--chi", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precisions", default="fp32,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import mpo_inputs as mi
+    import paper_2003_13163_amd as pm
+    pm.library()
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+
+    n, depth, p, chi, seed = 16, 10, 0.01, args.chi, 0
+    log(f"building in-situ snapshot: n={n} depth={depth} p={p} chi={chi}")
+    snap, dims, t_warm = build_snapshot(pm, mi, n, depth, p, chi, seed)
+    log(f"  bond dims {dims} ({t_warm:.1f} s)")
+    lo, hi = 5, 9
+    total = args.warmup + args.steps
+    sites = bulk_schedule(lo, hi, total)
+    draws = mi.ginibre_draws(n, 2 * total + 4, seed=seed + 1)
+    sups = pm.build_superops(draws[:total], p, "pauli")
+
+    res = {}
+    for prec in args.precisions.split(","):
+        log(f"timing {prec}: warmup {args.warmup} + {args.steps} gates")
+        dt, ent, prof, dims_after = timed_run(pm, torch, snap, n, chi, prec, sites, sups,
+                                              args.warmup, args.steps)
+        res[prec] = {"seconds": dt, "entropy": ent, "prof": prof, "dims": dims_after}
+        log(f"  {prec}: {args.steps / dt:.3f} updates/s ({1e3 * dt / args.steps:.1f} ms/update) "
+            f"svd {prof['svd']}")
+
+    head = "fp32" if "fp32" in res else next(iter(res))
+    value = args.steps / res[head]["seconds"]
+    rl_name, rl = roofline(res[head]["prof"], head)
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * res[head]["seconds"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if head == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": f"bulk noisy 2q gate at chi={chi} (theta' {4 * chi}x{4 * chi}) on an "
+                               f"in-situ {n}-qubit state (depth-{depth} Haar+depolarizing p={p} "
+                               f"brickwork, seed {seed}), brickwork gates on sites {lo}..{hi}",
+                   "chi": chi, "n": n, "p": p, "cutoff": 1e-12, "basis": "pauli",
+                   "bond_dims": dims},
+        "roofline": rl,
+    }
+    if "fp64" in res:
+        out["fp64"] = {"value": args.steps / res["fp64"]["seconds"],
+                       "ms_per_step": 1e3 * res["fp64"]["seconds"] / args.steps, "dtype": "f64"}
+    if "fp64" in res and "fp32" in res:
+        out["entropy_error"] = {"fp32_vs_fp64_max_abs": float(np.abs(res["fp32"]["entropy"] -
+                                                                     res["fp64"]["entropy"]).max())}
+    out["kernels"] = {k: {kk: vv for kk, vv in v["prof"]["kernels"].items() if vv["launches"]}
+                      for k, v in res.items()}
+    out["svd"] = {k: v["prof"]["svd"] for k, v in res.items()}
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on the first bulk gate of the snapshot")
+        dt, info, cores = cpu_baseline(snap, pm, sites[0], sups[0], chi)
+        out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "updates/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"1 bulk gate (site {sites[0]}, chi={chi}) of the same "
+                                         f"snapshot, numpy complex128 gesdd, {dt:.1f} s"}
+        err = out.setdefault("entropy_error", {})
+        for prec in res:
+            err[f"{prec}_vs_oracle_first_gate"] = abs(float(res[prec]["entropy"][0]) - info.entropy)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

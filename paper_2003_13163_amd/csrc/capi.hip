@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -77,7 +78,7 @@ Layout make_layout(int n, int chi_cap, mpo_precision prec) {
     L.max_pairs = nb / 2;
     L.partial_bytes = align256((size_t)L.max_pairs * kSplitsMax * 4096 * csz);
     L.w_bytes = align256((size_t)L.max_pairs * 4096 * csz);
-    L.skip_bytes = align256((size_t)L.max_pairs * sizeof(int));
+    L.skip_bytes = align256((size_t)4 * L.max_pairs * sizeof(int));   // 16-column blocks: 2x pairs
     L.vecN_bytes = align256((size_t)4 * chi_cap * sizeof(double));
     L.info_bytes = align256(sizeof(DevInfo));
     L.env_bytes = align256((size_t)(n + 1) * chi_cap * sizeof(double2));
@@ -541,6 +542,10 @@ mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis, v
     h->jw.max_pairs = L.max_pairs;
     h->jw.splits = kSplitsMax;
     h->jw.prof = &h->prof;
+    h->jw.block = 16;
+    h->jw.inner = 2;
+    if (const char* e = std::getenv("MPO_JACOBI_BLOCK")) h->jw.block = std::atoi(e) == 16 ? 16 : 32;
+    if (const char* e = std::getenv("MPO_JACOBI_INNER")) h->jw.inner = std::max(1, std::min(8, std::atoi(e)));
     h->envL = (double2*)p; p += L.env_bytes;
     h->envR = (double2*)p; p += L.env_bytes;
     h->tscr = (double2*)p; p += L.tscr_bytes;

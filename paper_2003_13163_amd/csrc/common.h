@@ -64,7 +64,7 @@ struct DevInfo {
     double entropy;
     unsigned long long offmax_bits;  // max relative off-diagonal of the sweep (bits of a double >= 0)
     int rotations;         // pairs rotated in the sweep
-    int pad;
+    int inner_steps;       // inner Jacobi steps executed in the sweep (all pairs)
 };
 
 }  // namespace mpo
@@ -94,6 +94,8 @@ struct JacobiWork {
     int max_pairs;
     int splits;
     Profiler* prof;        // may be off
+    int block;             // Jacobi block width: 16 or 32 columns
+    int inner;             // inner FP64 sweeps per block pair
     long long n_splits, n_sweeps, n_rounds, n_rotations;   // running counters
 };
 

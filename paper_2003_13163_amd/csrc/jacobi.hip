@@ -15,8 +15,7 @@
 
 namespace mpo {
 
-constexpr int JB = 32;         // columns per block
-constexpr int JP = 2 * JB;     // columns per pair
+// Block sizes: JB columns per block, 2*JB per pair (JB = 16 or 32).
 
 // Round-robin tournament (circle method) over nb players (nb even):
 // pair 0 of round r is (r, nb-1); pair i > 0 is (r+i, r-i) mod (nb-1).
@@ -89,39 +88,42 @@ __global__ __launch_bounds__(1024) void k_sort_desc(const double* __restrict__ n
 }
 
 // ------------------------------------------------------------- pair Gram
-// partials[(pair*splits + split)*4096 + i + 64*j] = sum_rows conj(x_i) x_j over
-// this split's row range, for the 64 columns of the pair.
-template <typename T>
+// partials[(pair*splits + split)*NB*NB + i + NB*j] = sum_rows conj(x_i) x_j over
+// this split's row range, for the NB = 2*JB columns of the pair.  Four waves in
+// a 2x2 layout, each owning (NB/2) x (NB/2) of the Gram tile.
+template <typename T, int JB>
 __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, int m, int N,
                                                    const int* __restrict__ colmap, int nb,
                                                    int round, int splits, int chunk,
                                                    C2<T>* __restrict__ partials) {
-    __shared__ C2<T> Xs[16][JP + 1];
-    __shared__ int cols[JP];
+    constexpr int NB = 2 * JB, MB = NB / 32;   // MFMA tiles per wave per dimension
+    constexpr int RB = 4096 / NB;              // rows per staged slab (LDS tile NB x RB)
+    __shared__ C2<T> Xs[RB][NB + 1];
+    __shared__ int cols[NB];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int pair = blockIdx.x, split = blockIdx.y;
     int p, q;
     pair_of(round, pair, nb, p, q);
-    if (t < JP) {
+    if (t < NB) {
         const int lj = (t < JB) ? p * JB + t : q * JB + (t - JB);
         cols[t] = (lj < N) ? colmap[lj] : -1;
     }
     __syncthreads();
     const int r0 = split * chunk;
     const int r1 = min(m, r0 + chunk);
-    A4<T> accR[2][2], accI[2][2];
+    A4<T> accR[MB][MB], accI[MB][MB];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < MB; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < MB; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
-    for (int k0 = r0; k0 < r1; k0 += 16) {
+    for (int k0 = r0; k0 < r1; k0 += RB) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < (RB * NB) / 256; ++r) {
             const int e = t + 256 * r;
-            const int row = e & 15, col = e >> 4;
+            const int row = e % RB, col = e / RB;
             const int c = cols[col];
             C2<T> v = czero<T>();
             if (c >= 0 && k0 + row < r1) v = X[(size_t)(k0 + row) + (size_t)m * c];
@@ -129,18 +131,18 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-            C2<T> a[2], b[2];
+        for (int kk = 0; kk < RB; kk += 4) {
+            C2<T> a[MB], b[MB];
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                a[s] = Xs[kk + (lane >> 4)][wm * 32 + s * 16 + (lane & 15)];
-                b[s] = Xs[kk + (lane >> 4)][wn * 32 + s * 16 + (lane & 15)];
+            for (int s = 0; s < MB; ++s) {
+                a[s] = Xs[kk + (lane >> 4)][wm * (NB / 2) + s * 16 + (lane & 15)];
+                b[s] = Xs[kk + (lane >> 4)][wn * (NB / 2) + s * 16 + (lane & 15)];
             }
             // A[i][k] = conj(X[k][i]): (ar - i ai)(br + i bi)
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
+            for (int bi = 0; bi < MB; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
+                for (int bj = 0; bj < MB; ++bj) {
                     accR[bi][bj] = mfma16(a[bi].x, b[bj].x, accR[bi][bj]);
                     accR[bi][bj] = mfma16(a[bi].y, b[bj].y, accR[bi][bj]);
                     accI[bi][bj] = mfma16(a[bi].x, b[bj].y, accI[bi][bj]);
@@ -149,40 +151,46 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
         }
         __syncthreads();
     }
-    C2<T>* out = partials + (size_t)(pair * splits + split) * (JP * JP);
+    C2<T>* out = partials + (size_t)(pair * splits + split) * (NB * NB);
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < MB; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < MB; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = wm * 32 + bi * 16 + acc_row<T>(lane, r);
-                const int j = wn * 32 + bj * 16 + (lane & 15);
-                out[i + JP * j] = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
+                const int i = wm * (NB / 2) + bi * 16 + acc_row<T>(lane, r);
+                const int j = wn * (NB / 2) + bj * 16 + (lane & 15);
+                out[i + NB * j] = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
             }
 }
 
-// ------------------------------------------------- 64x64 Hermitian eigen (FP64)
+// --------------------------------------------------- NB x NB Hermitian eigen (FP64)
 // Sums the Gram partials, measures the largest relative off-diagonal element
 // |g_ij| / sqrt(g_ii g_jj), and if it exceeds tol runs up to inner_max cyclic
-// Jacobi sweeps (parallel ordering, 32 disjoint rotations per step), giving a
-// unitary W with W^H G W close to diagonal.  Columns whose squared norm is at
-// most zthr2 * ||X||_F^2 are treated as zero and never rotated.
+// Jacobi sweeps (parallel ordering: NB/2 disjoint rotations per step), giving
+// a unitary W with W^H G W close to diagonal.  A step computes the NB/2
+// rotations in one wave, then every thread transforms whole 2x2 blocks
+// G[{i1,j1}][{i2,j2}] <- J1^H G J2 (rows and columns at once) and rotates
+// (row, pair) slices of W; inactive pairs use the exact identity rotation.
+// Columns whose squared norm is at most zrel2 * ||X||_F^2 are never rotated.
 __device__ __forceinline__ double2 dmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+__device__ __forceinline__ double2 dmulc(double2 a, double2 b) {   // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
 
-__device__ double block_off(const double2 (*G)[JP + 1], double zthr, double* red) {
+template <int NB>
+__device__ double block_off(const double2 (*G)[NB + 1], double zthr, double* red) {
     const int t = threadIdx.x;
     double mx = 0.0;
-    for (int e = t; e < JP * JP; e += 256) {
-        const int i = e & (JP - 1), j = e >> 6;
+    for (int e = t; e < NB * NB; e += 256) {
+        const int i = e % NB, j = e / NB;
         if (i < j) {
             const double a = G[i][i].x, d = G[j][j].x;
             if (a > zthr && d > zthr) {
                 const double2 g = G[i][j];
-                const double r = sqrt(g.x * g.x + g.y * g.y) / sqrt(a * d);
-                mx = fmax(mx, r);
+                mx = fmax(mx, sqrt(g.x * g.x + g.y * g.y) / sqrt(a * d));
             }
         }
     }
@@ -197,33 +205,32 @@ __device__ double block_off(const double2 (*G)[JP + 1], double zthr, double* red
     return r;
 }
 
-template <typename T>
+template <typename T, int JB>
 __global__ __launch_bounds__(256) void k_pair_eig(const C2<T>* __restrict__ partials, int splits,
                                                   double tol, double zrel2,
                                                   const double* __restrict__ fro2, int inner_max,
                                                   C2<T>* __restrict__ Wout, int* __restrict__ skip,
                                                   DevInfo* info) {
-    __shared__ double2 G[JP][JP + 1];
-    __shared__ double2 W[JP][JP + 1];
+    constexpr int NB = 2 * JB, NP = JB;
+    __shared__ double2 G[NB][NB + 1];
+    __shared__ double2 W[NB][NB + 1];
     __shared__ double red[256];
-    __shared__ double rc[JB], rs[JB];
-    __shared__ double2 rph[JB];
-    __shared__ int ri[JB], rj[JB], ract[JB];
+    __shared__ double4 rot[NP];       // c, s, Re ph, Im ph
+    __shared__ int pi_[NP], pj_[NP];
     const int t = threadIdx.x, pair = blockIdx.x;
-    for (int e = t; e < JP * JP; e += 256) {
-        const int i = e & (JP - 1), j = e >> 6;
+    for (int e = t; e < NB * NB; e += 256) {
+        const int i = e % NB, j = e / NB;
         double2 s = make_double2(0.0, 0.0);
         for (int sp = 0; sp < splits; ++sp) {
-            const double2 v = to_d2(partials[(size_t)(pair * splits + sp) * (JP * JP) + i + JP * j]);
+            const double2 v = to_d2(partials[(size_t)(pair * splits + sp) * (NB * NB) + i + NB * j]);
             s.x += v.x;
             s.y += v.y;
         }
         G[i][j] = s;
     }
     __syncthreads();
-    // exact Hermitian symmetry and real diagonal
-    for (int e = t; e < JP * JP; e += 256) {
-        const int i = e & (JP - 1), j = e >> 6;
+    for (int e = t; e < NB * NB; e += 256) {
+        const int i = e % NB, j = e / NB;
         if (i < j) {
             const double2 a = G[i][j], b = G[j][i];
             const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
@@ -235,107 +242,120 @@ __global__ __launch_bounds__(256) void k_pair_eig(const C2<T>* __restrict__ part
     }
     __syncthreads();
     const double zthr = zrel2 * (*fro2);
-    const double off0 = block_off(G, zthr, red);
+    const double off0 = block_off<NB>(G, zthr, red);
     if (off0 <= tol) {
         if (t == 0) skip[pair] = 1;
         return;
     }
-    for (int e = t; e < JP * JP; e += 256) {
-        const int i = e & (JP - 1), j = e >> 6;
+    for (int e = t; e < NB * NB; e += 256) {
+        const int i = e % NB, j = e / NB;
         W[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
+    int steps_done = 0;
     for (int sweep = 0; sweep < inner_max; ++sweep) {
-        for (int step = 0; step < JP - 1; ++step) {
-            if (t < JB) {
+        steps_done += NB - 1;
+        for (int step = 0; step < NB - 1; ++step) {
+            if (t < NP) {
                 int i, j;
-                pair_of(step, t, JP, i, j);
+                pair_of(step, t, NB, i, j);
                 const double a = G[i][i].x, d = G[j][j].x;
                 const double2 g = G[i][j];
                 const double ag = sqrt(g.x * g.x + g.y * g.y);
-                int act = (a > zthr && d > zthr && ag > tol * sqrt(a * d)) ? 1 : 0;
-                double c = 1.0, s = 0.0;
-                double2 ph = make_double2(1.0, 0.0);
-                if (act) {
-                    ph = make_double2(g.x / ag, g.y / ag);
+                double c = 1.0, s = 0.0, pr = 1.0, pim = 0.0;
+                if (a > zthr && d > zthr && ag > tol * sqrt(a * d)) {
+                    pr = g.x / ag;
+                    pim = g.y / ag;
                     const double tau = (d - a) / (2.0 * ag);
                     const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + tt * tt);
                     s = tt * c;
                 }
-                ri[t] = i; rj[t] = j; ract[t] = act; rc[t] = c; rs[t] = s; rph[t] = ph;
+                rot[t] = make_double4(c, s, pr, pim);
+                pi_[t] = i;
+                pj_[t] = j;
             }
             __syncthreads();
-            // G <- G J and W <- W J (columns i, j)
-            for (int e = t; e < JB * JP; e += 256) {
-                const int pr = e >> 6, row = e & (JP - 1);
-                if (!ract[pr]) continue;
-                const int i = ri[pr], j = rj[pr];
-                const double c = rc[pr], s = rs[pr];
-                const double2 phc = make_double2(rph[pr].x, -rph[pr].y);
-                double2 gi = G[row][i], gj = G[row][j];
-                double2 pg = dmul(phc, gj);
-                G[row][i] = make_double2(c * gi.x - s * pg.x, c * gi.y - s * pg.y);
-                G[row][j] = make_double2(s * gi.x + c * pg.x, s * gi.y + c * pg.y);
-                gi = W[row][i]; gj = W[row][j];
-                pg = dmul(phc, gj);
-                W[row][i] = make_double2(c * gi.x - s * pg.x, c * gi.y - s * pg.y);
-                W[row][j] = make_double2(s * gi.x + c * pg.x, s * gi.y + c * pg.y);
+            // G <- J^H G J, one 2x2 block per (P1, P2)
+#pragma unroll
+            for (int u = 0; u < (NP * NP + 255) / 256; ++u) {
+                const int b = t + 256 * u;
+                if (NP * NP % 256 == 0 || b < NP * NP) {
+                    const int P1 = b / NP, P2 = b % NP;
+                    const double4 r1 = rot[P1], r2 = rot[P2];
+                    const int i1 = pi_[P1], j1 = pj_[P1], i2 = pi_[P2], j2 = pj_[P2];
+                    const double2 b00 = G[i1][i2], b01 = G[i1][j2], b10 = G[j1][i2], b11 = G[j1][j2];
+                    // C = B J2 with J2 = [[c, s], [-s conj(ph), c conj(ph)]]
+                    const double2 ph2 = make_double2(r2.z, r2.w);
+                    const double2 q01 = dmulc(ph2, b01), q11 = dmulc(ph2, b11);
+                    const double2 c00 = make_double2(r2.x * b00.x - r2.y * q01.x, r2.x * b00.y - r2.y * q01.y);
+                    const double2 c01 = make_double2(r2.y * b00.x + r2.x * q01.x, r2.y * b00.y + r2.x * q01.y);
+                    const double2 c10 = make_double2(r2.x * b10.x - r2.y * q11.x, r2.x * b10.y - r2.y * q11.y);
+                    const double2 c11 = make_double2(r2.y * b10.x + r2.x * q11.x, r2.y * b10.y + r2.x * q11.y);
+                    // D = J1^H C: rows i1 <- c C0 - s ph C1, j1 <- s C0 + c ph C1
+                    const double2 ph1 = make_double2(r1.z, r1.w);
+                    const double2 p10 = dmul(ph1, c10), p11 = dmul(ph1, c11);
+                    G[i1][i2] = make_double2(r1.x * c00.x - r1.y * p10.x, r1.x * c00.y - r1.y * p10.y);
+                    G[i1][j2] = make_double2(r1.x * c01.x - r1.y * p11.x, r1.x * c01.y - r1.y * p11.y);
+                    G[j1][i2] = make_double2(r1.y * c00.x + r1.x * p10.x, r1.y * c00.y + r1.x * p10.y);
+                    G[j1][j2] = make_double2(r1.y * c01.x + r1.x * p11.x, r1.y * c01.y + r1.x * p11.y);
+                }
             }
-            __syncthreads();
-            // G <- J^H G (rows i, j)
-            for (int e = t; e < JB * JP; e += 256) {
-                const int pr = e >> 6, col = e & (JP - 1);
-                if (!ract[pr]) continue;
-                const int i = ri[pr], j = rj[pr];
-                const double c = rc[pr], s = rs[pr];
-                const double2 ph = rph[pr];
-                const double2 gi = G[i][col], gj = G[j][col];
-                const double2 pg = dmul(ph, gj);
-                G[i][col] = make_double2(c * gi.x - s * pg.x, c * gi.y - s * pg.y);
-                G[j][col] = make_double2(s * gi.x + c * pg.x, s * gi.y + c * pg.y);
+            // W <- W J
+#pragma unroll
+            for (int u = 0; u < (NB * NP) / 256; ++u) {
+                const int e = t + 256 * u;
+                const int P = e / NB, row = e % NB;
+                const double4 r = rot[P];
+                const int i = pi_[P], j = pj_[P];
+                const double2 wi = W[row][i], wj = W[row][j];
+                const double2 q = dmulc(make_double2(r.z, r.w), wj);
+                W[row][i] = make_double2(r.x * wi.x - r.y * q.x, r.x * wi.y - r.y * q.y);
+                W[row][j] = make_double2(r.y * wi.x + r.x * q.x, r.y * wi.y + r.x * q.y);
             }
             __syncthreads();
         }
-        if (sweep + 1 < inner_max && block_off(G, zthr, red) <= tol) break;
+        if (sweep + 1 < inner_max && block_off<NB>(G, zthr, red) <= tol) break;
     }
-    C2<T>* wo = Wout + (size_t)pair * (JP * JP);
-    for (int e = t; e < JP * JP; e += 256) {
-        const int i = e & (JP - 1), j = e >> 6;
-        wo[i + JP * j] = from_d2<T>(W[i][j]);
+    C2<T>* wo = Wout + (size_t)pair * (NB * NB);
+    for (int e = t; e < NB * NB; e += 256) {
+        const int i = e % NB, j = e / NB;
+        wo[i + NB * j] = from_d2<T>(W[i][j]);
     }
     if (t == 0) {
         skip[pair] = 0;
         atomicMax(&info->offmax_bits, (unsigned long long)__double_as_longlong(off0));
         atomicAdd(&info->rotations, 1);
+        atomicAdd(&info->inner_steps, steps_done);
     }
 }
 
 // ------------------------------------------------------------- pair update
-// [x_p x_q] <- [x_p x_q] W for one 64-row slab of the pair's columns.
-template <typename T>
+// [x_p x_q] <- [x_p x_q] W for one 64-row slab of the pair's NB columns.
+template <typename T, int JB>
 __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int m, int N,
                                                      const int* __restrict__ colmap, int nb,
                                                      int round, const C2<T>* __restrict__ Wm,
                                                      const int* __restrict__ skip) {
+    constexpr int NB = 2 * JB, MB = NB / 32;
     const int pair = blockIdx.x;
     if (skip[pair]) return;
-    __shared__ C2<T> Ws[JP][JP + 1];   // Ws[k][j] = W[k][j]
-    __shared__ C2<T> Xt[JP][JP + 1];   // Xt[col][row]
-    __shared__ int cols[JP];
+    __shared__ C2<T> Ws[NB][NB + 1];   // Ws[k][j] = W[k][j]
+    __shared__ C2<T> Xt[NB][64 + 1];   // Xt[col][row]
+    __shared__ int cols[NB];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     int p, q;
     pair_of(round, pair, nb, p, q);
-    if (t < JP) {
+    if (t < NB) {
         const int lj = (t < JB) ? p * JB + t : q * JB + (t - JB);
         cols[t] = (lj < N) ? colmap[lj] : -1;
     }
-    const C2<T>* wsrc = Wm + (size_t)pair * (JP * JP);
-    for (int e = t; e < JP * JP; e += 256) Ws[e & (JP - 1)][e >> 6] = wsrc[e];
+    const C2<T>* wsrc = Wm + (size_t)pair * (NB * NB);
+    for (int e = t; e < NB * NB; e += 256) Ws[e % NB][e / NB] = wsrc[e];
     __syncthreads();
     const int r0 = blockIdx.y * 64;
-    for (int e = t; e < JP * 64; e += 256) {
+    for (int e = t; e < NB * 64; e += 256) {
         const int row = e & 63, col = e >> 6;
         const int c = cols[col];
         C2<T> v = czero<T>();
@@ -343,25 +363,25 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
         Xt[col][row] = v;
     }
     __syncthreads();
-    A4<T> accR[2][2], accI[2][2];
+    // wave (wm, wn): rows wm*32 .. +32, columns wn*NB/2 .. +NB/2
+    A4<T> accR[2][MB], accI[2][MB];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < MB; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
 #pragma unroll 4
-    for (int kk = 0; kk < JP; kk += 4) {
-        C2<T> a[2], b[2];
+    for (int kk = 0; kk < NB; kk += 4) {
+        C2<T> a[2], b[MB];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            a[s] = Xt[kk + (lane >> 4)][wm * 32 + s * 16 + (lane & 15)];
-            b[s] = Ws[kk + (lane >> 4)][wn * 32 + s * 16 + (lane & 15)];
-        }
+        for (int s = 0; s < 2; ++s) a[s] = Xt[kk + (lane >> 4)][wm * 32 + s * 16 + (lane & 15)];
+#pragma unroll
+        for (int s = 0; s < MB; ++s) b[s] = Ws[kk + (lane >> 4)][wn * (NB / 2) + s * 16 + (lane & 15)];
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
+            for (int bj = 0; bj < MB; ++bj) {
                 accR[bi][bj] = mfma16(a[bi].x, b[bj].x, accR[bi][bj]);
                 accR[bi][bj] = mfma16(-a[bi].y, b[bj].y, accR[bi][bj]);
                 accI[bi][bj] = mfma16(a[bi].x, b[bj].y, accI[bi][bj]);
@@ -372,15 +392,15 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < MB; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = wm * 32 + bi * 16 + acc_row<T>(lane, r);
-                const int col = wn * 32 + bj * 16 + (lane & 15);
+                const int col = wn * (NB / 2) + bj * 16 + (lane & 15);
                 Xt[col][row] = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
             }
     __syncthreads();
-    for (int e = t; e < JP * 64; e += 256) {
+    for (int e = t; e < NB * 64; e += 256) {
         const int row = e & 63, col = e >> 6;
         const int c = cols[col];
         if (c >= 0 && r0 + row < m) X[(size_t)(r0 + row) + (size_t)m * c] = Xt[col][row];
@@ -546,18 +566,20 @@ __global__ void k_copy(const C2<T>* __restrict__ s, C2<T>* __restrict__ d, size_
 }
 
 // ------------------------------------------------------------------- host side
-template <typename T>
-int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, JacobiWork& w,
-                         hipStream_t st) {
+template <typename T, int JB>
+static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int inner_max,
+                      JacobiWork& w, hipStream_t st) {
+    constexpr int NB = 2 * JB;
     int nb = (N + JB - 1) / JB;
     if (nb < 2) nb = 2;
     if (nb & 1) ++nb;
     const int P = nb / 2;
-    if (P > w.max_pairs) return -3;
+    if ((size_t)P * NB * NB > (size_t)w.max_pairs * 4096 || P > 4 * w.max_pairs) return -3;
     int splits = (512 + P - 1) / P;
     if (splits > w.splits) splits = w.splits;
+    constexpr int RB = 4096 / NB;
     int chunk = (m + splits - 1) / splits;
-    chunk = (chunk + 15) / 16 * 16;
+    chunk = (chunk + RB - 1) / RB * RB;
     splits = (m + chunk - 1) / chunk;
     if (splits < 1) splits = 1;
     const double zrel2 = jacobi_zero_rel2<T>();
@@ -565,8 +587,8 @@ int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, Jac
     const dim3 gnorm((N + 3) / 4);
     Profiler& pf = *w.prof;
     const double csz = 2.0 * sizeof(T);
-    const double pair_flops = 8.0 * m * JP * JP;       // one 64x64 complex product over m rows
-    const double pair_bytes = (double)m * JP * csz;
+    const double pair_flops = 8.0 * m * NB * NB;      // one NB x NB complex product over m rows
+    const double pair_bytes = (double)m * NB * csz;
     w.n_splits += 1;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         pf.begin(st);
@@ -576,17 +598,17 @@ int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, Jac
         (void)hipMemsetAsync(&w.info->offmax_bits, 0, sizeof(unsigned long long) + 2 * sizeof(int), st);
         for (int r = 0; r < nb - 1; ++r) {
             pf.begin(st);
-            hipLaunchKernelGGL((k_pair_gram<T>), dim3(P, splits), dim3(256), 0, st, X, m, N,
+            hipLaunchKernelGGL((k_pair_gram<T, JB>), dim3(P, splits), dim3(256), 0, st, X, m, N,
                                w.colmap, nb, r, splits, chunk, (C2<T>*)w.gram_partials);
-            pf.end(st, K_GRAM, P * pair_flops, P * pair_bytes + (double)P * splits * JP * JP * csz);
+            pf.end(st, K_GRAM, P * pair_flops, P * pair_bytes + (double)P * splits * NB * NB * csz);
             pf.begin(st);
-            hipLaunchKernelGGL((k_pair_eig<T>), dim3(P), dim3(256), 0, st,
-                               (const C2<T>*)w.gram_partials, splits, tol, zrel2, fro2, 3,
+            hipLaunchKernelGGL((k_pair_eig<T, JB>), dim3(P), dim3(256), 0, st,
+                               (const C2<T>*)w.gram_partials, splits, tol, zrel2, fro2, inner_max,
                                (C2<T>*)w.w, w.skip, w.info);
-            pf.end(st, K_EIG, 0.0, (double)P * splits * JP * JP * csz);
+            pf.end(st, K_EIG, 0.0, (double)P * splits * NB * NB * csz);
             pf.begin(st);
-            hipLaunchKernelGGL((k_pair_update<T>), dim3(P, (m + 63) / 64), dim3(256), 0, st, X, m, N,
-                               w.colmap, nb, r, (const C2<T>*)w.w, w.skip);
+            hipLaunchKernelGGL((k_pair_update<T, JB>), dim3(P, (m + 63) / 64), dim3(256), 0, st, X, m,
+                               N, w.colmap, nb, r, (const C2<T>*)w.w, w.skip);
             pf.end(st, K_UPDATE, 0.0, 0.0);
         }
         w.n_rounds += nb - 1;
@@ -600,6 +622,9 @@ int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, Jac
         const int rot = w.info_host->rotations;
         w.n_rotations += rot;
         pf.add_work(K_UPDATE, rot * pair_flops, rot * 2.0 * pair_bytes);
+        // each inner step applies a two-sided 2x2 transform to all NB^2 entries of G
+        // (22 real flops per entry) and a column rotation to W (11 per entry)
+        pf.add_work(K_EIG, 33.0 * NB * NB * (double)w.info_host->inner_steps, 0.0);
         if (rot == 0 || off <= tol) {
             pf.begin(st);
             hipLaunchKernelGGL((k_colnorm2<T>), gnorm, dim3(256), 0, st, X, m, N, w.nrm2);
@@ -609,6 +634,13 @@ int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, Jac
         }
     }
     return -1;
+}
+
+template <typename T>
+int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, JacobiWork& w,
+                         hipStream_t st) {
+    if (w.block == 16) return jacobi_run<T, 16>(X, m, N, tol, max_sweeps, w.inner, w, st);
+    return jacobi_run<T, 32>(X, m, N, tol, max_sweeps, w.inner, w, st);
 }
 
 void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,
