@@ -96,9 +96,31 @@ def roofline(prof, prec):
     else:
         bound, peak = "mfma", PEAK[prec]
     return name, {"bound": bound, "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                  "frac": ach / peak, "traffic": None, "kernel": name, "launches": k["launches"],
-                  "avg_us": 1e3 * k["ms"] / launches, "flops_per_launch": k["flops"] / launches,
+                  "frac": ach / peak, "traffic": measured_traffic(name, prec), "kernel": name,
+                  "launches": k["launches"], "avg_us": 1e3 * k["ms"] / launches,
+                  "flops_per_launch": k["flops"] / launches,
+                  "algorithmic_bytes_per_launch": k["bytes"] / launches,
                   "share_of_timed_region": k["ms"] / sum(v["ms"] for v in ks.values())}
+
+
+def measured_traffic(kernel, prec):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
+    when the kernel source changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    for rel, sha in rec.get("source_sha256", {}).items():
+        try:
+            if hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest() != sha:
+                return None
+        except OSError:
+            return None
+    if rec.get("precision") != prec or kernel not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel]["bytes_per_launch"]
 
 
 def cpu_baseline(snap_bytes, pm, site, sup, chi):
@@ -126,6 +148,10 @@ def main():
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="fp32,fp64")
+    ap.add_argument("--save-snapshot", default=None, help="write the in-situ snapshot to this file")
+    ap.add_argument("--load-snapshot", default=None, help="reuse a snapshot written by --save-snapshot")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy a 256 MiB device buffer 4 times first (traffic-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -139,10 +165,26 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
 
+    if args.copy_probe:
+        x = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(4):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
     n, depth, p, chi, seed = 16, 10, 0.01, args.chi, 0
-    log(f"building in-situ snapshot: n={n} depth={depth} p={p} chi={chi}")
-    snap, dims, t_warm = build_snapshot(pm, mi, n, depth, p, chi, seed)
-    log(f"  bond dims {dims} ({t_warm:.1f} s)")
+    if args.load_snapshot:
+        snap = open(args.load_snapshot, "rb").read()
+        dims = [int(v) for v in np.frombuffer(snap, dtype=np.int64, count=n - 1, offset=32)]
+        log(f"loaded snapshot {args.load_snapshot}: bond dims {dims}")
+    else:
+        log(f"building in-situ snapshot: n={n} depth={depth} p={p} chi={chi}")
+        snap, dims, t_warm = build_snapshot(pm, mi, n, depth, p, chi, seed)
+        log(f"  bond dims {dims} ({t_warm:.1f} s)")
+        if args.save_snapshot:
+            with open(args.save_snapshot, "wb") as f:
+                f.write(snap)
     lo, hi = 5, 9
     total = args.warmup + args.steps
     sites = bulk_schedule(lo, hi, total)

@@ -141,11 +141,15 @@ mpo_status run_brickwork(mpo_handle *h, int depth, const double *superops, int n
                          double *S_out, double *Z_out, double *trace_out,
                          double *discarded_out);
 
-/* Host snapshot of the state.  Format: int64 header {magic 0x4d504f31, n,
- * basis, center, chi_0 .. chi_{n-2}} then per site the (chi_l, 4, chi_r)
- * tensor, row-major, complex128.  host_buf may be NULL to query *used.       */
+/* Host snapshot of the state.  Format: int64 header {magic, n, basis, center,
+ * chi_0 .. chi_{n-2}} then per site the (chi_l, 4, chi_r) tensor, row-major,
+ * complex128.  Exports carry magic 0x4d504f32 ("MPO2": sites left of center
+ * are left isometries, sites right of it right isometries).  host_buf may be
+ * NULL to query *used.                                                       */
 mpo_status mpo_export(mpo_handle *h, void *host_buf, size_t cap, size_t *used);
-/* Load a snapshot (any gauge); it is brought into canonical form.            */
+/* Load a snapshot.  Magic 0x4d504f31 ("MPO1"): tensors in any gauge, brought
+ * into canonical form by exact moves.  Magic 0x4d504f32: trusted to be in
+ * mixed canonical form about the stored center, loaded as is.               */
 mpo_status mpo_import(mpo_handle *h, const void *host_buf, size_t len);
 
 /* Noisy Haar gate superoperator, host only: U = Haar unitary from one complex

@@ -52,6 +52,8 @@ struct NumericError { const char* what; };
 struct NoConvError { const char* what; };
 
 constexpr int kMaxSuper = 1024;     // superoperators resident per upload
+constexpr int64_t kMagicAny = 0x4d504f31;        // "MPO1": tensors in any gauge
+constexpr int64_t kMagicCanonical = 0x4d504f32;  // "MPO2": mixed canonical about the stored centre
 constexpr int kSplitsMax = 16;
 constexpr int kMaxSweeps = 60;
 constexpr int kRightChunksMax = 64;
@@ -76,7 +78,7 @@ Layout make_layout(int n, int chi_cap, mpo_precision prec) {
     if (nb < 2) nb = 2;
     if (nb & 1) ++nb;
     L.max_pairs = nb / 2;
-    L.partial_bytes = align256((size_t)L.max_pairs * kSplitsMax * 4096 * csz);
+    L.partial_bytes = align256((size_t)L.max_pairs * kSplitsMax * 4096 * sizeof(double2));
     L.w_bytes = align256((size_t)L.max_pairs * 4096 * csz);
     L.skip_bytes = align256((size_t)4 * L.max_pairs * sizeof(int));   // 16-column blocks: 2x pairs
     L.vecN_bytes = align256((size_t)4 * chi_cap * sizeof(double));
@@ -132,10 +134,13 @@ namespace {
 
 double eps_of(size_t csz) { return csz == 16 ? 2.220446049250313e-16 : 1.1920928955078125e-07; }
 
+// Convergence threshold on |g_ij| / sqrt(g_ii g_jj).  FP64: a few units of
+// the Gram rounding sqrt(m) eps.  FP32: the Gram slabs are summed in FP64, so
+// the off-diagonal noise is about eps32 * sqrt(slab) / sqrt(slabs); 2e-6 keeps
+// the isometries orthonormal well below the 1e-4 entropy target.
 double jacobi_tol(const mpo_handle* h, int m) {
-    const double e = eps_of(h->csz);
-    const double floor = h->csz == 16 ? 1e-14 : 1e-6;
-    return std::fmax(floor, 8.0 * std::sqrt((double)m) * e);
+    if (h->csz == 16) return std::fmax(1e-14, 8.0 * std::sqrt((double)m) * eps_of(h->csz));
+    return 2e-6;
 }
 // singular values at or below this fraction of ||lambda||_2 carry no weight
 // above rounding and are dropped by exact re-gauging moves
@@ -401,7 +406,7 @@ struct Engine {
 
     static void do_export(mpo_handle* h, char* out) {
         int64_t* hdr = (int64_t*)out;
-        hdr[0] = 0x4d504f31;
+        hdr[0] = kMagicCanonical;
         hdr[1] = h->n;
         hdr[2] = h->basis;
         hdr[3] = h->centre;
@@ -446,9 +451,14 @@ struct Engine {
             HIPCHK(hipStreamSynchronize(h->st));
             src += (size_t)cl * 4 * cr * 2;
         }
-        // any gauge: a left-to-right sweep of exact QR-type moves canonicalises
-        h->centre = 0;
-        move_centre(h, h->n - 1);
+        if (hdr[0] == kMagicCanonical) {
+            // written by mpo_export: already in mixed canonical form about hdr[3]
+            h->centre = (int)hdr[3];
+        } else {
+            // any gauge: a left-to-right sweep of exact QR-type moves canonicalises
+            h->centre = 0;
+            move_centre(h, h->n - 1);
+        }
     }
 };
 
@@ -783,7 +793,8 @@ mpo_status mpo_import(mpo_handle* h, const void* host_buf, size_t len) {
     const size_t hdr_bytes = (size_t)(4 + n - 1) * 8;
     if (len < hdr_bytes) return fail(MPO_ERR_ARG, "snapshot too short");
     const int64_t* hdr = (const int64_t*)host_buf;
-    if (hdr[0] != 0x4d504f31) return fail(MPO_ERR_ARG, "bad snapshot magic");
+    if (hdr[0] != kMagicAny && hdr[0] != kMagicCanonical) return fail(MPO_ERR_ARG, "bad snapshot magic");
+    if (hdr[3] < 0 || hdr[3] >= n) return fail(MPO_ERR_ARG, "snapshot centre out of range");
     if (hdr[1] != n) return fail(MPO_ERR_ARG, "snapshot has n = %lld, handle has %d", (long long)hdr[1], n);
     if (hdr[2] != h->basis) return fail(MPO_ERR_ARG, "snapshot basis differs from the handle's");
     size_t need = hdr_bytes;

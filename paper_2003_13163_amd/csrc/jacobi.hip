@@ -95,7 +95,7 @@ template <typename T, int JB>
 __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, int m, int N,
                                                    const int* __restrict__ colmap, int nb,
                                                    int round, int splits, int chunk,
-                                                   C2<T>* __restrict__ partials) {
+                                                   double2* __restrict__ partials) {
     constexpr int NB = 2 * JB, MB = NB / 32;   // MFMA tiles per wave per dimension
     constexpr int RB = 4096 / NB;              // rows per staged slab (LDS tile NB x RB)
     __shared__ C2<T> Xs[RB][NB + 1];
@@ -112,14 +112,22 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
     __syncthreads();
     const int r0 = split * chunk;
     const int r1 = min(m, r0 + chunk);
+    // MFMA accumulation in T within one slab, slab sums accumulated in FP64
     A4<T> accR[MB][MB], accI[MB][MB];
+    d4 sumR[MB][MB], sumI[MB][MB];
 #pragma unroll
     for (int bi = 0; bi < MB; ++bi)
 #pragma unroll
         for (int bj = 0; bj < MB; ++bj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
+            for (int r = 0; r < 4; ++r) { sumR[bi][bj][r] = 0.0; sumI[bi][bj][r] = 0.0; }
     for (int k0 = r0; k0 < r1; k0 += RB) {
+#pragma unroll
+        for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < MB; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
 #pragma unroll
         for (int r = 0; r < (RB * NB) / 256; ++r) {
             const int e = t + 256 * r;
@@ -149,9 +157,18 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
                     accI[bi][bj] = mfma16(-a[bi].y, b[bj].x, accI[bi][bj]);
                 }
         }
+#pragma unroll
+        for (int bi = 0; bi < MB; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < MB; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    sumR[bi][bj][r] += (double)accR[bi][bj][r];
+                    sumI[bi][bj][r] += (double)accI[bi][bj][r];
+                }
         __syncthreads();
     }
-    C2<T>* out = partials + (size_t)(pair * splits + split) * (NB * NB);
+    double2* out = partials + (size_t)(pair * splits + split) * (NB * NB);
 #pragma unroll
     for (int bi = 0; bi < MB; ++bi)
 #pragma unroll
@@ -160,7 +177,7 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
             for (int r = 0; r < 4; ++r) {
                 const int i = wm * (NB / 2) + bi * 16 + acc_row<T>(lane, r);
                 const int j = wn * (NB / 2) + bj * 16 + (lane & 15);
-                out[i + NB * j] = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
+                out[i + NB * j] = make_double2(sumR[bi][bj][r], sumI[bi][bj][r]);
             }
 }
 
@@ -206,7 +223,7 @@ __device__ double block_off(const double2 (*G)[NB + 1], double zthr, double* red
 }
 
 template <typename T, int JB>
-__global__ __launch_bounds__(256) void k_pair_eig(const C2<T>* __restrict__ partials, int splits,
+__global__ __launch_bounds__(256) void k_pair_eig(const double2* __restrict__ partials, int splits,
                                                   double tol, double zrel2,
                                                   const double* __restrict__ fro2, int inner_max,
                                                   C2<T>* __restrict__ Wout, int* __restrict__ skip,
@@ -222,7 +239,7 @@ __global__ __launch_bounds__(256) void k_pair_eig(const C2<T>* __restrict__ part
         const int i = e % NB, j = e / NB;
         double2 s = make_double2(0.0, 0.0);
         for (int sp = 0; sp < splits; ++sp) {
-            const double2 v = to_d2(partials[(size_t)(pair * splits + sp) * (NB * NB) + i + NB * j]);
+            const double2 v = partials[(size_t)(pair * splits + sp) * (NB * NB) + i + NB * j];
             s.x += v.x;
             s.y += v.y;
         }
@@ -599,13 +616,13 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
         for (int r = 0; r < nb - 1; ++r) {
             pf.begin(st);
             hipLaunchKernelGGL((k_pair_gram<T, JB>), dim3(P, splits), dim3(256), 0, st, X, m, N,
-                               w.colmap, nb, r, splits, chunk, (C2<T>*)w.gram_partials);
-            pf.end(st, K_GRAM, P * pair_flops, P * pair_bytes + (double)P * splits * NB * NB * csz);
+                               w.colmap, nb, r, splits, chunk, (double2*)w.gram_partials);
+            pf.end(st, K_GRAM, P * pair_flops, P * pair_bytes + (double)P * splits * NB * NB * 16.0);
             pf.begin(st);
             hipLaunchKernelGGL((k_pair_eig<T, JB>), dim3(P), dim3(256), 0, st,
-                               (const C2<T>*)w.gram_partials, splits, tol, zrel2, fro2, inner_max,
+                               (const double2*)w.gram_partials, splits, tol, zrel2, fro2, inner_max,
                                (C2<T>*)w.w, w.skip, w.info);
-            pf.end(st, K_EIG, 0.0, (double)P * splits * NB * NB * csz);
+            pf.end(st, K_EIG, 0.0, (double)P * splits * NB * NB * 16.0);
             pf.begin(st);
             hipLaunchKernelGGL((k_pair_update<T, JB>), dim3(P, (m + 63) / 64), dim3(256), 0, st, X, m,
                                N, w.colmap, nb, r, (const C2<T>*)w.w, w.skip);
