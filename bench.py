@@ -123,6 +123,35 @@ def measured_traffic(kernel, prec):
     return rec["kernels"][kernel]["bytes_per_launch"]
 
 
+def batch_measurement(pm, mi, torch, count, depth_cap=6, chi_cap=64, streams=16):
+    """Independent circuits of the batched workload (circuit i: n even in 16..96,
+    depth in [n/2, n], p in [0.005, 0.03], chi_max in {64..512}, all from
+    PCG64(i)), with depth and chi_max capped so the run stays short: aggregate
+    updates/s on one stream vs `streams` concurrent streams (mpo_batch_run)."""
+    circuits, sups, ngates = [], [], 0
+    for i in range(count):
+        spec, draws = mi.batch_circuit(i)
+        depth, chi = min(spec.depth, depth_cap), min(spec.chi_max, chi_cap)
+        g = pm.n_schedule_gates(spec.n, depth)
+        circuits.append((spec.n, depth, chi, 1e-12))
+        sups.append(pm.build_superops(draws[:g], spec.p, "pauli"))
+        ngates += g
+    res = {}
+    outs = {}
+    for ns in (1, streams):
+        log(f"batch: {count} circuits, {ngates} gates, {ns} stream(s)")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs[ns] = pm.batch_run(circuits, sups, "fp32", "pauli", n_streams=ns)
+        dt = time.perf_counter() - t0
+        res[ns] = ngates / dt
+    same = all(np.array_equal(a["S"], b["S"]) for a, b in zip(outs[1], outs[streams]))
+    return {"workload": f"{count} circuits of the batched workload (seeds 0..{count - 1}), depth<={depth_cap}, "
+                        f"chi_max<={chi_cap}, FP32-MFMA", "gates": ngates,
+            "sequential_updates_per_s": res[1], f"streams{streams}_updates_per_s": res[streams],
+            "speedup": res[streams] / res[1], "results_identical": bool(same)}
+
+
 def cpu_baseline(snap_bytes, pm, site, sup, chi):
     """Oracle (numpy complex128) on one bulk gate of the same snapshot."""
     from oracle import mpo as omp
@@ -150,6 +179,8 @@ def main():
     ap.add_argument("--precisions", default="fp32,fp64")
     ap.add_argument("--save-snapshot", default=None, help="write the in-situ snapshot to this file")
     ap.add_argument("--load-snapshot", default=None, help="reuse a snapshot written by --save-snapshot")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-circuits", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy a 256 MiB device buffer 4 times first (traffic-counter calibration)")
     args = ap.parse_args()
@@ -225,6 +256,9 @@ def main():
     out["kernels"] = {k: {kk: vv for kk, vv in v["prof"]["kernels"].items() if vv["launches"]}
                       for k, v in res.items()}
     out["svd"] = {k: v["prof"]["svd"] for k, v in res.items()}
+
+    if not args.no_batch:
+        out["batch"] = batch_measurement(pm, mi, torch, args.batch_circuits)
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the first bulk gate of the snapshot")

@@ -161,6 +161,34 @@ mpo_status mpo_import(mpo_handle *h, const void *host_buf, size_t len);
 mpo_status mpo_build_superop(const double *re, const double *im, double p, mpo_basis basis,
                              double *out, double *u_out);
 
+/* Batched evolution of independent circuits (the paper averages over N_s
+ * independent random circuits, Sec. IV.A).  Each circuit is a brickwork as in
+ * run_brickwork, starting from |0..0><0..0|.
+ *   superops_concat: all circuits' superoperators (16x16 complex each),
+ *     circuit c using gates [gate_offset, gate_offset + n_gates(n, depth)).
+ *   results: per circuit at result_offset: S_b after the last time step
+ *     (n-1 values), <Z_i> (n), Tr rho, summed discarded weight, largest bond
+ *     dimension reached (as a double): 2n+2 values.
+ * Work is spread over n_streams caller-owned HIP streams (n_streams >= 1),
+ * one host worker thread per stream; circuits are taken largest first
+ * (n * depth * chi_max^3).  The arena is split into n_streams equal slices,
+ * each of mpo_batch_workspace_bytes(...) / n_streams bytes.  A circuit's
+ * computation does not depend on which stream runs it, so the results equal
+ * those of separate run_brickwork calls.  Synchronises all streams.          */
+typedef struct {
+    int n, depth, chi_max;
+    double cutoff;
+    size_t gate_offset;     /* first superoperator of this circuit            */
+    size_t result_offset;   /* first double of this circuit in results        */
+} mpo_batch_desc;
+mpo_status mpo_batch_workspace_bytes(const mpo_batch_desc *circuits, int count,
+                                     mpo_precision prec, int n_streams, size_t *bytes);
+mpo_status mpo_batch_run(const mpo_batch_desc *circuits, int count,
+                         const double *superops_concat, size_t n_superops,
+                         mpo_precision prec, mpo_basis basis,
+                         void *dev_arena, size_t arena_bytes,
+                         void *const *hip_streams, int n_streams, double *results);
+
 /* Instrumentation: per-kernel-class timing with HIP events recorded on the
  * handle's stream around every launch, plus the algorithmic flop and byte
  * counts of those launches (real flops; complex MAC = 8).  Enabling resets

@@ -87,6 +87,8 @@ def library() -> ctypes.CDLL:
         "mpo_export": [P, P, S, ctypes.POINTER(S)],
         "mpo_import": [P, P, S],
         "mpo_build_superop": [pd, pd, D, I, pd, pd],
+        "mpo_batch_workspace_bytes": [P, I, I, I, ctypes.POINTER(S)],
+        "mpo_batch_run": [P, I, pd, S, I, I, P, S, P, I, pd],
         "mpo_profile_enable": [P, I],
         "mpo_profile_read": [P, ctypes.POINTER(_KernelStat), I, pi, ctypes.POINTER(ctypes.c_longlong)],
         "mpo_last_error": [],
@@ -268,6 +270,55 @@ class Mpo:
         return {"S": S[: rows * (self.n - 1)].reshape(rows, self.n - 1),
                 "Z": Z[: rows * self.n].reshape(rows, self.n), "trace": tr[:rows],
                 "discarded": disc[:g]}
+
+
+class _BatchDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("depth", ctypes.c_int), ("chi_max", ctypes.c_int),
+                ("cutoff", ctypes.c_double), ("gate_offset", ctypes.c_size_t),
+                ("result_offset", ctypes.c_size_t)]
+
+
+def batch_run(circuits, superops, precision="fp32", basis="pauli", n_streams=8, device=None):
+    """Evolve independent circuits concurrently (mpo_batch_run).
+
+    circuits: list of (n, depth, chi_max, cutoff); superops: list of arrays
+    (n_gates(n, depth), 16, 16) per circuit.  Returns one dict per circuit with
+    S (n-1 bond entropies after the last time step), Z, trace, discarded (sum
+    over gates) and max_bond."""
+    import torch
+    lib = library()
+    count = len(circuits)
+    descs = (_BatchDesc * count)()
+    g_off, r_off = 0, 0
+    for i, (n, depth, chi, cut) in enumerate(circuits):
+        g = n_schedule_gates(n, depth)
+        if superops[i].shape[0] != g:
+            raise ValueError(f"circuit {i}: {superops[i].shape[0]} superoperators, {g} expected")
+        descs[i] = _BatchDesc(n, depth, chi, float(cut), g_off, r_off)
+        g_off += g
+        r_off += 2 * n + 2
+    sup = np.ascontiguousarray(np.concatenate([np.asarray(s, dtype=np.complex128).reshape(-1, 16, 16)
+                                               for s in superops]))
+    prec = _PREC[precision]
+    nbytes = ctypes.c_size_t()
+    dptr = ctypes.cast(descs, ctypes.c_void_p)
+    _check(lib.mpo_batch_workspace_bytes(dptr, count, prec, n_streams, ctypes.byref(nbytes)))
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    arena = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
+    handles = (ctypes.c_void_p * n_streams)(*[s.cuda_stream for s in streams])
+    res = np.zeros(max(r_off, 1))
+    torch.cuda.synchronize(dev)
+    _check(lib.mpo_batch_run(dptr, count, _dptr(sup.view(np.float64)), g_off, prec, _BASIS[basis],
+                             ctypes.c_void_p(arena.data_ptr()), nbytes.value,
+                             ctypes.cast(handles, ctypes.c_void_p), n_streams, _dptr(res)))
+    out = []
+    for i, (n, depth, chi, cut) in enumerate(circuits):
+        r = res[descs[i].result_offset: descs[i].result_offset + 2 * n + 2]
+        out.append({"S": r[: n - 1].copy(), "Z": r[n - 1: 2 * n - 1].copy(), "trace": r[2 * n - 1],
+                    "discarded": r[2 * n], "max_bond": int(r[2 * n + 1])})
+    del arena
+    return out
 
 
 def snapshot_to_tensors(data: bytes):

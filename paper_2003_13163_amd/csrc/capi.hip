@@ -498,6 +498,8 @@ bool finite_all(const double* v, size_t n) {
 
 }  // namespace
 
+void mpo_internal_set_error(const char* msg) { g_err = msg ? msg : ""; }
+
 // ==================================================================== C ABI
 extern "C" {
 

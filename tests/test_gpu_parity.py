@@ -286,3 +286,30 @@ def test_deterministic(pm):
         st.close()
     assert np.array_equal(outs[0]["S"], outs[1]["S"])
     assert np.array_equal(outs[0]["Z"], outs[1]["Z"])
+
+
+# ------------------------------------------------------------------- batching
+def test_batch_equals_individual_runs(pm):
+    shapes = [(6, 4, 16), (8, 5, 32), (10, 6, 16), (6, 3, 8), (8, 6, 64), (4, 2, 16), (12, 4, 32)]
+    circuits, sups = [], []
+    for i, (n, depth, chi) in enumerate(shapes):
+        draws = mi.ginibre_draws(n, depth, seed=100 + i)
+        circuits.append((n, depth, chi, 1e-12))
+        sups.append(pm.build_superops(draws, 0.02, "pauli"))
+    say(f"case batch of {len(shapes)} circuits on 3 streams")
+    out = pm.batch_run(circuits, sups, "fp64", "pauli", n_streams=3)
+    for (n, depth, chi, cut), sup, o in zip(circuits, sups, out):
+        st = pm.Mpo(n, chi, "fp64", "pauli")
+        res = st.run_brickwork(depth, sup, chi, cut, record="last")
+        assert np.array_equal(o["S"], res["S"][0])
+        assert np.array_equal(o["Z"], res["Z"][0])
+        assert o["trace"] == res["trace"][0]
+        assert abs(o["discarded"] - res["discarded"].sum()) <= 1e-15 + 1e-12 * res["discarded"].sum()
+        assert o["max_bond"] == max(st.bond_dims()[0])
+        st.close()
+    # one batched circuit against the oracle
+    n, depth, chi, cut = circuits[4]
+    ref = omp.run_brickwork(n, gates.circuit_superops(mi.ginibre_draws(n, depth, seed=104), 0.02, "pauli"),
+                            mi.brickwork_sites(n, depth), chi, cut, "pauli", record_layers={depth - 1})
+    assert np.abs(out[4]["S"] - ref["S"][0]).max() <= 1e-10
+    assert np.abs(out[4]["Z"] - ref["Z"][0]).max() <= 1e-8
