@@ -189,6 +189,30 @@ mpo_status mpo_batch_run(const mpo_batch_desc *circuits, int count,
                          void *dev_arena, size_t arena_bytes,
                          void *const *hip_streams, int n_streams, double *results);
 
+/* Gradient of O = sum_i Tr[Z_i rho_D] (unnormalised, so linear in rho) with
+ * respect to every gate superoperator, with the truncation projectors frozen.
+ * Truncation at gate g keeps the top-k left Schmidt vectors at its bond (App. A);
+ * frozen at the forward point it is the orthogonal projector
+ * P_g = (Phi_g Phi_g^H) (x) 1 onto the kept left vectors, and exact re-gauging
+ * moves are identities, so rho_D = P_G M_G ... P_1 M_1 rho_0 is linear in each
+ * M_g.  Runs the brickwork of run_brickwork (same superops, chi_max, cutoff)
+ * from the handle's current state, recording per time step the state at its
+ * start, every pre-gate centre tensor and the left isometries after its last
+ * gate; then propagates the co-state mu_G = w, lambda_g = P_g mu_g,
+ * mu_{g-1} = M_g^H lambda_g backwards as an MPS (bond <= min(1024, 4 chi_max);
+ * the largest bond reached is written to *costate_max_bond unless NULL).
+ *   O_out: O at the forward point;
+ *   dO_dsuperop: n_gates x 16 x 16 complex, dO/dM_g[row][col] such that
+ *     O = sum_{row,col} M_g[row][col] * dO_dsuperop_g[row][col] for every g;
+ *   dev_work: caller device memory, 256-byte aligned, of at least
+ *     mpo_adjoint_workspace_bytes(n, depth, chi_max, prec) bytes.
+ * The handle ends in the forward's final state.  Synchronises.               */
+mpo_status mpo_adjoint_workspace_bytes(int n, int depth, int chi_max, mpo_precision prec,
+                                       size_t *bytes);
+mpo_status mpo_adjoint_brickwork(mpo_handle *h, int depth, const double *superops, int n_gates,
+                                 int chi_max, double cutoff, void *dev_work, size_t work_bytes,
+                                 double *O_out, double *dO_dsuperop, int *costate_max_bond);
+
 /* Instrumentation: per-kernel-class timing with HIP events recorded on the
  * handle's stream around every launch, plus the algorithmic flop and byte
  * counts of those launches (real flops; complex MAC = 8).  Enabling resets

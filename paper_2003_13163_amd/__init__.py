@@ -89,6 +89,8 @@ def library() -> ctypes.CDLL:
         "mpo_build_superop": [pd, pd, D, I, pd, pd],
         "mpo_batch_workspace_bytes": [P, I, I, I, ctypes.POINTER(S)],
         "mpo_batch_run": [P, I, pd, S, I, I, P, S, P, I, pd],
+        "mpo_adjoint_workspace_bytes": [I, I, I, I, ctypes.POINTER(S)],
+        "mpo_adjoint_brickwork": [P, I, pd, I, I, D, P, S, pd, pd, pi],
         "mpo_profile_enable": [P, I],
         "mpo_profile_read": [P, ctypes.POINTER(_KernelStat), I, pi, ctypes.POINTER(ctypes.c_longlong)],
         "mpo_last_error": [],
@@ -236,6 +238,25 @@ class Mpo:
     def import_state(self, data: bytes):
         buf = ctypes.create_string_buffer(data, len(data))
         _check(library().mpo_import(self._h, buf, len(data)))
+
+    def adjoint_brickwork(self, depth: int, superops, chi_max: int, cutoff: float = 1e-12):
+        """(O, dO/dM of every gate (G,16,16) complex, largest co-state bond) with the
+        truncation projectors frozen; the state advances to the final one."""
+        import torch
+        lib = library()
+        sup = _as_complex_pairs(superops).reshape(-1)
+        g = sup.size // 512
+        nbytes = ctypes.c_size_t()
+        _check(lib.mpo_adjoint_workspace_bytes(self.n, depth, chi_max, self.precision, ctypes.byref(nbytes)))
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=self.arena.device)
+        O = ctypes.c_double()
+        grads = np.zeros(g * 512)
+        comax = ctypes.c_int()
+        _check(lib.mpo_adjoint_brickwork(self._h, depth, _dptr(sup), g, chi_max, float(cutoff),
+                                         ctypes.c_void_p(work.data_ptr()), nbytes.value,
+                                         ctypes.byref(O), _dptr(grads), ctypes.byref(comax)))
+        del work
+        return O.value, grads.view(np.complex128).reshape(g, 16, 16), comax.value
 
     # ------------------------------------------------------------- instrumentation
     def profile(self, on: bool = True):

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -462,6 +463,269 @@ struct Engine {
     }
 };
 
+// ----------------------------------------------------------------- adjoint
+// Frozen-projector gradient of O = sum_i Tr[Z_i rho_D].  With the kept
+// subspace of every truncation frozen, gate g is the linear map
+// rho -> P_g M_g rho, P_g = (Phi_g Phi_g^H) (x) 1 with Phi_g the left isometries
+// of sites 0..s after the gate; moves are exact identities.  The co-state
+// mu_G = w, lambda_g = P_g mu_g, mu_{g-1} = M_g^H lambda_g is carried as an MPS
+// of its own; dO/dM_g = <lambda_g | E_(IJ,KL) rho_{g-1}> is a two-site contraction.
+// In an ascending layer, after the projection at its last gate the co-state's
+// sites left of every earlier gate of the layer already are that gate's frozen
+// isometries, so only one projection (an environment sweep) per layer is
+// needed, and the left overlap of lambda_g with rho_{g-1} is the identity.
+struct AdjLayout {
+    size_t slot_bytes, tape_slots, mu_bytes, env_bytes, y_bytes, t1_bytes, th_bytes, mh_bytes, total;
+    int chi_mu;
+};
+
+AdjLayout adj_layout(int n, int depth, int chi_max, mpo_precision prec, int n_gates) {
+    AdjLayout L{};
+    const size_t csz = prec == MPO_FP64 ? 16 : 8;
+    const size_t cm = (size_t)chi_max;
+    L.chi_mu = std::min(1024, 4 * chi_max);
+    const size_t cu = (size_t)L.chi_mu;
+    L.slot_bytes = align256(4 * cm * cm * csz);
+    L.tape_slots = (size_t)depth * (2 * (size_t)n + (size_t)n / 2 + 1);
+    size_t mu = 0;
+    mpo_workspace_bytes(n, L.chi_mu, prec, &mu);
+    L.mu_bytes = align256(mu);
+    L.env_bytes = align256(cm * cu * csz);
+    L.y_bytes = align256(4 * std::max(cm, cu) * std::max(cm, cu) * csz);
+    L.t1_bytes = align256(4 * cm * cu * csz);
+    L.th_bytes = align256(16 * cm * cu * csz);
+    L.mh_bytes = align256(((size_t)n_gates + 1) * 256 * csz);
+    L.total = L.slot_bytes * L.tape_slots + L.mu_bytes + 4 * L.env_bytes + L.y_bytes + L.t1_bytes +
+              2 * L.th_bytes + L.mh_bytes + align256(256 * sizeof(double2));
+    return L;
+}
+
+template <typename T>
+struct Adjoint {
+    using C = C2<T>;
+    using E = Engine<T>;
+    struct Tape {
+        int first = 0, last = 0;
+        std::vector<int> pre_dims;        // bonds 0..n-2 at the start of the layer
+        std::vector<C*> pre;              // n site tensors (centre at `first`)
+        std::vector<C*> cen;              // pre-gate centre tensor of every gate
+        std::vector<int> cen_l, cen_r;    // its bond dimensions
+        std::vector<C*> post;             // sites 0..last after the last gate
+        std::vector<int> post_dims;       // bonds 0..last
+    };
+
+    static void copy_site(mpo_handle* h, int s, C* dst, int cl, int cr) {
+        launch_copy<T>(E::site(h, s), dst, (size_t)cl * 4 * cr, h->st);
+    }
+
+    // S_q from S_{q+1}: S_q[c, c'] = sum conj(lam[c', I, d']) rho[c, I, d] S_{q+1}[d, d']
+    static void right_step(mpo_handle* h, const C* rho, int rl, int rr, const C* lam, int ll, int lr,
+                           const C* Sin, C* Sout, C* Y) {
+        launch_cgemm<T>(0, 0, 4 * rl, lr, rr, rho, 4 * rl, Sin, rr, Y, 4 * rl, h->st);
+        launch_cgemm<T>(0, 1, rl, ll, 4 * lr, Y, rl, lam, ll, Sout, rl, h->st);
+    }
+    // E_{q+1}[a', b'] = sum conj(phi[a, I, a']) E_q[a, b] mu[b, I, b']
+    static void left_step(mpo_handle* h, const C* phi, int pl, int pr, const C* mu, int ml, int mr,
+                          const C* Ein, C* Eout, C* Y) {
+        launch_cgemm<T>(0, 0, pl, 4 * mr, ml, Ein, pl, mu, ml, Y, pl, h->st);
+        launch_cgemm<T>(1, 0, pr, mr, 4 * pl, phi, 4 * pl, Y, 4 * pl, Eout, pr, h->st);
+    }
+
+    static void set_one(mpo_handle* h, C* dst) {
+        C one;
+        one.x = T(1);
+        one.y = T(0);
+        HIPCHK(hipMemcpyAsync(dst, &one, sizeof(C), hipMemcpyHostToDevice, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+    }
+
+    // mu <- w = sum_i (Z at i, identity elsewhere) as a bond-2 MPS
+    static void init_observable(mpo_handle* mu) {
+        const int n = mu->n;
+        double2 t[4], z[4];
+        dual_vector(mu->basis, 0, t);
+        dual_vector(mu->basis, 3, z);
+        for (int b = 0; b < n - 1; ++b) mu->dims[b] = 2;
+        for (int s = 0; s < n; ++s) {
+            const int cl = s == 0 ? 1 : 2, cr = s == n - 1 ? 1 : 2;
+            std::vector<C> buf((size_t)cl * 4 * cr);
+            for (auto& v : buf) { v.x = T(0); v.y = T(0); }
+            auto put = [&](int a, int I, int c, double2 v) {
+                C& e = buf[(size_t)a + (size_t)cl * (I + 4 * c)];
+                e.x = (T)v.x;
+                e.y = (T)(-v.y);   // w = conj(dual vector): <w|rho> = sum dual * rho
+            };
+            for (int I = 0; I < 4; ++I) {
+                if (s == 0 && n > 1) { put(0, I, 0, t[I]); put(0, I, 1, z[I]); }
+                else if (s == n - 1) { put(0, I, 0, z[I]); put(1, I, 0, t[I]); }
+                else { put(0, I, 0, t[I]); put(0, I, 1, z[I]); put(1, I, 1, t[I]); }
+            }
+            HIPCHK(hipMemcpyAsync(E::site(mu, s), buf.data(), sizeof(C) * buf.size(), hipMemcpyHostToDevice, mu->st));
+            HIPCHK(hipStreamSynchronize(mu->st));
+        }
+        mu->centre = 0;
+    }
+
+    static void run(mpo_handle* h, int depth, const double* superops, int n_gates, int chi_max,
+                    double cutoff, char* work, const AdjLayout& L, double* O_out, double* grads,
+                    int* costate_max_bond) {
+        const int n = h->n;
+        // ---- carve the workspace
+        char* p = work;
+        char* tape_base = p;
+        p += L.slot_bytes * L.tape_slots;
+        char* mu_arena = p; p += L.mu_bytes;
+        C* env[4];
+        for (int k = 0; k < 4; ++k) { env[k] = (C*)p; p += L.env_bytes; }
+        C* Y = (C*)p; p += L.y_bytes;
+        C* T1 = (C*)p; p += L.t1_bytes;
+        C* THL = (C*)p; p += L.th_bytes;
+        C* TH = (C*)p; p += L.th_bytes;
+        C* MH = (C*)p; p += L.mh_bytes;
+        double2* gdev = (double2*)p;
+        size_t next_slot = 0;
+        auto take = [&]() -> C* {
+            if (next_slot >= L.tape_slots) throw HipError{hipErrorOutOfMemory, "adjoint tape"};
+            return (C*)(tape_base + L.slot_bytes * next_slot++);
+        };
+        // ---- forward with tape
+        std::vector<Tape> tape(depth);
+        int g = 0, resident0 = 0, resident = 0;
+        for (int t = 0; t < depth; ++t) {
+            Tape& tp = tape[t];
+            tp.first = (t % 2 == 0) ? 0 : 1;
+            E::move_centre(h, tp.first);
+            tp.pre_dims = h->dims;
+            for (int s = 0; s < n; ++s) {
+                tp.pre.push_back(take());
+                copy_site(h, s, tp.pre.back(), h->chiL(s), h->chiR(s));
+            }
+            for (int s = tp.first; s + 1 < n; s += 2) {
+                if (g >= resident0 + resident) {
+                    resident0 = g;
+                    resident = std::min(kMaxSuper, n_gates - g);
+                    HIPCHK(hipStreamSynchronize(h->st));
+                    E::upload_super(h, superops + (size_t)g * 512, resident);
+                }
+                E::move_centre(h, s);
+                tp.cen.push_back(take());
+                tp.cen_l.push_back(h->chiL(s));
+                tp.cen_r.push_back(h->dims[s]);
+                copy_site(h, s, tp.cen.back(), h->chiL(s), h->dims[s]);
+                E::apply(h, s, (const C*)h->Mdev + (size_t)(g - resident0) * 256, chi_max, cutoff);
+                tp.last = s;
+                ++g;
+            }
+            for (int s = 0; s <= tp.last; ++s) {
+                tp.post.push_back(take());
+                copy_site(h, s, tp.post.back(), h->chiL(s), h->chiR(s));
+            }
+            tp.post_dims.assign(h->dims.begin(), h->dims.begin() + tp.last + 1);
+        }
+        HIPCHK(hipGetLastError());
+        {
+            std::vector<double> z(n);
+            double tr = 0.0;
+            E::observables(h, z.data(), &tr, nullptr);
+            double O = 0.0;
+            for (int i = 0; i < n; ++i) O += z[i] * tr;
+            *O_out = O;
+        }
+        // ---- co-state and adjoint superoperators
+        mpo_handle* mu = nullptr;
+        mpo_status cst = mpo_create(n, L.chi_mu, h->prec, h->basis, mu_arena, L.mu_bytes, h->st, &mu);
+        if (cst != MPO_OK) throw HipError{hipErrorOutOfMemory, "co-state handle"};
+        std::unique_ptr<mpo_handle, void (*)(mpo_handle*)> mu_guard(mu, mpo_destroy);
+        init_observable(mu);
+        {
+            std::vector<T> mh((size_t)n_gates * 512 + 512);
+            for (int q = 0; q < n_gates; ++q)
+                for (int r = 0; r < 16; ++r)
+                    for (int c = 0; c < 16; ++c) {   // (M^H)[r][c] = conj(M[c][r])
+                        mh[(size_t)q * 512 + 2 * (16 * r + c)] = (T)superops[(size_t)q * 512 + 2 * (16 * c + r)];
+                        mh[(size_t)q * 512 + 2 * (16 * r + c) + 1] = (T)(-superops[(size_t)q * 512 + 2 * (16 * c + r) + 1]);
+                    }
+            for (int r = 0; r < 16; ++r) mh[(size_t)n_gates * 512 + 2 * (16 * r + r)] = T(1);
+            HIPCHK(hipMemcpyAsync(MH, mh.data(), sizeof(T) * mh.size(), hipMemcpyHostToDevice, h->st));
+            HIPCHK(hipStreamSynchronize(h->st));
+        }
+        const C* Id = MH + (size_t)n_gates * 256;
+        int co_max = 2;
+        // ---- backward
+        g = n_gates;
+        for (int t = depth - 1; t >= 0; --t) {
+            Tape& tp = tape[t];
+            const int m_gates = (int)tp.cen.size();
+            const int sm = tp.last;
+            auto pre_l = [&](int s) { return s == 0 ? 1 : tp.pre_dims[s - 1]; };
+            auto pre_r = [&](int s) { return s == n - 1 ? 1 : tp.pre_dims[s]; };
+            auto post_l = [&](int s) { return s == 0 ? 1 : tp.post_dims[s - 1]; };
+            // (1) projection at the layer's last gate: sites 0..sm <- Phi, E into site sm+1
+            C* Ea = env[0];
+            C* Eb = env[1];
+            set_one(h, Ea);
+            for (int q = 0; q <= sm; ++q) {
+                left_step(h, tp.post[q], post_l(q), tp.post_dims[q], E::site(mu, q), mu->chiL(q),
+                          mu->chiR(q), Ea, Eb, Y);
+                std::swap(Ea, Eb);
+            }
+            {
+                const int k = tp.post_dims[sm], ml = mu->chiL(sm + 1), mr = mu->chiR(sm + 1);
+                const int sl = mu->take_spare();
+                launch_cgemm<T>(0, 0, k, 4 * mr, ml, Ea, k, E::site(mu, sm + 1), ml, (C*)mu->slot[sl], k, h->st);
+                mu->give_spare(mu->site_slot[sm + 1]);
+                mu->site_slot[sm + 1] = sl;
+                for (int q = 0; q <= sm; ++q)
+                    launch_copy<T>(tp.post[q], E::site(mu, q), (size_t)post_l(q) * 4 * tp.post_dims[q], h->st);
+                for (int b = 0; b <= sm; ++b) mu->dims[b] = tp.post_dims[b];
+            }
+            // (2) right environment of the last gate: sites >= sm+2
+            C* Sa = env[2];
+            C* Sb = env[3];
+            set_one(h, Sa);
+            for (int q = n - 1; q >= sm + 2; --q) {
+                right_step(h, tp.pre[q], pre_l(q), pre_r(q), E::site(mu, q), mu->chiL(q), mu->chiR(q), Sa, Sb, Y);
+                std::swap(Sa, Sb);
+            }
+            // (3) gates of the layer, last to first
+            for (int j = m_gates - 1; j >= 0; --j) {
+                --g;
+                const int s = tp.first + 2 * j;
+                const int ca = mu->chiL(s), cb = mu->dims[s], cc = mu->chiR(s + 1);
+                if (ca != tp.cen_l[j]) throw HipError{hipErrorInvalidValue, "adjoint bond mismatch"};
+                // theta_lambda and Theta = theta_rho contracted with the right environment
+                launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1), Id, THL, nullptr, h->st);
+                const int rs = tp.cen_r[j], rr = pre_r(s + 1);
+                launch_cgemm<T>(0, 0, 4 * rs, cc, rr, tp.pre[s + 1], 4 * rs, Sa, rr, T1, 4 * rs, h->st);
+                launch_cgemm<T>(0, 0, 4 * ca, 4 * cc, rs, tp.cen[j], 4 * ca, T1, rs, TH, 4 * ca, h->st);
+                launch_local_grad<T>(THL, TH, ca, cc, gdev, h->st);
+                HIPCHK(hipMemcpyAsync(grads + (size_t)g * 512, gdev, 256 * sizeof(double2), hipMemcpyDeviceToHost, h->st));
+                // mu <- M^H lambda on (s, s+1), exact split
+                const int m = 4 * ca, N = 4 * cc;
+                launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1), MH + (size_t)g * 256,
+                                        (C*)mu->X, (C*)mu->X2, h->st);
+                HIPCHK(hipGetLastError());
+                DevInfo inf = E::split(mu, m, N, L.chi_mu, regauge_cut(mu));
+                const int r = inf.kept;
+                co_max = std::max(co_max, r);
+                launch_gather_cols<T>((C*)mu->X, m, mu->jw.colmap, mu->jw.sig2, r, E::site(mu, s), m, h->st);
+                launch_cgemm<T>(1, 0, r, N, m, E::site(mu, s), m, (C*)mu->X2, m, E::site(mu, s + 1), r, h->st);
+                mu->dims[s] = r;
+                // right environment for the previous gate of the layer: sites >= s
+                if (j > 0) {
+                    right_step(h, tp.pre[s + 1], pre_l(s + 1), pre_r(s + 1), E::site(mu, s + 1), r, cc, Sa, Sb, Y);
+                    std::swap(Sa, Sb);
+                    right_step(h, tp.pre[s], pre_l(s), pre_r(s), E::site(mu, s), mu->chiL(s), r, Sa, Sb, Y);
+                    std::swap(Sa, Sb);
+                }
+                HIPCHK(hipGetLastError());
+            }
+        }
+        HIPCHK(hipStreamSynchronize(h->st));
+        if (costate_max_bond) *costate_max_bond = co_max;
+    }
+};
+
 template <typename F>
 mpo_status guarded(mpo_handle* h, F&& f) {
     try {
@@ -777,6 +1041,41 @@ mpo_status mpo_profile_read(mpo_handle* h, mpo_kernel_stat* out, int cap, int* c
         svd_counters[3] = h->jw.n_rotations;
     }
     return MPO_OK;
+}
+
+mpo_status mpo_adjoint_workspace_bytes(int n, int depth, int chi_max, mpo_precision prec, size_t* bytes) {
+    if (!bytes) return fail(MPO_ERR_ARG, "bytes is NULL");
+    size_t dummy = 0;
+    mpo_status st = mpo_workspace_bytes(n, std::max(1, std::min(1024, 4 * chi_max)), prec, &dummy);
+    if (st != MPO_OK) return st;
+    if (depth < 1 || chi_max < 1 || chi_max > 1024) return fail(MPO_ERR_ARG, "depth >= 1 and 1 <= chi_max <= 1024 required");
+    const int g = ((depth + 1) / 2) * (n / 2) + (depth / 2) * (n / 2 - 1);
+    *bytes = adj_layout(n, depth, chi_max, prec, g).total;
+    return MPO_OK;
+}
+
+mpo_status mpo_adjoint_brickwork(mpo_handle* h, int depth, const double* superops, int n_gates,
+                                 int chi_max, double cutoff, void* dev_work, size_t work_bytes,
+                                 double* O_out, double* dO_dsuperop, int* costate_max_bond) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    const int n = h->n;
+    if (depth < 1) return fail(MPO_ERR_ARG, "depth must be >= 1");
+    const long expect = (long)((depth + 1) / 2) * (n / 2) + (long)(depth / 2) * (n / 2 - 1);
+    if (n_gates != expect)
+        return fail(MPO_ERR_ARG, "n_gates = %d but a depth-%d brickwork on %d qubits has %ld", n_gates, depth, n, expect);
+    if (!superops || !O_out || !dO_dsuperop || !dev_work) return fail(MPO_ERR_ARG, "null argument");
+    if (((uintptr_t)dev_work) & 255) return fail(MPO_ERR_ARG, "dev_work must be 256-byte aligned");
+    if (chi_max < 1 || chi_max > h->chi_cap) return fail(MPO_ERR_ARG, "chi_max %d out of [1, %d]", chi_max, h->chi_cap);
+    if (!(cutoff >= 0.0) || !std::isfinite(cutoff)) return fail(MPO_ERR_ARG, "cutoff must be finite and >= 0");
+    if (!finite_all(superops, (size_t)n_gates * 512)) return fail(MPO_ERR_ARG, "non-finite superoperator entry");
+    const AdjLayout L = adj_layout(n, depth, chi_max, h->prec, n_gates);
+    if (work_bytes < L.total) return fail(MPO_ERR_ARENA, "adjoint workspace has %zu bytes, %zu needed", work_bytes, L.total);
+    return guarded(h, [&] {
+        DISPATCH(h, Adjoint<typename E::C::value_type>::run(h, depth, superops, n_gates, chi_max, cutoff,
+                                                           (char*)dev_work, L, O_out, dO_dsuperop,
+                                                           costate_max_bond));
+    });
 }
 
 mpo_status mpo_export(mpo_handle* h, void* host_buf, size_t cap, size_t* used) {

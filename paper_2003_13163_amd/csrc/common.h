@@ -138,6 +138,10 @@ void launch_transfer_left(const C2<T>* A, int chiL, int chiR, const double2* env
 template <typename T>
 void launch_transfer_right(const C2<T>* A, int chiL, int chiR, const double2* env_in,
                            const double2* v, double2* env_out, double2* scratch, hipStream_t st);
+// out[4I+J][4K+L] = sum_{a,c} conj(X[(I,a),(J,c)]) Y[(K,a),(L,c)] (two-site blocks)
+template <typename T>
+void launch_local_grad(const C2<T>* X, const C2<T>* Y, int chiA, int chiC, double2* out,
+                       hipStream_t st);
 // out[slot] = sum_a x[a] * y[a]
 void launch_dot(const double2* x, const double2* y, int len, double2* out, hipStream_t st);
 }  // namespace mpo

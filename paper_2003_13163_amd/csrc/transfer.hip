@@ -90,6 +90,44 @@ __global__ __launch_bounds__(256) void k_dot(const double2* __restrict__ x,
     if (t == 0) *out = red[0];
 }
 
+// Local gradient of a bilinear form: out[4I+J][4K+L] =
+//   sum_{a,c} conj(X[(I,a),(J,c)]) Y[(K,a),(L,c)]
+// for two (4 chiA) x (4 chiC) column-major two-site blocks (row a + chiA*I,
+// column J + 4c).  One work-group per output entry, FP64 accumulation.
+template <typename T>
+__global__ __launch_bounds__(256) void k_local_grad(const C2<T>* __restrict__ X,
+                                                    const C2<T>* __restrict__ Y, int chiA,
+                                                    int chiC, double2* __restrict__ out) {
+    __shared__ double2 red[256];
+    const int o = blockIdx.x, t = threadIdx.x;
+    const int I = o >> 6, J = (o >> 4) & 3, K = (o >> 2) & 3, L = o & 3;
+    const size_t ld = 4 * (size_t)chiA;
+    double sr = 0.0, si = 0.0;
+    const int total = chiA * chiC;
+    for (int e = t; e < total; e += 256) {
+        const int a = e % chiA, c = e / chiA;
+        const double2 x = to_d2(X[(size_t)(a + chiA * I) + ld * (J + 4 * c)]);
+        const double2 y = to_d2(Y[(size_t)(a + chiA * K) + ld * (L + 4 * c)]);
+        sr += x.x * y.x + x.y * y.y;
+        si += x.x * y.y - x.y * y.x;
+    }
+    red[t] = make_double2(sr, si);
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) { red[t].x += red[t + s].x; red[t].y += red[t + s].y; }
+        __syncthreads();
+    }
+    if (t == 0) out[(4 * I + J) * 16 + (4 * K + L)] = red[0];
+}
+
+template <typename T>
+void launch_local_grad(const C2<T>* X, const C2<T>* Y, int chiA, int chiC, double2* out,
+                       hipStream_t st) {
+    hipLaunchKernelGGL((k_local_grad<T>), dim3(256), dim3(256), 0, st, X, Y, chiA, chiC, out);
+}
+template void launch_local_grad<double>(const double2*, const double2*, int, int, double2*, hipStream_t);
+template void launch_local_grad<float>(const float2*, const float2*, int, int, double2*, hipStream_t);
+
 template <typename T>
 void launch_transfer_left(const C2<T>* A, int chiL, int chiR, const double2* env_in,
                           const double2* v, double2* env_out, hipStream_t st) {

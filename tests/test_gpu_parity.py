@@ -313,3 +313,62 @@ def test_batch_equals_individual_runs(pm):
                             mi.brickwork_sites(n, depth), chi, cut, "pauli", record_layers={depth - 1})
     assert np.abs(out[4]["S"] - ref["S"][0]).max() <= 1e-10
     assert np.abs(out[4]["Z"] - ref["Z"][0]).max() <= 1e-8
+
+
+# -------------------------------------------------------------------- adjoint
+@pytest.mark.parametrize("basis,chi", [("pauli", 5), ("computational", 6), ("pauli", 64)])
+def test_adjoint_vs_oracle_dense(pm, basis, chi):
+    from oracle import adjoint as oadj
+    n, depth, p = 6, 4, 0.03
+    say(f"case adjoint n={n} depth={depth} chi={chi} basis={basis}")
+    draws = mi.ginibre_draws(n, depth, seed=21)
+    sup = gates.circuit_superops(draws, p, basis)
+    layers = mi.brickwork_sites(n, depth)
+    sites, phis, _ = oadj.record_forward(n, sup, layers, chi, 1e-12, basis)
+    O_ref, g_ref = oadj.frozen_gradient(n, sup, sites, phis, basis)
+    st = pm.Mpo(n, chi, "fp64", basis)
+    O, grads, comax = st.adjoint_brickwork(depth, sup, chi, 1e-12)
+    st.close()
+    err = np.abs(grads - g_ref).max() / max(1.0, np.abs(g_ref).max())
+    say(f"  O {O:.12f} vs {O_ref.real:.12f}  max grad err {err:.2e}  co-state bond {comax}")
+    assert abs(O - O_ref.real) <= 1e-11 * max(1.0, abs(O_ref))
+    assert err <= 1e-10
+
+
+def test_adjoint_euler_identity_larger(pm):
+    n, depth, p, chi = 12, 6, 0.01, 24
+    say(f"case adjoint Euler identity n={n} depth={depth} chi={chi}")
+    draws = mi.ginibre_draws(n, depth, seed=5)
+    sup = pm.build_superops(draws, p, "pauli")
+    st = pm.Mpo(n, chi, "fp64", "pauli")
+    O, grads, comax = st.adjoint_brickwork(depth, sup, chi, 1e-12)
+    st.close()
+    euler = np.einsum("gij,gij->g", sup, grads)
+    dev = np.abs(euler - O).max() / abs(O)
+    say(f"  O {O:.10f}  max |sum M dO/dM - O| / |O| = {dev:.2e}  co-state bond {comax}")
+    assert dev <= 1e-10
+    assert np.abs(grads.imag).max() <= 1e-10 * np.abs(grads).max()
+
+
+def test_autograd_dO_dp(pm):
+    import torch
+    from oracle import adjoint as oadj
+    from paper_2003_13163_amd.autograd import (BrickworkObservable, noisy_gate_superops_pauli,
+                                               unitary_ptms)
+    n, depth, p0, chi = 6, 4, 0.05, 8
+    draws = mi.ginibre_draws(n, depth, seed=11)
+    p = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    sup = noisy_gate_superops_pauli(unitary_ptms(draws), p)
+    O = BrickworkObservable.apply(sup, n, depth, chi, 1e-12, "fp64", "pauli")
+    O.backward()
+    # oracle: chain rule through dM/dp with its own frozen gradient
+    supc = gates.circuit_superops(draws, p0, "pauli")
+    sites, phis, _ = oadj.record_forward(n, supc, mi.brickwork_sites(n, depth), chi, 1e-12)
+    O_ref, g_ref = oadj.frozen_gradient(n, supc, sites, phis)
+    us = gates.circuit_unitaries(draws)
+    dsn = gates.depolarizing_superop(1.0) - gates.depolarizing_superop(0.0)
+    dp_ref = sum(np.sum(g_ref[g] * gates.to_pauli_basis(dsn @ gates.unitary_superop(us[g])))
+                 for g in range(len(sites))).real
+    say(f"  dO/dp {p.grad.item():.12f} vs oracle {dp_ref:.12f}")
+    assert abs(O.item() - O_ref.real) <= 1e-11
+    assert abs(p.grad.item() - dp_ref) <= 1e-9 * max(1.0, abs(dp_ref))
