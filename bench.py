@@ -152,6 +152,36 @@ def batch_measurement(pm, mi, torch, count, depth_cap=6, chi_cap=64, streams=16)
             "speedup": res[streams] / res[1], "results_identical": bool(same)}
 
 
+def adjoint_measurement(pm, mi, torch, n=32, depth=24, p=0.01, chi=256):
+    """Frozen-projector gradient of O = sum_i Tr[Z_i rho_D] for n = 32, depth 24,
+    p = 0.01, chi_max = 256 (seed 0): forward and backward times, the Euler
+    identity sum M_g dO/dM_g = O over every gate, and dO/dp by the chain rule
+    through M_g = diag(1, 1-16p/15, ...) S_U in the Pauli basis."""
+    draws = mi.ginibre_draws(n, depth, seed=0)
+    sup = pm.build_superops(draws, p, "pauli")
+    log(f"adjoint: n={n} depth={depth} p={p} chi={chi} ({len(sup)} gates)")
+    st = pm.Mpo(n, chi, "fp64", "pauli")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.run_brickwork(depth, sup, chi, 1e-12, record=None)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    st.close()
+    st = pm.Mpo(n, chi, "fp64", "pauli")
+    t0 = time.perf_counter()
+    O, grads, comax = st.adjoint_brickwork(depth, sup, chi, 1e-12)
+    t_adj = time.perf_counter() - t0
+    st.close()
+    euler = np.einsum("gij,gij->g", sup, grads)
+    su = pm.build_superops(draws, 0.0, "pauli")
+    dmdp = np.concatenate([[0.0], np.full(15, -16.0 / 15.0)])[None, :, None] * su
+    dO_dp = float(np.einsum("gij,gij->", grads, dmdp).real)
+    return {"workload": f"n={n}, depth {depth}, p={p}, chi_max={chi}, seed 0, FP64, O = sum_i Tr[Z_i rho_D]",
+            "gates": int(len(sup)), "forward_seconds": t_fwd, "forward_plus_adjoint_seconds": t_adj,
+            "backward_seconds": t_adj - t_fwd, "O": O, "dO_dp": dO_dp,
+            "euler_max_rel_dev": float(np.abs(euler - O).max() / abs(O)), "costate_max_bond": comax}
+
+
 def cpu_baseline(snap_bytes, pm, site, sup, chi):
     """Oracle (numpy complex128) on one bulk gate of the same snapshot."""
     from oracle import mpo as omp
@@ -180,6 +210,7 @@ def main():
     ap.add_argument("--save-snapshot", default=None, help="write the in-situ snapshot to this file")
     ap.add_argument("--load-snapshot", default=None, help="reuse a snapshot written by --save-snapshot")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batch-circuits", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy a 256 MiB device buffer 4 times first (traffic-counter calibration)")
@@ -259,6 +290,8 @@ def main():
 
     if not args.no_batch:
         out["batch"] = batch_measurement(pm, mi, torch, args.batch_circuits)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_measurement(pm, mi, torch)
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the first bulk gate of the snapshot")

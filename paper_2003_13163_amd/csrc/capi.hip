@@ -700,16 +700,30 @@ struct Adjoint {
                 launch_cgemm<T>(0, 0, 4 * ca, 4 * cc, rs, tp.cen[j], 4 * ca, T1, rs, TH, 4 * ca, h->st);
                 launch_local_grad<T>(THL, TH, ca, cc, gdev, h->st);
                 HIPCHK(hipMemcpyAsync(grads + (size_t)g * 512, gdev, 256 * sizeof(double2), hipMemcpyDeviceToHost, h->st));
-                // mu <- M^H lambda on (s, s+1), exact split
+                // mu <- M^H lambda on (s, s+1).  The co-state needs no canonical
+                // form, so when the bond fits it is split exactly as I * theta:
+                // site s the identity on (I, a), site s+1 theta itself (bond 4 ca,
+                // the generic rank).  Otherwise an SVD split capped at chi_mu.
                 const int m = 4 * ca, N = 4 * cc;
-                launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1), MH + (size_t)g * 256,
-                                        (C*)mu->X, (C*)mu->X2, h->st);
-                HIPCHK(hipGetLastError());
-                DevInfo inf = E::split(mu, m, N, L.chi_mu, regauge_cut(mu));
-                const int r = inf.kept;
+                int r;
+                if (m <= L.chi_mu) {
+                    const int sl = mu->take_spare();
+                    launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1),
+                                            MH + (size_t)g * 256, (C*)mu->slot[sl], nullptr, h->st);
+                    launch_identity_site<T>(E::site(mu, s), ca, h->st);
+                    mu->give_spare(mu->site_slot[s + 1]);
+                    mu->site_slot[s + 1] = sl;
+                    r = m;
+                } else {
+                    launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1),
+                                            MH + (size_t)g * 256, (C*)mu->X, (C*)mu->X2, h->st);
+                    HIPCHK(hipGetLastError());
+                    DevInfo inf = E::split(mu, m, N, L.chi_mu, regauge_cut(mu));
+                    r = inf.kept;
+                    launch_gather_cols<T>((C*)mu->X, m, mu->jw.colmap, mu->jw.sig2, r, E::site(mu, s), m, h->st);
+                    launch_cgemm<T>(1, 0, r, N, m, E::site(mu, s), m, (C*)mu->X2, m, E::site(mu, s + 1), r, h->st);
+                }
                 co_max = std::max(co_max, r);
-                launch_gather_cols<T>((C*)mu->X, m, mu->jw.colmap, mu->jw.sig2, r, E::site(mu, s), m, h->st);
-                launch_cgemm<T>(1, 0, r, N, m, E::site(mu, s), m, (C*)mu->X2, m, E::site(mu, s + 1), r, h->st);
                 mu->dims[s] = r;
                 // right environment for the previous gate of the layer: sites >= s
                 if (j > 0) {

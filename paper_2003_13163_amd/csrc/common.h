@@ -138,6 +138,9 @@ void launch_transfer_left(const C2<T>* A, int chiL, int chiR, const double2* env
 template <typename T>
 void launch_transfer_right(const C2<T>* A, int chiL, int chiR, const double2* env_in,
                            const double2* v, double2* env_out, double2* scratch, hipStream_t st);
+// A[a, I, b] = [b == a + chiA*I]: the (chiA, 4, 4 chiA) identity site tensor
+template <typename T>
+void launch_identity_site(C2<T>* A, int chiA, hipStream_t st);
 // out[4I+J][4K+L] = sum_{a,c} conj(X[(I,a),(J,c)]) Y[(K,a),(L,c)] (two-site blocks)
 template <typename T>
 void launch_local_grad(const C2<T>* X, const C2<T>* Y, int chiA, int chiC, double2* out,

@@ -120,6 +120,24 @@ __global__ __launch_bounds__(256) void k_local_grad(const C2<T>* __restrict__ X,
     if (t == 0) out[(4 * I + J) * 16 + (4 * K + L)] = red[0];
 }
 
+// A[a, I, b] = [b == a + chiA*I] for a (chiA, 4, 4 chiA) site tensor.
+template <typename T>
+__global__ void k_identity_site(C2<T>* __restrict__ A, int chiA) {
+    const size_t total = 16 * (size_t)chiA * chiA;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const size_t a_I = e % (4 * (size_t)chiA), b = e / (4 * (size_t)chiA);   // a + chiA*I, b
+    A[e] = cmake<T>(T(a_I == b ? 1 : 0), T(0));
+}
+
+template <typename T>
+void launch_identity_site(C2<T>* A, int chiA, hipStream_t st) {
+    const size_t total = 16 * (size_t)chiA * chiA;
+    hipLaunchKernelGGL((k_identity_site<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A, chiA);
+}
+template void launch_identity_site<double>(double2*, int, hipStream_t);
+template void launch_identity_site<float>(float2*, int, hipStream_t);
+
 template <typename T>
 void launch_local_grad(const C2<T>* X, const C2<T>* Y, int chiA, int chiC, double2* out,
                        hipStream_t st) {
