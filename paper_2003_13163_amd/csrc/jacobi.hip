@@ -89,19 +89,23 @@ __global__ __launch_bounds__(1024) void k_sort_desc(const double* __restrict__ n
 
 // ------------------------------------------------------------- pair Gram
 // partials[(pair*splits + split)*NB*NB + i + NB*j] = sum_rows conj(x_i) x_j over
-// this split's row range, for the NB = 2*JB columns of the pair.  Four waves in
-// a 2x2 layout, each owning (NB/2) x (NB/2) of the Gram tile.
+// this split's row range, for the NB = 2*JB columns of the pair, in FP64.  The
+// Gram matrix is Hermitian, so only its upper 16x16 tiles are computed; each
+// wave takes a quarter of every staged slab of rows and accumulates all upper
+// tiles (TB column tiles loaded once per 4-row step feed TB(TB+1)/2 complex MFMA
+// products), slab sums are added in FP64 and the four waves are reduced in LDS.
 template <typename T, int JB>
 __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, int m, int N,
                                                    const int* __restrict__ colmap, int nb,
                                                    int round, int splits, int chunk,
                                                    double2* __restrict__ partials) {
-    constexpr int NB = 2 * JB, MB = NB / 32;   // MFMA tiles per wave per dimension
-    constexpr int RB = 4096 / NB;              // rows per staged slab (LDS tile NB x RB)
+    constexpr int NB = 2 * JB, TB = NB / 16, NU = TB * (TB + 1) / 2;
+    constexpr int RB = 4096 / NB;              // rows per staged slab
+    constexpr int RW = RB / 4;                 // rows of a slab per wave
     __shared__ C2<T> Xs[RB][NB + 1];
+    __shared__ double2 red[NU * 256];
     __shared__ int cols[NB];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
     const int pair = blockIdx.x, split = blockIdx.y;
     int p, q;
     pair_of(round, pair, nb, p, q);
@@ -112,22 +116,13 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
     __syncthreads();
     const int r0 = split * chunk;
     const int r1 = min(m, r0 + chunk);
-    // MFMA accumulation in T within one slab, slab sums accumulated in FP64
-    A4<T> accR[MB][MB], accI[MB][MB];
-    d4 sumR[MB][MB], sumI[MB][MB];
+    A4<T> accR[NU], accI[NU];
+    d4 sumR[NU], sumI[NU];
 #pragma unroll
-    for (int bi = 0; bi < MB; ++bi)
+    for (int u = 0; u < NU; ++u)
 #pragma unroll
-        for (int bj = 0; bj < MB; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) { sumR[bi][bj][r] = 0.0; sumI[bi][bj][r] = 0.0; }
+        for (int r = 0; r < 4; ++r) { sumR[u][r] = 0.0; sumI[u][r] = 0.0; }
     for (int k0 = r0; k0 < r1; k0 += RB) {
-#pragma unroll
-        for (int bi = 0; bi < MB; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < MB; ++bj)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
 #pragma unroll
         for (int r = 0; r < (RB * NB) / 256; ++r) {
             const int e = t + 256 * r;
@@ -139,46 +134,64 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < RB; kk += 4) {
-            C2<T> a[MB], b[MB];
+        for (int u = 0; u < NU; ++u)
 #pragma unroll
-            for (int s = 0; s < MB; ++s) {
-                a[s] = Xs[kk + (lane >> 4)][wm * (NB / 2) + s * 16 + (lane & 15)];
-                b[s] = Xs[kk + (lane >> 4)][wn * (NB / 2) + s * 16 + (lane & 15)];
-            }
-            // A[i][k] = conj(X[k][i]): (ar - i ai)(br + i bi)
+            for (int r = 0; r < 4; ++r) { accR[u][r] = T(0); accI[u][r] = T(0); }
+#pragma unroll 2
+        for (int kk = wave * RW; kk < (wave + 1) * RW; kk += 4) {
+            C2<T> x[TB];
 #pragma unroll
-            for (int bi = 0; bi < MB; ++bi)
+            for (int b = 0; b < TB; ++b) x[b] = Xs[kk + (lane >> 4)][b * 16 + (lane & 15)];
+            int u = 0;
 #pragma unroll
-                for (int bj = 0; bj < MB; ++bj) {
-                    accR[bi][bj] = mfma16(a[bi].x, b[bj].x, accR[bi][bj]);
-                    accR[bi][bj] = mfma16(a[bi].y, b[bj].y, accR[bi][bj]);
-                    accI[bi][bj] = mfma16(a[bi].x, b[bj].y, accI[bi][bj]);
-                    accI[bi][bj] = mfma16(-a[bi].y, b[bj].x, accI[bi][bj]);
+            for (int bi = 0; bi < TB; ++bi)
+#pragma unroll
+                for (int bj = bi; bj < TB; ++bj, ++u) {
+                    // conj(x_bi) x_bj: (ar - i ai)(br + i bi)
+                    accR[u] = mfma16(x[bi].x, x[bj].x, accR[u]);
+                    accR[u] = mfma16(x[bi].y, x[bj].y, accR[u]);
+                    accI[u] = mfma16(x[bi].x, x[bj].y, accI[u]);
+                    accI[u] = mfma16(-x[bi].y, x[bj].x, accI[u]);
                 }
         }
 #pragma unroll
-        for (int bi = 0; bi < MB; ++bi)
+        for (int u = 0; u < NU; ++u)
 #pragma unroll
-            for (int bj = 0; bj < MB; ++bj)
+            for (int r = 0; r < 4; ++r) {
+                sumR[u][r] += (double)accR[u][r];
+                sumI[u][r] += (double)accI[u][r];
+            }
+        __syncthreads();
+    }
+    // reduce the four waves' tiles in LDS
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    sumR[bi][bj][r] += (double)accR[bi][bj][r];
-                    sumI[bi][bj][r] += (double)accI[bi][bj][r];
+                    const int idx = u * 256 + acc_row<T>(lane, r) + 16 * (lane & 15);
+                    if (w == 0) red[idx] = make_double2(sumR[u][r], sumI[u][r]);
+                    else { red[idx].x += sumR[u][r]; red[idx].y += sumI[u][r]; }
                 }
+        }
         __syncthreads();
     }
     double2* out = partials + (size_t)(pair * splits + split) * (NB * NB);
-#pragma unroll
-    for (int bi = 0; bi < MB; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < MB; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = wm * (NB / 2) + bi * 16 + acc_row<T>(lane, r);
-                const int j = wn * (NB / 2) + bj * 16 + (lane & 15);
-                out[i + NB * j] = make_double2(sumR[bi][bj][r], sumI[bi][bj][r]);
-            }
+    for (int e = t; e < NB * NB; e += 256) {
+        const int i = e % NB, j = e / NB;
+        const int bi = i >> 4, bj = j >> 4;
+        double2 v;
+        if (bi <= bj) {
+            const int u = bi * TB - bi * (bi - 1) / 2 + (bj - bi);
+            v = red[u * 256 + (i & 15) + 16 * (j & 15)];
+        } else {
+            const int u = bj * TB - bj * (bj - 1) / 2 + (bi - bj);
+            const double2 w = red[u * 256 + (j & 15) + 16 * (i & 15)];
+            v = make_double2(w.x, -w.y);
+        }
+        out[i + NB * j] = v;
+    }
 }
 
 // --------------------------------------------------- NB x NB Hermitian eigen (FP64)
@@ -348,6 +361,7 @@ __global__ __launch_bounds__(256) void k_pair_eig(const double2* __restrict__ pa
 }
 
 // ------------------------------------------------------------- pair update
+constexpr int kUpdateSlabs = 4;   // 64-row slabs per work-group
 // [x_p x_q] <- [x_p x_q] W for one 64-row slab of the pair's NB columns.
 template <typename T, int JB>
 __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int m, int N,
@@ -370,57 +384,61 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
     }
     const C2<T>* wsrc = Wm + (size_t)pair * (NB * NB);
     for (int e = t; e < NB * NB; e += 256) Ws[e % NB][e / NB] = wsrc[e];
-    __syncthreads();
-    const int r0 = blockIdx.y * 64;
-    for (int e = t; e < NB * 64; e += 256) {
-        const int row = e & 63, col = e >> 6;
-        const int c = cols[col];
-        C2<T> v = czero<T>();
-        if (c >= 0 && r0 + row < m) v = X[(size_t)(r0 + row) + (size_t)m * c];
-        Xt[col][row] = v;
-    }
-    __syncthreads();
-    // wave (wm, wn): rows wm*32 .. +32, columns wn*NB/2 .. +NB/2
-    A4<T> accR[2][MB], accI[2][MB];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < MB; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
-#pragma unroll 4
-    for (int kk = 0; kk < NB; kk += 4) {
-        C2<T> a[2], b[MB];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) a[s] = Xt[kk + (lane >> 4)][wm * 32 + s * 16 + (lane & 15)];
-#pragma unroll
-        for (int s = 0; s < MB; ++s) b[s] = Ws[kk + (lane >> 4)][wn * (NB / 2) + s * 16 + (lane & 15)];
+    // W stays in LDS for kUpdateSlabs consecutive 64-row slabs
+    for (int slab = 0; slab < kUpdateSlabs; ++slab) {
+        const int r0 = (blockIdx.y * kUpdateSlabs + slab) * 64;
+        if (r0 >= m) break;
+        __syncthreads();
+        for (int e = t; e < NB * 64; e += 256) {
+            const int row = e & 63, col = e >> 6;
+            const int c = cols[col];
+            C2<T> v = czero<T>();
+            if (c >= 0 && r0 + row < m) v = X[(size_t)(r0 + row) + (size_t)m * c];
+            Xt[col][row] = v;
+        }
+        __syncthreads();
+        // wave (wm, wn): rows wm*32 .. +32, columns wn*NB/2 .. +NB/2
+        A4<T> accR[2][MB], accI[2][MB];
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < MB; ++bj) {
-                accR[bi][bj] = mfma16(a[bi].x, b[bj].x, accR[bi][bj]);
-                accR[bi][bj] = mfma16(-a[bi].y, b[bj].y, accR[bi][bj]);
-                accI[bi][bj] = mfma16(a[bi].x, b[bj].y, accI[bi][bj]);
-                accI[bi][bj] = mfma16(a[bi].y, b[bj].x, accI[bi][bj]);
-            }
-    }
-    __syncthreads();
+            for (int bj = 0; bj < MB; ++bj)
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+                for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
+#pragma unroll 4
+        for (int kk = 0; kk < NB; kk += 4) {
+            C2<T> a[2], b[MB];
 #pragma unroll
-        for (int bj = 0; bj < MB; ++bj)
+            for (int s = 0; s < 2; ++s) a[s] = Xt[kk + (lane >> 4)][wm * 32 + s * 16 + (lane & 15)];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = wm * 32 + bi * 16 + acc_row<T>(lane, r);
-                const int col = wn * (NB / 2) + bj * 16 + (lane & 15);
-                Xt[col][row] = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
-            }
-    __syncthreads();
-    for (int e = t; e < NB * 64; e += 256) {
-        const int row = e & 63, col = e >> 6;
-        const int c = cols[col];
-        if (c >= 0 && r0 + row < m) X[(size_t)(r0 + row) + (size_t)m * c] = Xt[col][row];
+            for (int s = 0; s < MB; ++s) b[s] = Ws[kk + (lane >> 4)][wn * (NB / 2) + s * 16 + (lane & 15)];
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < MB; ++bj) {
+                    accR[bi][bj] = mfma16(a[bi].x, b[bj].x, accR[bi][bj]);
+                    accR[bi][bj] = mfma16(-a[bi].y, b[bj].y, accR[bi][bj]);
+                    accI[bi][bj] = mfma16(a[bi].x, b[bj].y, accI[bi][bj]);
+                    accI[bi][bj] = mfma16(a[bi].y, b[bj].x, accI[bi][bj]);
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < MB; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wm * 32 + bi * 16 + acc_row<T>(lane, r);
+                    const int col = wn * (NB / 2) + bj * 16 + (lane & 15);
+                    Xt[col][row] = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
+                }
+        __syncthreads();
+        for (int e = t; e < NB * 64; e += 256) {
+            const int row = e & 63, col = e >> 6;
+            const int c = cols[col];
+            if (c >= 0 && r0 + row < m) X[(size_t)(r0 + row) + (size_t)m * c] = Xt[col][row];
+        }
     }
 }
 
@@ -624,7 +642,7 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
                                (C2<T>*)w.w, w.skip, w.info);
             pf.end(st, K_EIG, 0.0, (double)P * splits * NB * NB * 16.0);
             pf.begin(st);
-            hipLaunchKernelGGL((k_pair_update<T, JB>), dim3(P, (m + 63) / 64), dim3(256), 0, st, X, m,
+            hipLaunchKernelGGL((k_pair_update<T, JB>), dim3(P, (m + 64 * kUpdateSlabs - 1) / (64 * kUpdateSlabs)), dim3(256), 0, st, X, m,
                                N, w.colmap, nb, r, (const C2<T>*)w.w, w.skip);
             pf.end(st, K_UPDATE, 0.0, 0.0);
         }
