@@ -198,8 +198,9 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
 // Sums the Gram partials, measures the largest relative off-diagonal element
 // |g_ij| / sqrt(g_ii g_jj), and if it exceeds tol runs up to inner_max cyclic
 // Jacobi sweeps (parallel ordering: NB/2 disjoint rotations per step), giving
-// a unitary W with W^H G W close to diagonal.  A step computes the NB/2
-// rotations in one wave, then every thread transforms whole 2x2 blocks
+// a unitary W with W^H G W close to diagonal.  In a step every wave computes
+// the NB/2 rotations itself (no work-group barrier between the rotations and
+// their use), then every thread transforms whole 2x2 blocks
 // G[{i1,j1}][{i2,j2}] <- J1^H G J2 (rows and columns at once) and rotates
 // (row, pair) slices of W; inactive pairs use the exact identity rotation.
 // Columns whose squared norm is at most zrel2 * ||X||_F^2 are never rotated.
@@ -208,6 +209,42 @@ __device__ __forceinline__ double2 dmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 dmulc(double2 a, double2 b) {   // conj(a) * b
     return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// 1/sqrt(x) for normal x > 0: hardware estimate and two Newton steps, each
+// y <- y + y (1 - x y^2) / 2, which take it to full FP64 accuracy.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double e = fma(-x * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+// Rotation J = [[c, s], [-conj(s), c]] (c real, c^2 + |s|^2 = 1) with
+// (J^H B J)_{01} = 0 for B = [[a, g], [conj(g), d]], through the smaller
+// angle: with h = d - a and r = sqrt(h^2 + 4|g|^2), c^2 = (1 + |h|/r)/2 and
+// s = sign(h) g / (r c).  Every term is a sum of non-negative parts, so small
+// angles keep full relative accuracy.
+__device__ __forceinline__ void jacobi_rotation(double a, double d, double2 g, double g2,
+                                                double& c, double2& s) {
+    const double h = d - a;
+    const double inv_r = rsqrt_nr(fma(h, h, 4.0 * g2));
+    const double c2 = fma(0.5 * fabs(h), inv_r, 0.5);
+    const double inv_c = rsqrt_nr(c2);
+    c = c2 * inv_c;
+    const double f = (h >= 0.0 ? inv_r : -inv_r) * inv_c;
+    s = make_double2(f * g.x, f * g.y);
+}
+
+// Orders this wave's LDS writes before its later LDS reads (lanes exchange
+// data through LDS without a work-group barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int NB>
@@ -245,9 +282,9 @@ __global__ __launch_bounds__(256) void k_pair_eig(const double2* __restrict__ pa
     __shared__ double2 G[NB][NB + 1];
     __shared__ double2 W[NB][NB + 1];
     __shared__ double red[256];
-    __shared__ double4 rot[NP];       // c, s, Re ph, Im ph
-    __shared__ int pi_[NP], pj_[NP];
-    const int t = threadIdx.x, pair = blockIdx.x;
+    __shared__ double rc[4][NP];      // per-wave copies of the step's rotations
+    __shared__ double2 rs[4][NP];
+    const int t = threadIdx.x, pair = blockIdx.x, lane = t & 63, wave = t >> 6;
     for (int e = t; e < NB * NB; e += 256) {
         const int i = e % NB, j = e / NB;
         double2 s = make_double2(0.0, 0.0);
@@ -272,6 +309,7 @@ __global__ __launch_bounds__(256) void k_pair_eig(const double2* __restrict__ pa
     }
     __syncthreads();
     const double zthr = zrel2 * (*fro2);
+    const double tol2 = tol * tol;
     const double off0 = block_off<NB>(G, zthr, red);
     if (off0 <= tol) {
         if (t == 0) skip[pair] = 1;
@@ -286,49 +324,45 @@ __global__ __launch_bounds__(256) void k_pair_eig(const double2* __restrict__ pa
     for (int sweep = 0; sweep < inner_max; ++sweep) {
         steps_done += NB - 1;
         for (int step = 0; step < NB - 1; ++step) {
-            if (t < NP) {
+            if (lane < NP) {
                 int i, j;
-                pair_of(step, t, NB, i, j);
+                pair_of(step, lane, NB, i, j);
                 const double a = G[i][i].x, d = G[j][j].x;
                 const double2 g = G[i][j];
-                const double ag = sqrt(g.x * g.x + g.y * g.y);
-                double c = 1.0, s = 0.0, pr = 1.0, pim = 0.0;
-                if (a > zthr && d > zthr && ag > tol * sqrt(a * d)) {
-                    pr = g.x / ag;
-                    pim = g.y / ag;
-                    const double tau = (d - a) / (2.0 * ag);
-                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + tt * tt);
-                    s = tt * c;
-                }
-                rot[t] = make_double4(c, s, pr, pim);
-                pi_[t] = i;
-                pj_[t] = j;
+                const double g2 = g.x * g.x + g.y * g.y;
+                double c = 1.0;
+                double2 s = make_double2(0.0, 0.0);
+                if (a > zthr && d > zthr && g2 > tol2 * a * d) jacobi_rotation(a, d, g, g2, c, s);
+                rc[wave][lane] = c;
+                rs[wave][lane] = s;
             }
-            __syncthreads();
+            wave_lds_sync();
             // G <- J^H G J, one 2x2 block per (P1, P2)
 #pragma unroll
             for (int u = 0; u < (NP * NP + 255) / 256; ++u) {
                 const int b = t + 256 * u;
                 if (NP * NP % 256 == 0 || b < NP * NP) {
                     const int P1 = b / NP, P2 = b % NP;
-                    const double4 r1 = rot[P1], r2 = rot[P2];
-                    const int i1 = pi_[P1], j1 = pj_[P1], i2 = pi_[P2], j2 = pj_[P2];
+                    int i1, j1, i2, j2;
+                    pair_of(step, P1, NB, i1, j1);
+                    pair_of(step, P2, NB, i2, j2);
+                    const double c1 = rc[wave][P1], c2 = rc[wave][P2];
+                    const double2 s1 = rs[wave][P1], s2 = rs[wave][P2];
                     const double2 b00 = G[i1][i2], b01 = G[i1][j2], b10 = G[j1][i2], b11 = G[j1][j2];
-                    // C = B J2 with J2 = [[c, s], [-s conj(ph), c conj(ph)]]
-                    const double2 ph2 = make_double2(r2.z, r2.w);
-                    const double2 q01 = dmulc(ph2, b01), q11 = dmulc(ph2, b11);
-                    const double2 c00 = make_double2(r2.x * b00.x - r2.y * q01.x, r2.x * b00.y - r2.y * q01.y);
-                    const double2 c01 = make_double2(r2.y * b00.x + r2.x * q01.x, r2.y * b00.y + r2.x * q01.y);
-                    const double2 c10 = make_double2(r2.x * b10.x - r2.y * q11.x, r2.x * b10.y - r2.y * q11.y);
-                    const double2 c11 = make_double2(r2.y * b10.x + r2.x * q11.x, r2.y * b10.y + r2.x * q11.y);
-                    // D = J1^H C: rows i1 <- c C0 - s ph C1, j1 <- s C0 + c ph C1
-                    const double2 ph1 = make_double2(r1.z, r1.w);
-                    const double2 p10 = dmul(ph1, c10), p11 = dmul(ph1, c11);
-                    G[i1][i2] = make_double2(r1.x * c00.x - r1.y * p10.x, r1.x * c00.y - r1.y * p10.y);
-                    G[i1][j2] = make_double2(r1.x * c01.x - r1.y * p11.x, r1.x * c01.y - r1.y * p11.y);
-                    G[j1][i2] = make_double2(r1.y * c00.x + r1.x * p10.x, r1.y * c00.y + r1.x * p10.y);
-                    G[j1][j2] = make_double2(r1.y * c01.x + r1.x * p11.x, r1.y * c01.y + r1.x * p11.y);
+                    // C = B J2: column i2 <- c2 B_i2 - conj(s2) B_j2, column j2 <- s2 B_i2 + c2 B_j2
+                    const double2 t01 = dmulc(s2, b01), t11 = dmulc(s2, b11);
+                    const double2 u00 = dmul(s2, b00), u10 = dmul(s2, b10);
+                    const double2 c00 = make_double2(c2 * b00.x - t01.x, c2 * b00.y - t01.y);
+                    const double2 c10 = make_double2(c2 * b10.x - t11.x, c2 * b10.y - t11.y);
+                    const double2 c01 = make_double2(u00.x + c2 * b01.x, u00.y + c2 * b01.y);
+                    const double2 c11 = make_double2(u10.x + c2 * b11.x, u10.y + c2 * b11.y);
+                    // D = J1^H C: row i1 <- c1 C_i1 - s1 C_j1, row j1 <- conj(s1) C_i1 + c1 C_j1
+                    const double2 v10 = dmul(s1, c10), v11 = dmul(s1, c11);
+                    const double2 w00 = dmulc(s1, c00), w01 = dmulc(s1, c01);
+                    G[i1][i2] = make_double2(c1 * c00.x - v10.x, c1 * c00.y - v10.y);
+                    G[i1][j2] = make_double2(c1 * c01.x - v11.x, c1 * c01.y - v11.y);
+                    G[j1][i2] = make_double2(w00.x + c1 * c10.x, w00.y + c1 * c10.y);
+                    G[j1][j2] = make_double2(w01.x + c1 * c11.x, w01.y + c1 * c11.y);
                 }
             }
             // W <- W J
@@ -336,12 +370,14 @@ __global__ __launch_bounds__(256) void k_pair_eig(const double2* __restrict__ pa
             for (int u = 0; u < (NB * NP) / 256; ++u) {
                 const int e = t + 256 * u;
                 const int P = e / NB, row = e % NB;
-                const double4 r = rot[P];
-                const int i = pi_[P], j = pj_[P];
+                int i, j;
+                pair_of(step, P, NB, i, j);
+                const double c = rc[wave][P];
+                const double2 s = rs[wave][P];
                 const double2 wi = W[row][i], wj = W[row][j];
-                const double2 q = dmulc(make_double2(r.z, r.w), wj);
-                W[row][i] = make_double2(r.x * wi.x - r.y * q.x, r.x * wi.y - r.y * q.y);
-                W[row][j] = make_double2(r.y * wi.x + r.x * q.x, r.y * wi.y + r.x * q.y);
+                const double2 q = dmulc(s, wj), v = dmul(s, wi);
+                W[row][i] = make_double2(c * wi.x - q.x, c * wi.y - q.y);
+                W[row][j] = make_double2(v.x + c * wj.x, v.y + c * wj.y);
             }
             __syncthreads();
         }
