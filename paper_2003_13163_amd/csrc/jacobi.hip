@@ -122,17 +122,31 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
     for (int u = 0; u < NU; ++u)
 #pragma unroll
         for (int r = 0; r < 4; ++r) { sumR[u][r] = 0.0; sumI[u][r] = 0.0; }
+    // the next slab is loaded into registers while the current one is reduced
+    constexpr int LE = (RB * NB) / 256;        // slab elements per thread
+    C2<T> pre[LE];
+#pragma unroll
+    for (int r = 0; r < LE; ++r) {
+        const int e = t + 256 * r;
+        const int row = e % RB, c = cols[e / RB];
+        pre[r] = (c >= 0 && r0 + row < r1) ? X[(size_t)(r0 + row) + (size_t)m * c] : czero<T>();
+    }
     for (int k0 = r0; k0 < r1; k0 += RB) {
 #pragma unroll
-        for (int r = 0; r < (RB * NB) / 256; ++r) {
+        for (int r = 0; r < LE; ++r) {
             const int e = t + 256 * r;
-            const int row = e % RB, col = e / RB;
-            const int c = cols[col];
-            C2<T> v = czero<T>();
-            if (c >= 0 && k0 + row < r1) v = X[(size_t)(k0 + row) + (size_t)m * c];
-            Xs[row][col] = v;
+            Xs[e % RB][e / RB] = pre[r];
         }
         __syncthreads();
+        if (k0 + RB < r1) {
+            const int k1 = k0 + RB;
+#pragma unroll
+            for (int r = 0; r < LE; ++r) {
+                const int e = t + 256 * r;
+                const int row = e % RB, c = cols[e / RB];
+                pre[r] = (c >= 0 && k1 + row < r1) ? X[(size_t)(k1 + row) + (size_t)m * c] : czero<T>();
+            }
+        }
 #pragma unroll
         for (int u = 0; u < NU; ++u)
 #pragma unroll
@@ -198,11 +212,10 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
 // Sums the Gram partials, measures the largest relative off-diagonal element
 // |g_ij| / sqrt(g_ii g_jj), and if it exceeds tol runs up to inner_max cyclic
 // Jacobi sweeps (parallel ordering: NB/2 disjoint rotations per step), giving
-// a unitary W with W^H G W close to diagonal.  In a step every wave computes
-// the NB/2 rotations itself (no work-group barrier between the rotations and
-// their use), then every thread transforms whole 2x2 blocks
-// G[{i1,j1}][{i2,j2}] <- J1^H G J2 (rows and columns at once) and rotates
-// (row, pair) slices of W; inactive pairs use the exact identity rotation.
+// a unitary W with W^H G W close to diagonal.  In a step every thread owns
+// 2x2 blocks G[{i1,j1}][{i2,j2}], computes the two rotations it needs itself
+// and applies G <- J1^H G J2 to its blocks (rows and columns at once) and J1
+// to the matching entries of W; inactive pairs use the exact identity.
 // Columns whose squared norm is at most zrel2 * ||X||_F^2 are never rotated.
 __device__ __forceinline__ double2 dmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -227,31 +240,30 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // (J^H B J)_{01} = 0 for B = [[a, g], [conj(g), d]], through the smaller
 // angle: with h = d - a and r = sqrt(h^2 + 4|g|^2), c^2 = (1 + |h|/r)/2 and
 // s = sign(h) g / (r c).  Every term is a sum of non-negative parts, so small
-// angles keep full relative accuracy.
-__device__ __forceinline__ void jacobi_rotation(double a, double d, double2 g, double g2,
-                                                double& c, double2& s) {
+// angles keep full relative accuracy.  The identity is returned when either
+// column is at the rounding floor (squared norm <= zthr) or the pair is
+// already orthogonal to tol.  The code has no branches, so the two rotations
+// a thread needs are computed side by side; every thread that needs a pair's
+// rotation computes it from the same values with the same operations, so all
+// of them agree bit for bit.
+__device__ __forceinline__ void pair_rotation(double a, double d, double2 g, double zthr,
+                                              double tol2, double& c, double2& s) {
+    const double g2 = fma(g.x, g.x, g.y * g.y);
+    const bool act = (a > zthr) & (d > zthr) & (g2 > tol2 * a * d);
     const double h = d - a;
-    const double inv_r = rsqrt_nr(fma(h, h, 4.0 * g2));
-    const double c2 = fma(0.5 * fabs(h), inv_r, 0.5);
+    const double inv_r = rsqrt_nr(act ? fma(h, h, 4.0 * g2) : 1.0);
+    const double c2 = act ? fma(0.5 * fabs(h), inv_r, 0.5) : 1.0;
     const double inv_c = rsqrt_nr(c2);
-    c = c2 * inv_c;
-    const double f = (h >= 0.0 ? inv_r : -inv_r) * inv_c;
+    const double f = act ? (h >= 0.0 ? inv_r : -inv_r) * inv_c : 0.0;
+    c = act ? c2 * inv_c : 1.0;
     s = make_double2(f * g.x, f * g.y);
 }
 
-// Orders this wave's LDS writes before its later LDS reads (lanes exchange
-// data through LDS without a work-group barrier).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int NB>
+template <int NB, int NT>
 __device__ double block_off(const double2 (*G)[NB + 1], double zthr, double* red) {
     const int t = threadIdx.x;
     double mx = 0.0;
-    for (int e = t; e < NB * NB; e += 256) {
+    for (int e = t; e < NB * NB; e += NT) {
         const int i = e % NB, j = e / NB;
         if (i < j) {
             const double a = G[i][i].x, d = G[j][j].x;
@@ -263,7 +275,7 @@ __device__ double block_off(const double2 (*G)[NB + 1], double zthr, double* red
     }
     red[t] = mx;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = NT / 2; o > 0; o >>= 1) {
         if (t < o) red[t] = fmax(red[t], red[t + o]);
         __syncthreads();
     }
@@ -272,22 +284,35 @@ __device__ double block_off(const double2 (*G)[NB + 1], double zthr, double* red
     return r;
 }
 
+// Pair indices of a thread's blocks, advanced from one step of the
+// round-robin ordering to the next: both members move on by one modulo NB-1,
+// except the fixed member NB-1 of pair 0.
+template <int NB>
+__device__ __forceinline__ void next_pair(int P, int& i, int& j) {
+    i = (i + 1 == NB - 1) ? 0 : i + 1;
+    if (P != 0) j = (j + 1 == NB - 1) ? 0 : j + 1;
+}
+
+constexpr int kEigThreads = 512;   // waves 0-3 transform G, waves 4-7 accumulate W
+
 template <typename T, int JB>
-__global__ __launch_bounds__(256) void k_pair_eig(const double2* __restrict__ partials, int splits,
-                                                  double tol, double zrel2,
-                                                  const double* __restrict__ fro2, int inner_max,
-                                                  C2<T>* __restrict__ Wout, int* __restrict__ skip,
-                                                  DevInfo* info) {
-    constexpr int NB = 2 * JB, NP = JB;
+__global__ __launch_bounds__(kEigThreads) void k_pair_eig(const double2* __restrict__ partials,
+                                                         int splits, double tol, double zrel2,
+                                                         const double* __restrict__ fro2,
+                                                         int inner_max, C2<T>* __restrict__ Wout,
+                                                         int* __restrict__ skip, DevInfo* info) {
+    constexpr int NT = kEigThreads, NB = 2 * JB, NP = JB, U = NP * NP / 256;   // blocks per thread
+    static_assert(NP * NP % 256 == 0, "block count must fill four waves");
     __shared__ double2 G[NB][NB + 1];
     __shared__ double2 W[NB][NB + 1];
-    __shared__ double red[256];
-    __shared__ double rc[4][NP];      // per-wave copies of the step's rotations
-    __shared__ double2 rs[4][NP];
-    const int t = threadIdx.x, pair = blockIdx.x, lane = t & 63, wave = t >> 6;
-    for (int e = t; e < NB * NB; e += 256) {
+    __shared__ double red[NT];
+    __shared__ double rc[2][NP];       // rotations of the last two steps, for the W waves
+    __shared__ double2 rs[2][NP];
+    const int t = threadIdx.x, pair = blockIdx.x;
+    for (int e = t; e < NB * NB; e += NT) {
         const int i = e % NB, j = e / NB;
         double2 s = make_double2(0.0, 0.0);
+#pragma unroll 4
         for (int sp = 0; sp < splits; ++sp) {
             const double2 v = partials[(size_t)(pair * splits + sp) * (NB * NB) + i + NB * j];
             s.x += v.x;
@@ -296,7 +321,7 @@ __global__ __launch_bounds__(256) void k_pair_eig(const double2* __restrict__ pa
         G[i][j] = s;
     }
     __syncthreads();
-    for (int e = t; e < NB * NB; e += 256) {
+    for (int e = t; e < NB * NB; e += NT) {
         const int i = e % NB, j = e / NB;
         if (i < j) {
             const double2 a = G[i][j], b = G[j][i];
@@ -310,81 +335,133 @@ __global__ __launch_bounds__(256) void k_pair_eig(const double2* __restrict__ pa
     __syncthreads();
     const double zthr = zrel2 * (*fro2);
     const double tol2 = tol * tol;
-    const double off0 = block_off<NB>(G, zthr, red);
+    const double off0 = block_off<NB, NT>(G, zthr, red);
     if (off0 <= tol) {
         if (t == 0) skip[pair] = 1;
         return;
     }
-    for (int e = t; e < NB * NB; e += 256) {
+    for (int e = t; e < NB * NB; e += NT) {
         const int i = e % NB, j = e / NB;
         W[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
-    int steps_done = 0;
+    // Thread tt of either half owns the 2x2 blocks b = tt + 256u, (P1, P2) =
+    // (b / NP, b % NP).  A G thread rebuilds the rotations of P1 and P2 from
+    // the diagonal blocks of G (all of them are read before any is
+    // overwritten) and applies G <- J1^H G J2 to its block; the rotations of
+    // the step are published for the W threads, which apply W <- W J1 to rows
+    // {i2, j2} one step later, off the critical path of G.
+    const bool gthr = t < 256;
+    const int tt = t & 255;
+    int i1[U], j1[U], i2[U], j2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int b = tt + 256 * u;
+        pair_of(0, b / NP, NB, i1[u], j1[u]);
+        pair_of(0, b % NP, NB, i2[u], j2[u]);
+    }
+    int steps_done = 0, k = 0;   // k counts steps over all sweeps
     for (int sweep = 0; sweep < inner_max; ++sweep) {
         steps_done += NB - 1;
-        for (int step = 0; step < NB - 1; ++step) {
-            if (lane < NP) {
-                int i, j;
-                pair_of(step, lane, NB, i, j);
-                const double a = G[i][i].x, d = G[j][j].x;
-                const double2 g = G[i][j];
-                const double g2 = g.x * g.x + g.y * g.y;
-                double c = 1.0;
-                double2 s = make_double2(0.0, 0.0);
-                if (a > zthr && d > zthr && g2 > tol2 * a * d) jacobi_rotation(a, d, g, g2, c, s);
-                rc[wave][lane] = c;
-                rs[wave][lane] = s;
-            }
-            wave_lds_sync();
-            // G <- J^H G J, one 2x2 block per (P1, P2)
+        for (int step = 0; step < NB - 1; ++step, ++k) {
+            double2 bk[U][4], s1[U], s2[U];
+            double c1[U], c2[U];
+            if (gthr) {
 #pragma unroll
-            for (int u = 0; u < (NP * NP + 255) / 256; ++u) {
-                const int b = t + 256 * u;
-                if (NP * NP % 256 == 0 || b < NP * NP) {
-                    const int P1 = b / NP, P2 = b % NP;
-                    int i1, j1, i2, j2;
-                    pair_of(step, P1, NB, i1, j1);
-                    pair_of(step, P2, NB, i2, j2);
-                    const double c1 = rc[wave][P1], c2 = rc[wave][P2];
-                    const double2 s1 = rs[wave][P1], s2 = rs[wave][P2];
-                    const double2 b00 = G[i1][i2], b01 = G[i1][j2], b10 = G[j1][i2], b11 = G[j1][j2];
-                    // C = B J2: column i2 <- c2 B_i2 - conj(s2) B_j2, column j2 <- s2 B_i2 + c2 B_j2
-                    const double2 t01 = dmulc(s2, b01), t11 = dmulc(s2, b11);
-                    const double2 u00 = dmul(s2, b00), u10 = dmul(s2, b10);
-                    const double2 c00 = make_double2(c2 * b00.x - t01.x, c2 * b00.y - t01.y);
-                    const double2 c10 = make_double2(c2 * b10.x - t11.x, c2 * b10.y - t11.y);
-                    const double2 c01 = make_double2(u00.x + c2 * b01.x, u00.y + c2 * b01.y);
-                    const double2 c11 = make_double2(u10.x + c2 * b11.x, u10.y + c2 * b11.y);
-                    // D = J1^H C: row i1 <- c1 C_i1 - s1 C_j1, row j1 <- conj(s1) C_i1 + c1 C_j1
-                    const double2 v10 = dmul(s1, c10), v11 = dmul(s1, c11);
-                    const double2 w00 = dmulc(s1, c00), w01 = dmulc(s1, c01);
-                    G[i1][i2] = make_double2(c1 * c00.x - v10.x, c1 * c00.y - v10.y);
-                    G[i1][j2] = make_double2(c1 * c01.x - v11.x, c1 * c01.y - v11.y);
-                    G[j1][i2] = make_double2(w00.x + c1 * c10.x, w00.y + c1 * c10.y);
-                    G[j1][j2] = make_double2(w01.x + c1 * c11.x, w01.y + c1 * c11.y);
+                for (int u = 0; u < U; ++u) {
+                    bk[u][0] = G[i1[u]][i2[u]];
+                    bk[u][1] = G[i1[u]][j2[u]];
+                    bk[u][2] = G[j1[u]][i2[u]];
+                    bk[u][3] = G[j1[u]][j2[u]];
+                    pair_rotation(G[i1[u]][i1[u]].x, G[j1[u]][j1[u]].x, G[i1[u]][j1[u]], zthr, tol2,
+                                  c1[u], s1[u]);
+                    pair_rotation(G[i2[u]][i2[u]].x, G[j2[u]][j2[u]].x, G[i2[u]][j2[u]], zthr, tol2,
+                                  c2[u], s2[u]);
+                }
+                if (tt < NP) {          // P1 == 0: publish rotation P2 = tt
+                    rc[k & 1][tt] = c2[0];
+                    rs[k & 1][tt] = s2[0];
+                }
+            } else if (k > 0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int P1 = (tt + 256 * u) / NP;
+                    c1[u] = rc[(k - 1) & 1][P1];
+                    s1[u] = rs[(k - 1) & 1][P1];
+                    bk[u][0] = W[i2[u]][i1[u]];
+                    bk[u][1] = W[i2[u]][j1[u]];
+                    bk[u][2] = W[j2[u]][i1[u]];
+                    bk[u][3] = W[j2[u]][j1[u]];
                 }
             }
-            // W <- W J
+            __syncthreads();
+            if (gthr) {
 #pragma unroll
-            for (int u = 0; u < (NB * NP) / 256; ++u) {
-                const int e = t + 256 * u;
-                const int P = e / NB, row = e % NB;
-                int i, j;
-                pair_of(step, P, NB, i, j);
-                const double c = rc[wave][P];
-                const double2 s = rs[wave][P];
-                const double2 wi = W[row][i], wj = W[row][j];
-                const double2 q = dmulc(s, wj), v = dmul(s, wi);
-                W[row][i] = make_double2(c * wi.x - q.x, c * wi.y - q.y);
-                W[row][j] = make_double2(v.x + c * wj.x, v.y + c * wj.y);
+                for (int u = 0; u < U; ++u) {
+                    const double2 b00 = bk[u][0], b01 = bk[u][1], b10 = bk[u][2], b11 = bk[u][3];
+                    const double c1u = c1[u], c2u = c2[u];
+                    // C = B J2: column i2 <- c2 B_i2 - conj(s2) B_j2, column j2 <- s2 B_i2 + c2 B_j2
+                    const double2 t01 = dmulc(s2[u], b01), t11 = dmulc(s2[u], b11);
+                    const double2 u00 = dmul(s2[u], b00), u10 = dmul(s2[u], b10);
+                    const double2 c00 = make_double2(c2u * b00.x - t01.x, c2u * b00.y - t01.y);
+                    const double2 c10 = make_double2(c2u * b10.x - t11.x, c2u * b10.y - t11.y);
+                    const double2 c01 = make_double2(u00.x + c2u * b01.x, u00.y + c2u * b01.y);
+                    const double2 c11 = make_double2(u10.x + c2u * b11.x, u10.y + c2u * b11.y);
+                    // D = J1^H C: row i1 <- c1 C_i1 - s1 C_j1, row j1 <- conj(s1) C_i1 + c1 C_j1
+                    const double2 v10 = dmul(s1[u], c10), v11 = dmul(s1[u], c11);
+                    const double2 x00 = dmulc(s1[u], c00), x01 = dmulc(s1[u], c01);
+                    G[i1[u]][i2[u]] = make_double2(c1u * c00.x - v10.x, c1u * c00.y - v10.y);
+                    G[i1[u]][j2[u]] = make_double2(c1u * c01.x - v11.x, c1u * c01.y - v11.y);
+                    G[j1[u]][i2[u]] = make_double2(x00.x + c1u * c10.x, x00.y + c1u * c10.y);
+                    G[j1[u]][j2[u]] = make_double2(x01.x + c1u * c11.x, x01.y + c1u * c11.y);
+                }
+            } else if (k > 0) {
+                // W <- W J1 on rows i2, j2 with the previous step's pairing
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double2 w00 = bk[u][0], w01 = bk[u][1], w10 = bk[u][2], w11 = bk[u][3];
+                    const double c1u = c1[u];
+                    const double2 q0 = dmulc(s1[u], w01), q1 = dmulc(s1[u], w11);
+                    const double2 r0 = dmul(s1[u], w00), r1 = dmul(s1[u], w10);
+                    W[i2[u]][i1[u]] = make_double2(c1u * w00.x - q0.x, c1u * w00.y - q0.y);
+                    W[i2[u]][j1[u]] = make_double2(r0.x + c1u * w01.x, r0.y + c1u * w01.y);
+                    W[j2[u]][i1[u]] = make_double2(c1u * w10.x - q1.x, c1u * w10.y - q1.y);
+                    W[j2[u]][j1[u]] = make_double2(r1.x + c1u * w11.x, r1.y + c1u * w11.y);
+                }
+            }
+            // G threads move to the next step's pairing; W threads to this step's
+            if (gthr || k > 0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int b = tt + 256 * u;
+                    next_pair<NB>(b / NP, i1[u], j1[u]);
+                    next_pair<NB>(b % NP, i2[u], j2[u]);
+                }
             }
             __syncthreads();
         }
-        if (sweep + 1 < inner_max && block_off<NB>(G, zthr, red) <= tol) break;
+        if (sweep + 1 < inner_max && block_off<NB, NT>(G, zthr, red) <= tol) break;
     }
+    // the W threads still owe the last step
+    if (!gthr && k > 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int P1 = (tt + 256 * u) / NP;
+            const double c1u = rc[(k - 1) & 1][P1];
+            const double2 s1u = rs[(k - 1) & 1][P1];
+            const double2 w00 = W[i2[u]][i1[u]], w01 = W[i2[u]][j1[u]];
+            const double2 w10 = W[j2[u]][i1[u]], w11 = W[j2[u]][j1[u]];
+            const double2 q0 = dmulc(s1u, w01), q1 = dmulc(s1u, w11);
+            const double2 r0 = dmul(s1u, w00), r1 = dmul(s1u, w10);
+            W[i2[u]][i1[u]] = make_double2(c1u * w00.x - q0.x, c1u * w00.y - q0.y);
+            W[i2[u]][j1[u]] = make_double2(r0.x + c1u * w01.x, r0.y + c1u * w01.y);
+            W[j2[u]][i1[u]] = make_double2(c1u * w10.x - q1.x, c1u * w10.y - q1.y);
+            W[j2[u]][j1[u]] = make_double2(r1.x + c1u * w11.x, r1.y + c1u * w11.y);
+        }
+    }
+    __syncthreads();
     C2<T>* wo = Wout + (size_t)pair * (NB * NB);
-    for (int e = t; e < NB * NB; e += 256) {
+    for (int e = t; e < NB * NB; e += NT) {
         const int i = e % NB, j = e / NB;
         wo[i + NB * j] = from_d2<T>(W[i][j]);
     }
@@ -420,19 +497,39 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
     }
     const C2<T>* wsrc = Wm + (size_t)pair * (NB * NB);
     for (int e = t; e < NB * NB; e += 256) Ws[e % NB][e / NB] = wsrc[e];
-    // W stays in LDS for kUpdateSlabs consecutive 64-row slabs
+    // W stays in LDS for kUpdateSlabs consecutive 64-row slabs; the next slab
+    // is loaded into registers while the current one is multiplied
+    constexpr int LE = NB * 64 / 256;
+    C2<T> pre[LE];
+    __syncthreads();
+    {
+        const int r0 = blockIdx.y * kUpdateSlabs * 64;
+#pragma unroll
+        for (int r = 0; r < LE; ++r) {
+            const int e = t + 256 * r;
+            const int row = e & 63, c = cols[e >> 6];
+            pre[r] = (c >= 0 && r0 + row < m) ? X[(size_t)(r0 + row) + (size_t)m * c] : czero<T>();
+        }
+    }
     for (int slab = 0; slab < kUpdateSlabs; ++slab) {
         const int r0 = (blockIdx.y * kUpdateSlabs + slab) * 64;
         if (r0 >= m) break;
         __syncthreads();
-        for (int e = t; e < NB * 64; e += 256) {
-            const int row = e & 63, col = e >> 6;
-            const int c = cols[col];
-            C2<T> v = czero<T>();
-            if (c >= 0 && r0 + row < m) v = X[(size_t)(r0 + row) + (size_t)m * c];
-            Xt[col][row] = v;
+#pragma unroll
+        for (int r = 0; r < LE; ++r) {
+            const int e = t + 256 * r;
+            Xt[e >> 6][e & 63] = pre[r];
         }
         __syncthreads();
+        if (slab + 1 < kUpdateSlabs && r0 + 64 < m) {
+            const int r1 = r0 + 64;
+#pragma unroll
+            for (int r = 0; r < LE; ++r) {
+                const int e = t + 256 * r;
+                const int row = e & 63, c = cols[e >> 6];
+                pre[r] = (c >= 0 && r1 + row < m) ? X[(size_t)(r1 + row) + (size_t)m * c] : czero<T>();
+            }
+        }
         // wave (wm, wn): rows wm*32 .. +32, columns wn*NB/2 .. +NB/2
         A4<T> accR[2][MB], accI[2][MB];
 #pragma unroll
@@ -673,7 +770,7 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
                                w.colmap, nb, r, splits, chunk, (double2*)w.gram_partials);
             pf.end(st, K_GRAM, P * pair_flops, P * pair_bytes + (double)P * splits * NB * NB * 16.0);
             pf.begin(st);
-            hipLaunchKernelGGL((k_pair_eig<T, JB>), dim3(P), dim3(256), 0, st,
+            hipLaunchKernelGGL((k_pair_eig<T, JB>), dim3(P), dim3(kEigThreads), 0, st,
                                (const double2*)w.gram_partials, splits, tol, zrel2, fro2, inner_max,
                                (C2<T>*)w.w, w.skip, w.info);
             pf.end(st, K_EIG, 0.0, (double)P * splits * NB * NB * 16.0);
