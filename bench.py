@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "2q-gate MPO updates/sec at chi=1024 (FP32-MFMA vs FP64) + entropy err vs oracle"
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}   # dense MFMA (= vector) peaks of MI355X
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12,   # dense MFMA (= vector) peaks of MI355X
+        "bf16x3": 2.5e15}                      # BF16 dense MFMA peak
 HBM_PEAK = 8.0e12
 
 
@@ -206,7 +207,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precisions", default="fp32,fp64")
+    ap.add_argument("--precisions", default="fp32,fp64,bf16x3")
     ap.add_argument("--save-snapshot", default=None, help="write the in-situ snapshot to this file")
     ap.add_argument("--load-snapshot", default=None, help="reuse a snapshot written by --save-snapshot")
     ap.add_argument("--no-batch", action="store_true")
@@ -278,12 +279,17 @@ def main():
                    "bond_dims": dims},
         "roofline": rl,
     }
+    for other, dt_name in (("fp64", "f64"), ("bf16x3", "f32 storage, split-bf16x3 products")):
+        if other in res and other != head:
+            out[other] = {"value": args.steps / res[other]["seconds"],
+                          "ms_per_step": 1e3 * res[other]["seconds"] / args.steps, "dtype": dt_name,
+                          "roofline": roofline(res[other]["prof"], other)[1]}
     if "fp64" in res:
-        out["fp64"] = {"value": args.steps / res["fp64"]["seconds"],
-                       "ms_per_step": 1e3 * res["fp64"]["seconds"] / args.steps, "dtype": "f64"}
-    if "fp64" in res and "fp32" in res:
-        out["entropy_error"] = {"fp32_vs_fp64_max_abs": float(np.abs(res["fp32"]["entropy"] -
-                                                                     res["fp64"]["entropy"]).max())}
+        err = out.setdefault("entropy_error", {})
+        for prec in res:
+            if prec != "fp64":
+                err[f"{prec}_vs_fp64_max_abs"] = float(np.abs(res[prec]["entropy"] -
+                                                              res["fp64"]["entropy"]).max())
     out["kernels"] = {k: {kk: vv for kk, vv in v["prof"]["kernels"].items() if vv["launches"]}
                       for k, v in res.items()}
     out["svd"] = {k: v["prof"]["svd"] for k, v in res.items()}

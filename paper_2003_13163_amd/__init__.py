@@ -18,14 +18,15 @@ import os
 import numpy as np
 
 __all__ = ["MpoError", "TruncInfo", "Mpo", "build_superop", "build_superops", "library",
-           "FP64", "FP32_MFMA", "PAULI", "COMPUTATIONAL", "n_schedule_gates"]
+           "FP64", "FP32_MFMA", "BF16X3", "PAULI", "COMPUTATIONAL", "n_schedule_gates"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmpo.so")
 
-FP64, FP32_MFMA = 0, 1
+FP64, FP32_MFMA, BF16X3 = 0, 1, 2
 PAULI, COMPUTATIONAL = 0, 1
-_PREC = {"fp64": FP64, "fp32": FP32_MFMA, "fp32_mfma": FP32_MFMA, FP64: FP64, FP32_MFMA: FP32_MFMA}
+_PREC = {"fp64": FP64, "fp32": FP32_MFMA, "fp32_mfma": FP32_MFMA, "bf16x3": BF16X3,
+         FP64: FP64, FP32_MFMA: FP32_MFMA, BF16X3: BF16X3}
 _BASIS = {"pauli": PAULI, "computational": COMPUTATIONAL, PAULI: PAULI, COMPUTATIONAL: COMPUTATIONAL}
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_ARENA", 3: "ERR_HIP", 4: "ERR_NUMERIC",
            5: "ERR_NOCONV", 6: "ERR_STATE"}

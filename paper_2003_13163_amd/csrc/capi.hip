@@ -104,6 +104,7 @@ struct mpo_handle {
     mpo_basis basis = MPO_BASIS_PAULI;
     hipStream_t st = nullptr;
     size_t csz = 16;
+    bool bf3 = false;            // split-BF16x3 products on FP32 storage
     std::vector<char*> slot;     // slot base addresses
     std::vector<int> site_slot;  // slot index of every site
     std::vector<int> spare;      // free slot indices
@@ -139,13 +140,19 @@ double eps_of(size_t csz) { return csz == 16 ? 2.220446049250313e-16 : 1.1920928
 // the Gram rounding sqrt(m) eps.  FP32: the Gram slabs are summed in FP64, so
 // the off-diagonal noise is about eps32 * sqrt(slab) / sqrt(slabs); 2e-6 keeps
 // the isometries orthonormal well below the 1e-4 entropy target.
+// Split-BF16x3: every product term carries a relative error up to about
+// 2^-15, so the off-diagonal measure has noise up to about 3e-5; 1e-4 is
+// reachable and keeps the rotations' own error (2^-16 per update) below it.
 double jacobi_tol(const mpo_handle* h, int m) {
     if (h->csz == 16) return std::fmax(1e-14, 8.0 * std::sqrt((double)m) * eps_of(h->csz));
-    return 2e-6;
+    return h->bf3 ? 1e-4 : 2e-6;
 }
 // singular values at or below this fraction of ||lambda||_2 carry no weight
 // above rounding and are dropped by exact re-gauging moves
-double regauge_cut(const mpo_handle* h) { return h->csz == 16 ? 1e-15 : 1e-7; }
+double regauge_cut(const mpo_handle* h) {
+    if (h->bf3) return std::sqrt(kZeroRel2Bf3);
+    return h->csz == 16 ? 1e-15 : 1e-7;
+}
 
 // Site dual vectors v[J] = Tr[P B_J] for the basis operators B_J.
 void dual_vector(mpo_basis basis, int code, double2 v[4]) {
@@ -193,7 +200,8 @@ struct Engine {
         if (sw == -3) throw HipError{hipErrorInvalidValue, "jacobi pair capacity"};
         if (sw < 0) throw NoConvError{"one-sided Jacobi SVD did not converge"};
         h->prof.begin(h->st);
-        launch_truncate(h->jw.sig2, N, chi_max, cutoff, jacobi_zero_rel2<T>(), h->jw.info, h->st);
+        launch_truncate(h->jw.sig2, N, chi_max, cutoff,
+                        h->bf3 ? kZeroRel2Bf3 : jacobi_zero_rel2<T>(), h->jw.info, h->st);
         h->prof.end(h->st, K_TRUNC, 0.0, 8.0 * N);
         HIPCHK(hipGetLastError());
         DevInfo inf = read_info(h);
@@ -217,8 +225,8 @@ struct Engine {
         launch_gather_cols<T>((C*)h->X, m, h->jw.colmap, h->jw.sig2, r, U, m, h->st);
         h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * r);
         h->prof.begin(h->st);
-        launch_cgemm<T>(1, 0, r, chiR, m, U, m, site(h, c), m, (C*)h->R, r, h->st);
-        launch_cgemm<T>(0, 0, r, 4 * chiR2, chiR, (C*)h->R, r, site(h, c + 1), chiR, Anext, r, h->st);
+        launch_cgemm<T>(1, 0, r, chiR, m, U, m, site(h, c), m, (C*)h->R, r, h->st, h->bf3);
+        launch_cgemm<T>(0, 0, r, 4 * chiR2, chiR, (C*)h->R, r, site(h, c + 1), chiR, Anext, r, h->st, h->bf3);
         h->prof.end(h->st, K_GEMM, 8.0 * r * chiR * m + 8.0 * r * 4.0 * chiR2 * chiR,
                     (double)sizeof(C) * (2.0 * m * chiR + (double)m * r + 8.0 * chiR * chiR2 + 4.0 * r * chiR2));
         HIPCHK(hipGetLastError());
@@ -255,9 +263,9 @@ struct Engine {
         launch_gather_rows_conj<T>((C*)h->X, m, h->jw.colmap, h->jw.sig2, r, Q, h->st);
         h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * r);
         h->prof.begin(h->st);
-        launch_cgemm<T>(0, 1, chiL, r, m, site(h, c), chiL, Q, r, (C*)h->R, chiL, h->st);
+        launch_cgemm<T>(0, 1, chiL, r, m, site(h, c), chiL, Q, r, (C*)h->R, chiL, h->st, h->bf3);
         launch_cgemm<T>(0, 0, 4 * chiLL, r, chiL, site(h, c - 1), 4 * chiLL, (C*)h->R, chiL, Aprev,
-                        4 * chiLL, h->st);
+                        4 * chiLL, h->st, h->bf3);
         h->prof.end(h->st, K_GEMM, 8.0 * chiL * r * m + 8.0 * 4.0 * chiLL * r * chiL,
                     (double)sizeof(C) * ((double)chiL * m + (double)r * m + 8.0 * chiLL * chiL + 4.0 * chiLL * r));
         HIPCHK(hipGetLastError());
@@ -282,7 +290,7 @@ struct Engine {
         const int m = 4 * chiL, N = 4 * chiR;
         h->prof.begin(h->st);
         launch_theta_channel<T>(chiL, chiM, chiR, site(h, s), site(h, s + 1), Mg, (C*)h->X,
-                                (C*)h->X2, h->st);
+                                (C*)h->X2, h->st, h->bf3);
         h->prof.end(h->st, K_THETA, 8.0 * m * chiM * N + 2048.0 * chiL * chiR,
                     (double)sizeof(C) * (4.0 * chiL * chiM + 4.0 * chiM * chiR + 2.0 * m * N));
         HIPCHK(hipGetLastError());
@@ -293,7 +301,7 @@ struct Engine {
         launch_gather_cols<T>((C*)h->X, m, h->jw.colmap, h->jw.sig2, k, site(h, s), m, h->st);
         h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * k);
         h->prof.begin(h->st);
-        launch_cgemm<T>(1, 0, k, N, m, site(h, s), m, (C*)h->X2, m, site(h, s + 1), k, h->st);
+        launch_cgemm<T>(1, 0, k, N, m, site(h, s), m, (C*)h->X2, m, site(h, s + 1), k, h->st, h->bf3);
         h->prof.end(h->st, K_GEMM, 8.0 * k * N * m, (double)sizeof(C) * ((double)m * k + (double)m * N + (double)k * N));
         HIPCHK(hipGetLastError());
         h->dims[s] = k;
@@ -521,14 +529,14 @@ struct Adjoint {
     // S_q from S_{q+1}: S_q[c, c'] = sum conj(lam[c', I, d']) rho[c, I, d] S_{q+1}[d, d']
     static void right_step(mpo_handle* h, const C* rho, int rl, int rr, const C* lam, int ll, int lr,
                            const C* Sin, C* Sout, C* Y) {
-        launch_cgemm<T>(0, 0, 4 * rl, lr, rr, rho, 4 * rl, Sin, rr, Y, 4 * rl, h->st);
-        launch_cgemm<T>(0, 1, rl, ll, 4 * lr, Y, rl, lam, ll, Sout, rl, h->st);
+        launch_cgemm<T>(0, 0, 4 * rl, lr, rr, rho, 4 * rl, Sin, rr, Y, 4 * rl, h->st, h->bf3);
+        launch_cgemm<T>(0, 1, rl, ll, 4 * lr, Y, rl, lam, ll, Sout, rl, h->st, h->bf3);
     }
     // E_{q+1}[a', b'] = sum conj(phi[a, I, a']) E_q[a, b] mu[b, I, b']
     static void left_step(mpo_handle* h, const C* phi, int pl, int pr, const C* mu, int ml, int mr,
                           const C* Ein, C* Eout, C* Y) {
-        launch_cgemm<T>(0, 0, pl, 4 * mr, ml, Ein, pl, mu, ml, Y, pl, h->st);
-        launch_cgemm<T>(1, 0, pr, mr, 4 * pl, phi, 4 * pl, Y, 4 * pl, Eout, pr, h->st);
+        launch_cgemm<T>(0, 0, pl, 4 * mr, ml, Ein, pl, mu, ml, Y, pl, h->st, h->bf3);
+        launch_cgemm<T>(1, 0, pr, mr, 4 * pl, phi, 4 * pl, Y, 4 * pl, Eout, pr, h->st, h->bf3);
     }
 
     static void set_one(mpo_handle* h, C* dst) {
@@ -672,7 +680,7 @@ struct Adjoint {
             {
                 const int k = tp.post_dims[sm], ml = mu->chiL(sm + 1), mr = mu->chiR(sm + 1);
                 const int sl = mu->take_spare();
-                launch_cgemm<T>(0, 0, k, 4 * mr, ml, Ea, k, E::site(mu, sm + 1), ml, (C*)mu->slot[sl], k, h->st);
+                launch_cgemm<T>(0, 0, k, 4 * mr, ml, Ea, k, E::site(mu, sm + 1), ml, (C*)mu->slot[sl], k, h->st, h->bf3);
                 mu->give_spare(mu->site_slot[sm + 1]);
                 mu->site_slot[sm + 1] = sl;
                 for (int q = 0; q <= sm; ++q)
@@ -694,10 +702,10 @@ struct Adjoint {
                 const int ca = mu->chiL(s), cb = mu->dims[s], cc = mu->chiR(s + 1);
                 if (ca != tp.cen_l[j]) throw HipError{hipErrorInvalidValue, "adjoint bond mismatch"};
                 // theta_lambda and Theta = theta_rho contracted with the right environment
-                launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1), Id, THL, nullptr, h->st);
+                launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1), Id, THL, nullptr, h->st, h->bf3);
                 const int rs = tp.cen_r[j], rr = pre_r(s + 1);
-                launch_cgemm<T>(0, 0, 4 * rs, cc, rr, tp.pre[s + 1], 4 * rs, Sa, rr, T1, 4 * rs, h->st);
-                launch_cgemm<T>(0, 0, 4 * ca, 4 * cc, rs, tp.cen[j], 4 * ca, T1, rs, TH, 4 * ca, h->st);
+                launch_cgemm<T>(0, 0, 4 * rs, cc, rr, tp.pre[s + 1], 4 * rs, Sa, rr, T1, 4 * rs, h->st, h->bf3);
+                launch_cgemm<T>(0, 0, 4 * ca, 4 * cc, rs, tp.cen[j], 4 * ca, T1, rs, TH, 4 * ca, h->st, h->bf3);
                 launch_local_grad<T>(THL, TH, ca, cc, gdev, h->st);
                 HIPCHK(hipMemcpyAsync(grads + (size_t)g * 512, gdev, 256 * sizeof(double2), hipMemcpyDeviceToHost, h->st));
                 // mu <- M^H lambda on (s, s+1).  The co-state needs no canonical
@@ -709,19 +717,19 @@ struct Adjoint {
                 if (m <= L.chi_mu) {
                     const int sl = mu->take_spare();
                     launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1),
-                                            MH + (size_t)g * 256, (C*)mu->slot[sl], nullptr, h->st);
+                                            MH + (size_t)g * 256, (C*)mu->slot[sl], nullptr, h->st, h->bf3);
                     launch_identity_site<T>(E::site(mu, s), ca, h->st);
                     mu->give_spare(mu->site_slot[s + 1]);
                     mu->site_slot[s + 1] = sl;
                     r = m;
                 } else {
                     launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1),
-                                            MH + (size_t)g * 256, (C*)mu->X, (C*)mu->X2, h->st);
+                                            MH + (size_t)g * 256, (C*)mu->X, (C*)mu->X2, h->st, h->bf3);
                     HIPCHK(hipGetLastError());
                     DevInfo inf = E::split(mu, m, N, L.chi_mu, regauge_cut(mu));
                     r = inf.kept;
                     launch_gather_cols<T>((C*)mu->X, m, mu->jw.colmap, mu->jw.sig2, r, E::site(mu, s), m, h->st);
-                    launch_cgemm<T>(1, 0, r, N, m, E::site(mu, s), m, (C*)mu->X2, m, E::site(mu, s + 1), r, h->st);
+                    launch_cgemm<T>(1, 0, r, N, m, E::site(mu, s), m, (C*)mu->X2, m, E::site(mu, s + 1), r, h->st, h->bf3);
                 }
                 co_max = std::max(co_max, r);
                 mu->dims[s] = r;
@@ -787,7 +795,8 @@ mpo_status mpo_workspace_bytes(int n, int chi_cap, mpo_precision prec, size_t* b
     if (!bytes) return fail(MPO_ERR_ARG, "bytes is NULL");
     if (n < 2 || (n & 1)) return fail(MPO_ERR_ARG, "n must be even and >= 2 (got %d)", n);
     if (chi_cap < 1 || chi_cap > 1024) return fail(MPO_ERR_ARG, "chi_cap must be in [1, 1024] (got %d)", chi_cap);
-    if (prec != MPO_FP64 && prec != MPO_FP32_MFMA) return fail(MPO_ERR_ARG, "unknown precision %d", (int)prec);
+    if (prec != MPO_FP64 && prec != MPO_FP32_MFMA && prec != MPO_BF16X3)
+        return fail(MPO_ERR_ARG, "unknown precision %d", (int)prec);
     *bytes = make_layout(n, chi_cap, prec).total;
     return MPO_OK;
 }
@@ -812,6 +821,7 @@ mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis, v
     h->basis = basis;
     h->st = (hipStream_t)hip_stream;
     h->csz = prec == MPO_FP64 ? 16 : 8;
+    h->bf3 = prec == MPO_BF16X3;
     const Layout L = make_layout(n, chi_cap, prec);
     char* p = (char*)dev_arena;
     h->slot.resize(L.slots);
@@ -832,8 +842,11 @@ mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis, v
     h->jw.max_pairs = L.max_pairs;
     h->jw.splits = kSplitsMax;
     h->jw.prof = &h->prof;
+    h->jw.bf3 = h->bf3;
     h->jw.block = 16;
-    h->jw.inner = 2;
+    // one inner sweep per block pair is the faster setting wherever the outer
+    // tolerance is loose (FP32, BF16x3); FP64 gains nothing from it
+    h->jw.inner = prec == MPO_FP64 ? 2 : 1;
     if (const char* e = std::getenv("MPO_JACOBI_BLOCK")) h->jw.block = std::atoi(e) == 16 ? 16 : 32;
     if (const char* e = std::getenv("MPO_JACOBI_INNER")) h->jw.inner = std::max(1, std::min(8, std::atoi(e)));
     h->envL = (double2*)p; p += L.env_bytes;

@@ -34,6 +34,61 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// ------------------------------------------------------------ split-BF16x3
+// An FP32 value x is carried as hi + lo with hi = bf16(x) and lo = bf16(x - hi)
+// (round to nearest even; x - hi is exact in FP32), i.e. about 16 significant
+// bits.  A real product a*b is taken as ah*bh + ah*bl + al*bh (the al*bl term,
+// of relative size 2^-16, is dropped) on the BF16 MFMA with FP32 accumulation.
+// v_mfma_f32_16x16x16_bf16 layout (wave64, checked on gfx950): lane l supplies
+// A[l%16][4(l/16)+j] and B[4(l/16)+j][l%16], j = 0..3; the result layout is
+// that of the FP32 16x16x4 product.
+typedef short bf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned bf16_bits(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Four complex FP32 values (k = 0..3 of one row or column) as BF16 hi/lo parts
+// of the real and imaginary components; conj negates the imaginary parts.
+struct CBF { bf4 rh, rl, ih, il; };
+
+__device__ __forceinline__ CBF cbf_split(const float2 (&v)[4], bool conj) {
+    CBF o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float re = v[j].x, im = conj ? -v[j].y : v[j].y;
+        const unsigned rh = bf16_bits(re), ih = bf16_bits(im);
+        o.rh[j] = (short)rh;
+        o.ih[j] = (short)ih;
+        o.rl[j] = (short)bf16_bits(re - __uint_as_float(rh << 16));
+        o.il[j] = (short)bf16_bits(im - __uint_as_float(ih << 16));
+    }
+    return o;
+}
+
+__device__ __forceinline__ f4 mfma_bf16(bf4 a, bf4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// (accR, accI) += A * B for one 16x16x16 complex tile product, 12 BF16 MFMAs.
+__device__ __forceinline__ void cmfma_bf3(f4& accR, f4& accI, const CBF& a, const CBF& b) {
+    const bf4 sign = {(short)0x8000, (short)0x8000, (short)0x8000, (short)0x8000};
+    const bf4 nih = a.ih ^ sign, nil = a.il ^ sign;
+    accR = mfma_bf16(a.rl, b.rh, accR);
+    accR = mfma_bf16(a.rh, b.rl, accR);
+    accR = mfma_bf16(nil, b.ih, accR);
+    accR = mfma_bf16(nih, b.il, accR);
+    accR = mfma_bf16(a.rh, b.rh, accR);
+    accR = mfma_bf16(nih, b.ih, accR);
+    accI = mfma_bf16(a.rl, b.ih, accI);
+    accI = mfma_bf16(a.rh, b.il, accI);
+    accI = mfma_bf16(a.il, b.rh, accI);
+    accI = mfma_bf16(a.ih, b.rl, accI);
+    accI = mfma_bf16(a.rh, b.ih, accI);
+    accI = mfma_bf16(a.ih, b.rh, accI);
+}
+
 template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);
 template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
 template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
@@ -72,15 +127,16 @@ struct DevInfo {
 // ----------------------------------------------------------------- launchers
 // Column-major storage everywhere.  op = 0: as stored; op = 1: conjugate transpose.
 namespace mpo {
+// bf3 selects the split-BF16x3 products (FP32 storage only).
 template <typename T>
 void launch_cgemm(int opa, int opb, int M, int N, int K, const C2<T>* A, int lda,
-                  const C2<T>* B, int ldb, C2<T>* C, int ldc, hipStream_t st);
+                  const C2<T>* B, int ldb, C2<T>* C, int ldc, hipStream_t st, bool bf3 = false);
 
 // X[(a + chiL*I) + m*(J + 4c)] = sum M[4I+J][4I'+J'] * theta[(I',a),(J',c)],
 // theta = L(As) * R(Bs); also written to X2 when non-null.
 template <typename T>
 void launch_theta_channel(int chiL, int chiM, int chiR, const C2<T>* As, const C2<T>* Bs,
-                          const C2<T>* Mdev, C2<T>* X, C2<T>* X2, hipStream_t st);
+                          const C2<T>* Mdev, C2<T>* X, C2<T>* X2, hipStream_t st, bool bf3 = false);
 
 struct JacobiWork {
     void* gram_partials;   // P_max * splits * 64*64 complex (T)
@@ -96,6 +152,7 @@ struct JacobiWork {
     Profiler* prof;        // may be off
     int block;             // Jacobi block width: 16 or 32 columns
     int inner;             // inner FP64 sweeps per block pair
+    bool bf3;              // Gram and rotations as split-BF16x3 products (FP32 storage)
     long long n_splits, n_sweeps, n_rounds, n_rotations;   // running counters
 };
 
@@ -111,6 +168,7 @@ int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps,
 // rounding floor of the working precision: the sweep never rotates them and
 // the truncation never keeps them.
 template <typename T> constexpr double jacobi_zero_rel2() { return sizeof(T) == 8 ? 1e-30 : 1e-14; }
+constexpr double kZeroRel2Bf3 = 1e-9;   // the same floor for split-BF16x3 products
 
 // Truncation + entropy from the sorted squared norms (single work-group).
 void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,

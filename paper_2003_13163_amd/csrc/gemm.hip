@@ -41,6 +41,36 @@ __device__ __forceinline__ void mma_tile(const C2<T> (*As)[BM + 1], const C2<T> 
     }
 }
 
+// The same 64x64 tile with split-BF16x3 products: one K = 16 step per call.
+__device__ __forceinline__ void mma_tile_bf3(const float2 (*As)[BM + 1], const float2 (*Bs)[BN + 1],
+                                             int lane, int wm, int wn, f4 (&accR)[2][2],
+                                             f4 (&accI)[2][2]) {
+    CBF a[2], b[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        float2 va[4], vb[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            va[j] = As[4 * (lane >> 4) + j][wm * 32 + q * 16 + (lane & 15)];
+            vb[j] = Bs[4 * (lane >> 4) + j][wn * 32 + q * 16 + (lane & 15)];
+        }
+        a[q] = cbf_split(va, false);
+        b[q] = cbf_split(vb, false);
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) cmfma_bf3(accR[bi][bj], accI[bi][bj], a[bi], b[bj]);
+}
+
+template <typename T, bool BF>
+__device__ __forceinline__ void mma_step(const C2<T> (*As)[BM + 1], const C2<T> (*Bs)[BN + 1],
+                                         int lane, int wm, int wn, A4<T> (&accR)[2][2],
+                                         A4<T> (&accI)[2][2]) {
+    if constexpr (BF) mma_tile_bf3(As, Bs, lane, wm, wn, accR, accI);
+    else mma_tile<T>(As, Bs, lane, wm, wn, accR, accI);
+}
+
 template <typename T>
 __device__ __forceinline__ void zero_acc(A4<T> (&accR)[2][2], A4<T> (&accI)[2][2]) {
 #pragma unroll
@@ -52,7 +82,7 @@ __device__ __forceinline__ void zero_acc(A4<T> (&accR)[2][2], A4<T> (&accI)[2][2
 }
 
 // C (M x N) = op(A) (M x K) * op(B) (K x N); op 0 = as stored, 1 = conj-transpose.
-template <typename T, int OPA, int OPB>
+template <typename T, int OPA, int OPB, bool BF>
 __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, const C2<T>* __restrict__ A,
                                                int lda, const C2<T>* __restrict__ B, int ldb,
                                                C2<T>* __restrict__ Cm, int ldc) {
@@ -87,7 +117,7 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, const C2<T>*
             Bs[k][j] = v;
         }
         __syncthreads();
-        mma_tile<T>(As, Bs, lane, wm, wn, accR, accI);
+        mma_step<T, BF>(As, Bs, lane, wm, wn, accR, accI);
         __syncthreads();
     }
 #pragma unroll
@@ -103,24 +133,33 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, const C2<T>*
             }
 }
 
+template <typename T, bool BF>
+static void cgemm_dispatch(int opa, int opb, dim3 grid, int M, int N, int K, const C2<T>* A, int lda,
+                           const C2<T>* B, int ldb, C2<T>* C, int ldc, hipStream_t st) {
+    if (opa == 0 && opb == 0)
+        hipLaunchKernelGGL((k_cgemm<T, 0, 0, BF>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+    else if (opa == 1 && opb == 0)
+        hipLaunchKernelGGL((k_cgemm<T, 1, 0, BF>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+    else if (opa == 0 && opb == 1)
+        hipLaunchKernelGGL((k_cgemm<T, 0, 1, BF>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+    else
+        hipLaunchKernelGGL((k_cgemm<T, 1, 1, BF>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+}
+
 template <typename T>
 void launch_cgemm(int opa, int opb, int M, int N, int K, const C2<T>* A, int lda,
-                  const C2<T>* B, int ldb, C2<T>* C, int ldc, hipStream_t st) {
+                  const C2<T>* B, int ldb, C2<T>* C, int ldc, hipStream_t st, bool bf3) {
     if (M <= 0 || N <= 0) return;
     dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN);
-    if (opa == 0 && opb == 0)
-        hipLaunchKernelGGL((k_cgemm<T, 0, 0>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
-    else if (opa == 1 && opb == 0)
-        hipLaunchKernelGGL((k_cgemm<T, 1, 0>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
-    else if (opa == 0 && opb == 1)
-        hipLaunchKernelGGL((k_cgemm<T, 0, 1>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
-    else
-        hipLaunchKernelGGL((k_cgemm<T, 1, 1>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc);
+    if constexpr (sizeof(T) == 4) {
+        if (bf3) { cgemm_dispatch<T, true>(opa, opb, grid, M, N, K, A, lda, B, ldb, C, ldc, st); return; }
+    }
+    cgemm_dispatch<T, false>(opa, opb, grid, M, N, K, A, lda, B, ldb, C, ldc, st);
 }
 
 // One work-group owns 16 left-bond values a and 16 right-bond values c, i.e.
 // the 64 theta rows (I, a) and 64 columns (c, J) that the channel couples.
-template <typename T>
+template <typename T, bool BF>
 __global__ __launch_bounds__(256) void k_theta_channel(int chiL, int chiM, int chiR,
                                                        const C2<T>* __restrict__ As_g,
                                                        const C2<T>* __restrict__ Bs_g,
@@ -157,7 +196,7 @@ __global__ __launch_bounds__(256) void k_theta_channel(int chiL, int chiM, int c
             Bs[k][j] = v;
         }
         __syncthreads();
-        mma_tile<T>(As, Bs, lane, wm, wn, accR, accI);
+        mma_step<T, BF>(As, Bs, lane, wm, wn, accR, accI);
         __syncthreads();
     }
 #pragma unroll
@@ -197,19 +236,26 @@ __global__ __launch_bounds__(256) void k_theta_channel(int chiL, int chiM, int c
 
 template <typename T>
 void launch_theta_channel(int chiL, int chiM, int chiR, const C2<T>* As, const C2<T>* Bs,
-                          const C2<T>* Mdev, C2<T>* X, C2<T>* X2, hipStream_t st) {
+                          const C2<T>* Mdev, C2<T>* X, C2<T>* X2, hipStream_t st, bool bf3) {
     dim3 grid((chiL + 15) / 16, (chiR + 15) / 16);
-    hipLaunchKernelGGL((k_theta_channel<T>), grid, dim3(256), 0, st, chiL, chiM, chiR, As, Bs,
+    if constexpr (sizeof(T) == 4) {
+        if (bf3) {
+            hipLaunchKernelGGL((k_theta_channel<T, true>), grid, dim3(256), 0, st, chiL, chiM, chiR,
+                               As, Bs, Mdev, X, X2);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_theta_channel<T, false>), grid, dim3(256), 0, st, chiL, chiM, chiR, As, Bs,
                        Mdev, X, X2);
 }
 
 template void launch_cgemm<double>(int, int, int, int, int, const double2*, int, const double2*,
-                                   int, double2*, int, hipStream_t);
+                                   int, double2*, int, hipStream_t, bool);
 template void launch_cgemm<float>(int, int, int, int, int, const float2*, int, const float2*, int,
-                                  float2*, int, hipStream_t);
+                                  float2*, int, hipStream_t, bool);
 template void launch_theta_channel<double>(int, int, int, const double2*, const double2*,
-                                           const double2*, double2*, double2*, hipStream_t);
+                                           const double2*, double2*, double2*, hipStream_t, bool);
 template void launch_theta_channel<float>(int, int, int, const float2*, const float2*,
-                                          const float2*, float2*, float2*, hipStream_t);
+                                          const float2*, float2*, float2*, hipStream_t, bool);
 
 }  // namespace mpo

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(1024) void k_sort_desc(const double* __restrict__ n
 // wave takes a quarter of every staged slab of rows and accumulates all upper
 // tiles (TB column tiles loaded once per 4-row step feed TB(TB+1)/2 complex MFMA
 // products), slab sums are added in FP64 and the four waves are reduced in LDS.
-template <typename T, int JB>
+template <typename T, int JB, bool BF>
 __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, int m, int N,
                                                    const int* __restrict__ colmap, int nb,
                                                    int round, int splits, int chunk,
@@ -151,6 +151,27 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
         for (int u = 0; u < NU; ++u)
 #pragma unroll
             for (int r = 0; r < 4; ++r) { accR[u][r] = T(0); accI[u][r] = T(0); }
+        if constexpr (BF) {
+            for (int kk = wave * RW; kk < (wave + 1) * RW; kk += 16) {
+                const bf4 sign = {(short)0x8000, (short)0x8000, (short)0x8000, (short)0x8000};
+                CBF xb[TB], xa[TB];        // x and conj(x), rows kk + 4(l/16) + j
+#pragma unroll
+                for (int b = 0; b < TB; ++b) {
+                    float2 v[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j] = Xs[kk + 4 * (lane >> 4) + j][b * 16 + (lane & 15)];
+                    xb[b] = cbf_split(v, false);
+                    xa[b] = xb[b];
+                    xa[b].ih = xb[b].ih ^ sign;
+                    xa[b].il = xb[b].il ^ sign;
+                }
+                int u = 0;
+#pragma unroll
+                for (int bi = 0; bi < TB; ++bi)
+#pragma unroll
+                    for (int bj = bi; bj < TB; ++bj, ++u) cmfma_bf3(accR[u], accI[u], xa[bi], xb[bj]);
+            }
+        } else
 #pragma unroll 2
         for (int kk = wave * RW; kk < (wave + 1) * RW; kk += 4) {
             C2<T> x[TB];
@@ -476,7 +497,7 @@ __global__ __launch_bounds__(kEigThreads) void k_pair_eig(const double2* __restr
 // ------------------------------------------------------------- pair update
 constexpr int kUpdateSlabs = 4;   // 64-row slabs per work-group
 // [x_p x_q] <- [x_p x_q] W for one 64-row slab of the pair's NB columns.
-template <typename T, int JB>
+template <typename T, int JB, bool BF>
 __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int m, int N,
                                                      const int* __restrict__ colmap, int nb,
                                                      int round, const C2<T>* __restrict__ Wm,
@@ -538,6 +559,29 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
             for (int bj = 0; bj < MB; ++bj)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
+        if constexpr (BF) {
+            for (int kk = 0; kk < NB; kk += 16) {
+                CBF a[2], b[MB];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    float2 v[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j] = Xt[kk + 4 * (lane >> 4) + j][wm * 32 + s * 16 + (lane & 15)];
+                    a[s] = cbf_split(v, false);
+                }
+#pragma unroll
+                for (int s = 0; s < MB; ++s) {
+                    float2 v[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j] = Ws[kk + 4 * (lane >> 4) + j][wn * (NB / 2) + s * 16 + (lane & 15)];
+                    b[s] = cbf_split(v, false);
+                }
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < MB; ++bj) cmfma_bf3(accR[bi][bj], accI[bi][bj], a[bi], b[bj]);
+            }
+        } else
 #pragma unroll 4
         for (int kk = 0; kk < NB; kk += 4) {
             C2<T> a[2], b[MB];
@@ -734,7 +778,7 @@ __global__ void k_copy(const C2<T>* __restrict__ s, C2<T>* __restrict__ d, size_
 }
 
 // ------------------------------------------------------------------- host side
-template <typename T, int JB>
+template <typename T, int JB, bool BF>
 static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int inner_max,
                       JacobiWork& w, hipStream_t st) {
     constexpr int NB = 2 * JB;
@@ -750,7 +794,7 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
     chunk = (chunk + RB - 1) / RB * RB;
     splits = (m + chunk - 1) / chunk;
     if (splits < 1) splits = 1;
-    const double zrel2 = jacobi_zero_rel2<T>();
+    const double zrel2 = BF ? kZeroRel2Bf3 : jacobi_zero_rel2<T>();
     double* fro2 = &w.info->total;   // scratch slot reused for ||X||_F^2
     const dim3 gnorm((N + 3) / 4);
     Profiler& pf = *w.prof;
@@ -766,7 +810,7 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
         (void)hipMemsetAsync(&w.info->offmax_bits, 0, sizeof(unsigned long long) + 2 * sizeof(int), st);
         for (int r = 0; r < nb - 1; ++r) {
             pf.begin(st);
-            hipLaunchKernelGGL((k_pair_gram<T, JB>), dim3(P, splits), dim3(256), 0, st, X, m, N,
+            hipLaunchKernelGGL((k_pair_gram<T, JB, BF>), dim3(P, splits), dim3(256), 0, st, X, m, N,
                                w.colmap, nb, r, splits, chunk, (double2*)w.gram_partials);
             pf.end(st, K_GRAM, P * pair_flops, P * pair_bytes + (double)P * splits * NB * NB * 16.0);
             pf.begin(st);
@@ -775,7 +819,7 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
                                (C2<T>*)w.w, w.skip, w.info);
             pf.end(st, K_EIG, 0.0, (double)P * splits * NB * NB * 16.0);
             pf.begin(st);
-            hipLaunchKernelGGL((k_pair_update<T, JB>), dim3(P, (m + 64 * kUpdateSlabs - 1) / (64 * kUpdateSlabs)), dim3(256), 0, st, X, m,
+            hipLaunchKernelGGL((k_pair_update<T, JB, BF>), dim3(P, (m + 64 * kUpdateSlabs - 1) / (64 * kUpdateSlabs)), dim3(256), 0, st, X, m,
                                N, w.colmap, nb, r, (const C2<T>*)w.w, w.skip);
             pf.end(st, K_UPDATE, 0.0, 0.0);
         }
@@ -807,8 +851,14 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
 template <typename T>
 int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, JacobiWork& w,
                          hipStream_t st) {
-    if (w.block == 16) return jacobi_run<T, 16>(X, m, N, tol, max_sweeps, w.inner, w, st);
-    return jacobi_run<T, 32>(X, m, N, tol, max_sweeps, w.inner, w, st);
+    if constexpr (sizeof(T) == 4) {
+        if (w.bf3) {
+            if (w.block == 16) return jacobi_run<T, 16, true>(X, m, N, tol, max_sweeps, w.inner, w, st);
+            return jacobi_run<T, 32, true>(X, m, N, tol, max_sweeps, w.inner, w, st);
+        }
+    }
+    if (w.block == 16) return jacobi_run<T, 16, false>(X, m, N, tol, max_sweeps, w.inner, w, st);
+    return jacobi_run<T, 32, false>(X, m, N, tol, max_sweeps, w.inner, w, st);
 }
 
 void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,

@@ -1,7 +1,8 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
 Tolerances: FP64 mode |dS| <= 1e-10 and |d<Z>| <= 1e-6 (the stated targets
-for entropies and expectation values); FP32-MFMA mode |dS| <= 1e-4.  Raw
+for entropies and expectation values); FP32-MFMA mode |dS| <= 1e-4;
+split-BF16x3 mode as derived beside its constants below.  Raw
 tensors are compared only through gauge-invariant quantities (dense states,
 singular values, entropies, expectation values).
 """
@@ -18,6 +19,15 @@ from oracle import dense, gates, mpo as omp
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+
+# Split-BF16x3 carries about 16 significant bits: a product term is off by up
+# to about 2^-15 = 3e-5 relative, and one truncated gate applies the
+# two-site product, the channel and some 15 sweeps of Jacobi rotations, so a
+# gate moves the state by about sqrt(15) * 1.5e-5 = 6e-5.  One bulk gate is
+# held to 2e-4 (entropy, and singular values relative to the largest); the
+# 32 gates of the n = 8 circuit, adding up at worst linearly, to 2e-3.
+BF3_GATE_TOL = 2e-4
+BF3_CIRCUIT_TOL = 2e-3
 
 
 @pytest.fixture(scope="module")
@@ -77,20 +87,21 @@ def test_n8_exact_fp64_vs_dense(pm, basis):
     st.close()
 
 
-def test_n8_exact_fp32_vs_dense(pm):
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16x3", BF3_CIRCUIT_TOL)])
+def test_n8_exact_reduced_precision_vs_dense(pm, prec, tol):
     n, depth, p = 8, 8, 0.02
-    say("case n8 exact fp32")
+    say(f"case n8 exact {prec}")
     draws = mi.ginibre_draws(n, depth, seed=0)
     sup = pm.build_superops(draws, p, "pauli")
-    st = pm.Mpo(n, 256, "fp32", "pauli")
+    st = pm.Mpo(n, 256, prec, "pauli")
     res = st.run_brickwork(depth, sup, 256, 1e-12, record="all")
     _, s_ref, z_ref, _ = dense.run_dense(n, depth, gates.circuit_superops(draws, p, "computational"),
                                          mi.brickwork_sites(n, depth))
     dS = np.abs(res["S"] - s_ref).max()
     dZ = np.abs(res["Z"] - z_ref).max()
-    say(f"  fp32 max|dS| {dS:.3e} max|dZ| {dZ:.3e}")
-    assert dS <= 1e-4
-    assert dZ <= 1e-4
+    say(f"  {prec} max|dS| {dS:.3e} max|dZ| {dZ:.3e} trace-1 {np.abs(res['trace'] - 1).max():.3e}")
+    assert dS <= tol
+    assert dZ <= tol
     st.close()
 
 
@@ -122,7 +133,8 @@ def test_single_gate_ragged_vs_oracle(pm, site, chi_max):
     st.close()
 
 
-@pytest.mark.parametrize("chi,prec,tol", [(128, "fp64", 1e-10), (512, "fp64", 1e-10), (128, "fp32", 1e-4)])
+@pytest.mark.parametrize("chi,prec,tol", [(128, "fp64", 1e-10), (512, "fp64", 1e-10), (128, "fp32", 1e-4),
+                                          (128, "bf16x3", BF3_GATE_TOL)])
 def test_bulk_gate_singular_values(pm, chi, prec, tol):
     # a saturated bulk gate: chi_L = chi_M = chi_R = chi, theta' is (4 chi) x (4 chi)
     n = 12
@@ -143,7 +155,8 @@ def test_bulk_gate_singular_values(pm, chi, prec, tol):
     lam_ref = ref.schmidt_sweep()[s0]
     lam_gpu = st.singular_values(s0)
     k = min(lam_ref.size, lam_gpu.size)
-    say(f"  kept {info.kept}/{rinfo.kept} dS {info.entropy - rinfo.entropy:.3e}")
+    say(f"  kept {info.kept}/{rinfo.kept} dS {info.entropy - rinfo.entropy:.3e} "
+        f"dlam {np.abs(lam_gpu[:k] - lam_ref[:k]).max() / lam_ref[0]:.3e}")
     assert info.kept == rinfo.kept
     assert abs(info.entropy - rinfo.entropy) <= tol
     assert np.abs(lam_gpu[:k] - lam_ref[:k]).max() <= tol * lam_ref[0]
