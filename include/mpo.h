@@ -53,15 +53,17 @@ typedef enum {
     MPO_FP64 = 0,       /* complex128 tensors, FP64 MFMA contractions        */
     MPO_FP32_MFMA = 1,  /* complex64 tensors and contractions on FP32 MFMA;
                            truncation weights and entropy in FP64            */
-    MPO_BF16X3 = 2      /* complex64 tensors; every contraction (two-site
-                           product, channel-fused theta, Jacobi Gram and
-                           rotations, centre moves) splits each FP32 operand
-                           into BF16 hi + lo and sums three BF16 MFMA products
-                           in FP32 (about 16 significant bits, relative error
-                           of a product up to about 3e-5).  The eigen core,
-                           weights and entropy stay FP64.  Singular values
-                           with lambda^2 / sum lambda^2 <= 1e-9 are at the
-                           mode's rounding floor and are never kept.          */
+    MPO_BF16X3 = 2      /* complex64 tensors; the two-site product, the
+                           channel-fused theta, the centre moves and the
+                           Jacobi Gram split each FP32 operand into BF16
+                           hi + lo and sum three BF16 MFMA products in FP32
+                           (about 16 significant bits, relative error of a
+                           product up to about 3e-5).  The Jacobi rotations,
+                           applied hundreds of times to each column, stay on
+                           FP32 MFMA; the eigen core, weights and entropy stay
+                           FP64.  Singular values with
+                           lambda^2 / sum lambda^2 <= 1e-9 are at the mode's
+                           rounding floor and are never kept.                 */
 } mpo_precision;
 
 typedef enum { MPO_BASIS_PAULI = 0, MPO_BASIS_COMPUTATIONAL = 1 } mpo_basis;

@@ -280,6 +280,30 @@ __device__ __forceinline__ void pair_rotation(double a, double d, double2 g, dou
     s = make_double2(f * g.x, f * g.y);
 }
 
+// The same rotation from the hardware reciprocal square root estimate alone
+// (relative error below 2^-24), made unitary to FP64 rounding afterwards:
+// with e = c~^2 + |s~|^2 - 1 (about 2^-22), (c, s) = (c~, s~)(1 - e/2 + 3e^2/8)
+// leaves c^2 + |s|^2 - 1 of order e^3.  The angle is off by about 2^-23, so
+// the pair keeps an off-diagonal of that relative size, far below the outer
+// tolerance of the FP32 and BF16x3 modes; the dependent chain is 14 operations
+// instead of 21.
+__device__ __forceinline__ void pair_rotation_fast(double a, double d, double2 g, double zthr,
+                                                   double tol2, double& c, double2& s) {
+    const double g2 = fma(g.x, g.x, g.y * g.y);
+    const bool act = (a > zthr) & (d > zthr) & (g2 > tol2 * a * d);
+    const double h = d - a;
+    const double inv_r = __builtin_amdgcn_rsq(act ? fma(h, h, 4.0 * g2) : 1.0);
+    const double c2 = act ? fma(0.5 * fabs(h), inv_r, 0.5) : 1.0;
+    const double inv_c = __builtin_amdgcn_rsq(c2);
+    const double ct = c2 * inv_c;
+    const double f = act ? (h >= 0.0 ? inv_r : -inv_r) * inv_c : 0.0;
+    const double sx = f * g.x, sy = f * g.y;
+    const double e = fma(sy, sy, fma(sx, sx, fma(ct, ct, -1.0)));
+    const double k = fma(e, fma(e, 0.375, -0.5), 1.0);
+    c = act ? ct * k : 1.0;
+    s = make_double2(sx * k, sy * k);
+}
+
 template <int NB, int NT>
 __device__ double block_off(const double2 (*G)[NB + 1], double zthr, double* red) {
     const int t = threadIdx.x;
@@ -394,10 +418,17 @@ __global__ __launch_bounds__(kEigThreads) void k_pair_eig(const double2* __restr
                     bk[u][1] = G[i1[u]][j2[u]];
                     bk[u][2] = G[j1[u]][i2[u]];
                     bk[u][3] = G[j1[u]][j2[u]];
-                    pair_rotation(G[i1[u]][i1[u]].x, G[j1[u]][j1[u]].x, G[i1[u]][j1[u]], zthr, tol2,
-                                  c1[u], s1[u]);
-                    pair_rotation(G[i2[u]][i2[u]].x, G[j2[u]][j2[u]].x, G[i2[u]][j2[u]], zthr, tol2,
-                                  c2[u], s2[u]);
+                    if constexpr (sizeof(T) == 8) {   // exact angles for the FP64 mode
+                        pair_rotation(G[i1[u]][i1[u]].x, G[j1[u]][j1[u]].x, G[i1[u]][j1[u]], zthr,
+                                      tol2, c1[u], s1[u]);
+                        pair_rotation(G[i2[u]][i2[u]].x, G[j2[u]][j2[u]].x, G[i2[u]][j2[u]], zthr,
+                                      tol2, c2[u], s2[u]);
+                    } else {
+                        pair_rotation_fast(G[i1[u]][i1[u]].x, G[j1[u]][j1[u]].x, G[i1[u]][j1[u]],
+                                           zthr, tol2, c1[u], s1[u]);
+                        pair_rotation_fast(G[i2[u]][i2[u]].x, G[j2[u]][j2[u]].x, G[i2[u]][j2[u]],
+                                           zthr, tol2, c2[u], s2[u]);
+                    }
                 }
                 if (tt < NP) {          // P1 == 0: publish rotation P2 = tt
                     rc[k & 1][tt] = c2[0];
@@ -496,8 +527,12 @@ __global__ __launch_bounds__(kEigThreads) void k_pair_eig(const double2* __restr
 
 // ------------------------------------------------------------- pair update
 constexpr int kUpdateSlabs = 4;   // 64-row slabs per work-group
-// [x_p x_q] <- [x_p x_q] W for one 64-row slab of the pair's NB columns.
-template <typename T, int JB, bool BF>
+// [x_p x_q] <- [x_p x_q] W for one 64-row slab of the pair's NB columns.  A
+// column is rotated hundreds of times in one decomposition, so this product
+// stays on the storage precision's own MFMA in every mode: rounding of W or X
+// here accumulates in the state, while Gram rounding only perturbs angles.
+
+template <typename T, int JB>
 __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int m, int N,
                                                      const int* __restrict__ colmap, int nb,
                                                      int round, const C2<T>* __restrict__ Wm,
@@ -559,29 +594,6 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
             for (int bj = 0; bj < MB; ++bj)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
-        if constexpr (BF) {
-            for (int kk = 0; kk < NB; kk += 16) {
-                CBF a[2], b[MB];
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    float2 v[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) v[j] = Xt[kk + 4 * (lane >> 4) + j][wm * 32 + s * 16 + (lane & 15)];
-                    a[s] = cbf_split(v, false);
-                }
-#pragma unroll
-                for (int s = 0; s < MB; ++s) {
-                    float2 v[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) v[j] = Ws[kk + 4 * (lane >> 4) + j][wn * (NB / 2) + s * 16 + (lane & 15)];
-                    b[s] = cbf_split(v, false);
-                }
-#pragma unroll
-                for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                    for (int bj = 0; bj < MB; ++bj) cmfma_bf3(accR[bi][bj], accI[bi][bj], a[bi], b[bj]);
-            }
-        } else
 #pragma unroll 4
         for (int kk = 0; kk < NB; kk += 4) {
             C2<T> a[2], b[MB];
@@ -819,7 +831,7 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
                                (C2<T>*)w.w, w.skip, w.info);
             pf.end(st, K_EIG, 0.0, (double)P * splits * NB * NB * 16.0);
             pf.begin(st);
-            hipLaunchKernelGGL((k_pair_update<T, JB, BF>), dim3(P, (m + 64 * kUpdateSlabs - 1) / (64 * kUpdateSlabs)), dim3(256), 0, st, X, m,
+            hipLaunchKernelGGL((k_pair_update<T, JB>), dim3(P, (m + 64 * kUpdateSlabs - 1) / (64 * kUpdateSlabs)), dim3(256), 0, st, X, m,
                                N, w.colmap, nb, r, (const C2<T>*)w.w, w.skip);
             pf.end(st, K_UPDATE, 0.0, 0.0);
         }
