@@ -304,38 +304,45 @@ __device__ __forceinline__ void pair_rotation_fast(double a, double d, double2 g
     s = make_double2(sx * k, sy * k);
 }
 
+// Largest relative off-diagonal |g_ij| / sqrt(g_ii g_jj) over the columns
+// above the rounding floor, and the set of round-robin steps (bit s) that pair
+// at least one (i, j) above tol.  Pair (i, j), i, j < NB-1, meets at the step
+// s with i + j = 2s (mod NB-1); the fixed member NB-1 meets i at step i.
 template <int NB, int NT>
-__device__ double block_off(const double2 (*G)[NB + 1], double zthr, double* red) {
+__device__ double block_scan(const double2 (*G)[NB + 2], double zthr, double tol2, double* red,
+                             unsigned long long* smask, unsigned long long& mask) {
+    constexpr int M = NB - 1;
     const int t = threadIdx.x;
+    if (t == 0) *smask = 0ull;
+    __syncthreads();
     double mx = 0.0;
+    unsigned long long bits = 0ull;
     for (int e = t; e < NB * NB; e += NT) {
         const int i = e % NB, j = e / NB;
         if (i < j) {
             const double a = G[i][i].x, d = G[j][j].x;
             if (a > zthr && d > zthr) {
                 const double2 g = G[i][j];
-                mx = fmax(mx, sqrt(g.x * g.x + g.y * g.y) / sqrt(a * d));
+                const double g2 = fma(g.x, g.x, g.y * g.y);
+                mx = fmax(mx, sqrt(g2) / sqrt(a * d));
+                if (g2 > tol2 * a * d) {
+                    const int st = (j == M) ? i : ((i + j) * ((M + 1) / 2)) % M;
+                    bits |= 1ull << st;
+                }
             }
         }
     }
     red[t] = mx;
+    if (bits) atomicOr(smask, bits);
     __syncthreads();
     for (int o = NT / 2; o > 0; o >>= 1) {
         if (t < o) red[t] = fmax(red[t], red[t + o]);
         __syncthreads();
     }
     const double r = red[0];
+    mask = *smask;
     __syncthreads();
     return r;
-}
-
-// Pair indices of a thread's blocks, advanced from one step of the
-// round-robin ordering to the next: both members move on by one modulo NB-1,
-// except the fixed member NB-1 of pair 0.
-template <int NB>
-__device__ __forceinline__ void next_pair(int P, int& i, int& j) {
-    i = (i + 1 == NB - 1) ? 0 : i + 1;
-    if (P != 0) j = (j + 1 == NB - 1) ? 0 : j + 1;
 }
 
 constexpr int kEigThreads = 512;   // waves 0-3 transform G, waves 4-7 accumulate W
@@ -348,11 +355,14 @@ __global__ __launch_bounds__(kEigThreads) void k_pair_eig(const double2* __restr
                                                          int* __restrict__ skip, DevInfo* info) {
     constexpr int NT = kEigThreads, NB = 2 * JB, NP = JB, U = NP * NP / 256;   // blocks per thread
     static_assert(NP * NP % 256 == 0, "block count must fill four waves");
-    __shared__ double2 G[NB][NB + 1];
+    // Row pitch NB + 2 for G: the pair entries G[s+P][s-P] of one step then
+    // fall in distinct banks (pitch NB + 1 maps them all to one bank).
+    __shared__ double2 G[NB][NB + 2];
     __shared__ double2 W[NB][NB + 1];
     __shared__ double red[NT];
     __shared__ double rc[2][NP];       // rotations of the last two steps, for the W waves
     __shared__ double2 rs[2][NP];
+    __shared__ unsigned long long smask;
     const int t = threadIdx.x, pair = blockIdx.x;
     for (int e = t; e < NB * NB; e += NT) {
         const int i = e % NB, j = e / NB;
@@ -380,7 +390,8 @@ __global__ __launch_bounds__(kEigThreads) void k_pair_eig(const double2* __restr
     __syncthreads();
     const double zthr = zrel2 * (*fro2);
     const double tol2 = tol * tol;
-    const double off0 = block_off<NB, NT>(G, zthr, red);
+    unsigned long long mask;
+    const double off0 = block_scan<NB, NT>(G, zthr, tol2, red, &smask, mask);
     if (off0 <= tol) {
         if (t == 0) skip[pair] = 1;
         return;
@@ -395,20 +406,24 @@ __global__ __launch_bounds__(kEigThreads) void k_pair_eig(const double2* __restr
     // the diagonal blocks of G (all of them are read before any is
     // overwritten) and applies G <- J1^H G J2 to its block; the rotations of
     // the step are published for the W threads, which apply W <- W J1 to rows
-    // {i2, j2} one step later, off the critical path of G.
+    // {i2, j2} one step later, off the critical path of G.  A sweep visits
+    // only the steps that held an entry above tol when it started (threshold
+    // Jacobi: every other rotation of such a step is the identity).
     const bool gthr = t < 256;
     const int tt = t & 255;
-    int i1[U], j1[U], i2[U], j2[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int b = tt + 256 * u;
-        pair_of(0, b / NP, NB, i1[u], j1[u]);
-        pair_of(0, b % NP, NB, i2[u], j2[u]);
-    }
-    int steps_done = 0, k = 0;   // k counts steps over all sweeps
+    int steps_done = 0, k = 0, prev = 0;   // k counts executed steps, prev is the last one
     for (int sweep = 0; sweep < inner_max; ++sweep) {
-        steps_done += NB - 1;
-        for (int step = 0; step < NB - 1; ++step, ++k) {
+        for (; mask; mask &= mask - 1, ++k) {
+            const int step = __ffsll((long long)mask) - 1;
+            ++steps_done;
+            int i1[U], j1[U], i2[U], j2[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int b = tt + 256 * u;
+                const int sp = gthr ? step : prev;   // W threads work on the previous step
+                pair_of(sp, b / NP, NB, i1[u], j1[u]);
+                pair_of(sp, b % NP, NB, i2[u], j2[u]);
+            }
             double2 bk[U][4], s1[U], s2[U];
             double c1[U], c2[U];
             if (gthr) {
@@ -481,34 +496,29 @@ __global__ __launch_bounds__(kEigThreads) void k_pair_eig(const double2* __restr
                     W[j2[u]][j1[u]] = make_double2(r1.x + c1u * w11.x, r1.y + c1u * w11.y);
                 }
             }
-            // G threads move to the next step's pairing; W threads to this step's
-            if (gthr || k > 0) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int b = tt + 256 * u;
-                    next_pair<NB>(b / NP, i1[u], j1[u]);
-                    next_pair<NB>(b % NP, i2[u], j2[u]);
-                }
-            }
+            prev = step;
             __syncthreads();
         }
-        if (sweep + 1 < inner_max && block_off<NB, NT>(G, zthr, red) <= tol) break;
+        if (sweep + 1 < inner_max && block_scan<NB, NT>(G, zthr, tol2, red, &smask, mask) <= tol) break;
     }
     // the W threads still owe the last step
     if (!gthr && k > 0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int P1 = (tt + 256 * u) / NP;
+            int i1, j1, i2, j2;
+            pair_of(prev, P1, NB, i1, j1);
+            pair_of(prev, (tt + 256 * u) % NP, NB, i2, j2);
             const double c1u = rc[(k - 1) & 1][P1];
             const double2 s1u = rs[(k - 1) & 1][P1];
-            const double2 w00 = W[i2[u]][i1[u]], w01 = W[i2[u]][j1[u]];
-            const double2 w10 = W[j2[u]][i1[u]], w11 = W[j2[u]][j1[u]];
+            const double2 w00 = W[i2][i1], w01 = W[i2][j1];
+            const double2 w10 = W[j2][i1], w11 = W[j2][j1];
             const double2 q0 = dmulc(s1u, w01), q1 = dmulc(s1u, w11);
             const double2 r0 = dmul(s1u, w00), r1 = dmul(s1u, w10);
-            W[i2[u]][i1[u]] = make_double2(c1u * w00.x - q0.x, c1u * w00.y - q0.y);
-            W[i2[u]][j1[u]] = make_double2(r0.x + c1u * w01.x, r0.y + c1u * w01.y);
-            W[j2[u]][i1[u]] = make_double2(c1u * w10.x - q1.x, c1u * w10.y - q1.y);
-            W[j2[u]][j1[u]] = make_double2(r1.x + c1u * w11.x, r1.y + c1u * w11.y);
+            W[i2][i1] = make_double2(c1u * w00.x - q0.x, c1u * w00.y - q0.y);
+            W[i2][j1] = make_double2(r0.x + c1u * w01.x, r0.y + c1u * w01.y);
+            W[j2][i1] = make_double2(c1u * w10.x - q1.x, c1u * w10.y - q1.y);
+            W[j2][j1] = make_double2(r1.x + c1u * w11.x, r1.y + c1u * w11.y);
         }
     }
     __syncthreads();
