@@ -536,7 +536,9 @@ __global__ __launch_bounds__(kEigThreads) void k_pair_eig(const double2* __restr
 }
 
 // ------------------------------------------------------------- pair update
-constexpr int kUpdateSlabs = 4;   // 64-row slabs per work-group
+// 64-row slabs per work-group (measured at a 4096 x 4096 split: FP32 is
+// fastest with one slab and the most work-groups, FP64 with four)
+template <typename T> constexpr int update_slabs() { return sizeof(T) == 8 ? 4 : 1; }
 // [x_p x_q] <- [x_p x_q] W for one 64-row slab of the pair's NB columns.  A
 // column is rotated hundreds of times in one decomposition, so this product
 // stays on the storage precision's own MFMA in every mode: rounding of W or X
@@ -563,6 +565,7 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
     }
     const C2<T>* wsrc = Wm + (size_t)pair * (NB * NB);
     for (int e = t; e < NB * NB; e += 256) Ws[e % NB][e / NB] = wsrc[e];
+    constexpr int kUpdateSlabs = update_slabs<T>();
     // W stays in LDS for kUpdateSlabs consecutive 64-row slabs; the next slab
     // is loaded into registers while the current one is multiplied
     constexpr int LE = NB * 64 / 256;
@@ -841,7 +844,8 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
                                (C2<T>*)w.w, w.skip, w.info);
             pf.end(st, K_EIG, 0.0, (double)P * splits * NB * NB * 16.0);
             pf.begin(st);
-            hipLaunchKernelGGL((k_pair_update<T, JB>), dim3(P, (m + 64 * kUpdateSlabs - 1) / (64 * kUpdateSlabs)), dim3(256), 0, st, X, m,
+            constexpr int US = update_slabs<T>();
+            hipLaunchKernelGGL((k_pair_update<T, JB>), dim3(P, (m + 64 * US - 1) / (64 * US)), dim3(256), 0, st, X, m,
                                N, w.colmap, nb, r, (const C2<T>*)w.w, w.skip);
             pf.end(st, K_UPDATE, 0.0, 0.0);
         }
