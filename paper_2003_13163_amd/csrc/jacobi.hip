@@ -434,15 +434,24 @@ __global__ __launch_bounds__(kEigThreads) void k_pair_eig(const double2* __restr
                     bk[u][2] = G[j1[u]][i2[u]];
                     bk[u][3] = G[j1[u]][j2[u]];
                     if constexpr (sizeof(T) == 8) {   // exact angles for the FP64 mode
-                        pair_rotation(G[i1[u]][i1[u]].x, G[j1[u]][j1[u]].x, G[i1[u]][j1[u]], zthr,
-                                      tol2, c1[u], s1[u]);
                         pair_rotation(G[i2[u]][i2[u]].x, G[j2[u]][j2[u]].x, G[i2[u]][j2[u]], zthr,
                                       tol2, c2[u], s2[u]);
                     } else {
-                        pair_rotation_fast(G[i1[u]][i1[u]].x, G[j1[u]][j1[u]].x, G[i1[u]][j1[u]],
-                                           zthr, tol2, c1[u], s1[u]);
                         pair_rotation_fast(G[i2[u]][i2[u]].x, G[j2[u]][j2[u]].x, G[i2[u]][j2[u]],
                                            zthr, tol2, c2[u], s2[u]);
+                    }
+                    if constexpr (U == 1) {
+                        // lane q < 16 of this wave holds rotation q as its P2 rotation, and
+                        // P1 = 4 * wave + lane / 16 < 16: fetch it instead of recomputing
+                        const int src = 4 * (tt >> 6) + ((tt & 63) >> 4);
+                        c1[u] = __shfl(c2[u], src);
+                        s1[u] = make_double2(__shfl(s2[u].x, src), __shfl(s2[u].y, src));
+                    } else if constexpr (sizeof(T) == 8) {
+                        pair_rotation(G[i1[u]][i1[u]].x, G[j1[u]][j1[u]].x, G[i1[u]][j1[u]], zthr,
+                                      tol2, c1[u], s1[u]);
+                    } else {
+                        pair_rotation_fast(G[i1[u]][i1[u]].x, G[j1[u]][j1[u]].x, G[i1[u]][j1[u]],
+                                           zthr, tol2, c1[u], s1[u]);
                     }
                 }
                 if (tt < NP) {          // P1 == 0: publish rotation P2 = tt
