@@ -10,6 +10,8 @@
 // the left singular vectors are the normalised columns and the singular
 // values their norms.  Columns are re-ordered by decreasing norm before each
 // sweep through an index map (no data movement).
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include <cstring>
 
@@ -843,20 +845,23 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
         pf.end(st, K_NORMSORT, 8.0 * m * N, (double)m * N * csz);
         (void)hipMemsetAsync(&w.info->offmax_bits, 0, sizeof(unsigned long long) + 2 * sizeof(int), st);
         for (int r = 0; r < nb - 1; ++r) {
-            pf.begin(st);
-            hipLaunchKernelGGL((k_pair_gram<T, JB, BF>), dim3(P, splits), dim3(256), 0, st, X, m, N,
-                               w.colmap, nb, r, splits, chunk, (double2*)w.gram_partials);
-            pf.end(st, K_GRAM, P * pair_flops, P * pair_bytes + (double)P * splits * NB * NB * 16.0);
-            pf.begin(st);
-            hipLaunchKernelGGL((k_pair_eig<T, JB>), dim3(P), dim3(kEigThreads), 0, st,
-                               (const double2*)w.gram_partials, splits, tol, zrel2, fro2, inner_max,
-                               (C2<T>*)w.w, w.skip, w.info);
-            pf.end(st, K_EIG, 0.0, (double)P * splits * NB * NB * 16.0);
-            pf.begin(st);
+            hipEvent_t a, b;
+            pf.stamps(a, b);
+            hipExtLaunchKernelGGL((k_pair_gram<T, JB, BF>), dim3(P, splits), dim3(256), 0, st, a, b, 0,
+                                  X, m, N, (const int*)w.colmap, nb, r, splits, chunk,
+                                  (double2*)w.gram_partials);
+            pf.record(K_GRAM, a, b, P * pair_flops, P * pair_bytes + (double)P * splits * NB * NB * 16.0);
+            pf.stamps(a, b);
+            hipExtLaunchKernelGGL((k_pair_eig<T, JB>), dim3(P), dim3(kEigThreads), 0, st, a, b, 0,
+                                  (const double2*)w.gram_partials, splits, tol, zrel2,
+                                  (const double*)fro2, inner_max, (C2<T>*)w.w, w.skip, w.info);
+            pf.record(K_EIG, a, b, 0.0, (double)P * splits * NB * NB * 16.0);
             constexpr int US = update_slabs<T>();
-            hipLaunchKernelGGL((k_pair_update<T, JB>), dim3(P, (m + 64 * US - 1) / (64 * US)), dim3(256), 0, st, X, m,
-                               N, w.colmap, nb, r, (const C2<T>*)w.w, w.skip);
-            pf.end(st, K_UPDATE, 0.0, 0.0);
+            pf.stamps(a, b);
+            hipExtLaunchKernelGGL((k_pair_update<T, JB>), dim3(P, (m + 64 * US - 1) / (64 * US)), dim3(256),
+                                  0, st, a, b, 0, X, m, N, (const int*)w.colmap, nb, r,
+                                  (const C2<T>*)w.w, (const int*)w.skip);
+            pf.record(K_UPDATE, a, b, 0.0, 0.0);
         }
         w.n_rounds += nb - 1;
         w.n_sweeps += 1;

@@ -1,5 +1,7 @@
 // Per-kernel timing with HIP events on the launching stream (instrumentation).
-// When enabled, each instrumented launch is bracketed by two events and its
+// When enabled, each instrumented launch gets a start and a stop event (the
+// Jacobi kernels through hipExtLaunchKernel, which stamps them with the
+// dispatch's own start and end; the others bracketed by event records) and its
 // algorithmic flop and byte counts are accumulated; elapsed times are
 // collected lazily when the caller reads the statistics.
 #pragma once
@@ -57,6 +59,21 @@ struct Profiler {
         hipEvent_t b = get();
         (void)hipEventRecord(b, st);
         pending.push_back({cur_a, b, k});
+        launches[k] += 1;
+        flops[k] += fl;
+        bytes[k] += by;
+        if (pending.size() >= 16384) collect();
+    }
+    // Events for hipExtLaunchKernel to stamp with the launch's own start and
+    // stop (no separate event packets around it); both null when off.
+    void stamps(hipEvent_t& a, hipEvent_t& b) {
+        if (!on) { a = b = nullptr; return; }
+        a = get();
+        b = get();
+    }
+    void record(int k, hipEvent_t a, hipEvent_t b, double fl, double by) {
+        if (!on) return;
+        pending.push_back({a, b, k});
         launches[k] += 1;
         flops[k] += fl;
         bytes[k] += by;
