@@ -134,6 +134,31 @@ mpo_status mpo_trace(mpo_handle *h, double *re, double *im);
 /* All <Z_i> = Tr[Z_i rho]/Tr[rho] (n values) and Tr[rho].                    */
 mpo_status mpo_expect_z_all(mpo_handle *h, double *z, double *trace);
 
+/* Output probability of a computational-basis measurement (Sec. III.D):
+ * P(x) = Tr[|x><x| rho], a contraction of the MPO with one projector vector
+ * per site.  bits: n values in {0,1}, bits[0] is the leftmost qubit.  The value
+ * is that of the held (possibly truncated) state, not divided by Tr rho; im is
+ * a rounding diagnostic.  Summed over all x it gives Tr rho (Sec. III.D).
+ * Errors: MPO_ERR_ARG for a null pointer or a bit outside {0,1}.             */
+mpo_status mpo_probability(mpo_handle *h, const unsigned char *bits, double *re, double *im);
+
+/* Bit strings drawn by sequential conditional sampling (Sec. III.D, sampling
+ * via marginals): the marginal of x_1 with every later site summed out, then
+ * the conditional of each next bit given the drawn prefix.  The caller supplies
+ * the randomness: uniforms is n_samples x n values in [0, 1), sample-major
+ * (uniforms[s*n + k] draws bit k of sample s); bit k is 0 when
+ * uniforms[s*n+k] < P(0 | prefix) / (P(0 | prefix) + P(1 | prefix)), else 1.
+ * A truncated rho need not be positive: a negative marginal is taken as 0 and
+ * the sample is counted in *clamped; if both marginals vanish the bit is 0.
+ * Outputs (host): bits (n_samples x n, sample-major), prob (n_samples values of
+ * P(x) of each drawn string, unnormalised as in mpo_probability; may be NULL),
+ * clamped (may be NULL).  The samples are processed in chunks sized to the
+ * handle's scratch (theta buffers; the state itself is not modified).
+ * Errors: MPO_ERR_ARG for n_samples < 1, null inputs or a uniform outside
+ * [0, 1); MPO_ERR_ARENA if the scratch cannot hold even one sample.          */
+mpo_status mpo_sample(mpo_handle *h, int n_samples, const double *uniforms, unsigned char *bits,
+                      double *prob, int *clamped);
+
 /* Current bond dimensions (n-1 values) and orthogonality centre.            */
 mpo_status mpo_bond_dims(mpo_handle *h, int *dims, int *center);
 

@@ -58,6 +58,13 @@ def ginibre_draws(n: int, depth: int, seed: int | None = None,
     return out
 
 
+def sampling_uniforms(n_samples: int, n: int, seed: int) -> np.ndarray:
+    """Uniform draws in [0, 1) for bit-string sampling: array (n_samples, n)
+    float64, sample-major, from a fresh PCG64 stream."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.random((n_samples, n))
+
+
 @dataclasses.dataclass(frozen=True)
 class CircuitSpec:
     """One random circuit instance of the batched workload."""

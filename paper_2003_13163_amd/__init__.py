@@ -80,6 +80,8 @@ def library() -> ctypes.CDLL:
         "mpo_canonicalize": [P, I],
         "mpo_bond_entropy": [P, I, pd],
         "mpo_singular_values": [P, I, pd, I, pi],
+        "mpo_probability": [P, ctypes.c_char_p, pd, pd],
+        "mpo_sample": [P, I, pd, ctypes.c_void_p, pd, pi],
         "mpo_expect_pauli": [P, ctypes.c_char_p, pd, pd],
         "mpo_trace": [P, pd, pd],
         "mpo_expect_z_all": [P, pd, pd],
@@ -216,6 +218,29 @@ class Mpo:
         re, im = ctypes.c_double(), ctypes.c_double()
         _check(library().mpo_trace(self._h, ctypes.byref(re), ctypes.byref(im)))
         return complex(re.value, im.value)
+
+    def probability(self, bits) -> complex:
+        """P(x) = Tr[|x><x| rho] of the held state (not divided by Tr rho)."""
+        b = bytes(int(v) for v in bits)
+        if len(b) != self.n:
+            raise ValueError("one bit per site")
+        re, im = ctypes.c_double(), ctypes.c_double()
+        _check(library().mpo_probability(self._h, b, ctypes.byref(re), ctypes.byref(im)))
+        return complex(re.value, im.value)
+
+    def sample(self, uniforms):
+        """Sequential conditional sampling with caller-supplied uniforms
+        (n_samples x n, in [0, 1)).  Returns (bits uint8 (n_samples, n), P(x)
+        of each string, number of samples that met a negative marginal)."""
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        if u.ndim != 2 or u.shape[1] != self.n:
+            raise ValueError("uniforms must be (n_samples, n)")
+        bits = np.zeros(u.shape, dtype=np.uint8)
+        prob = np.zeros(u.shape[0])
+        clamped = ctypes.c_int()
+        _check(library().mpo_sample(self._h, u.shape[0], _dptr(u), bits.ctypes.data, _dptr(prob),
+                                    ctypes.byref(clamped)))
+        return bits, prob, clamped.value
 
     def expect_z_all(self):
         z = np.zeros(self.n)

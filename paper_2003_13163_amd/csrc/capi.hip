@@ -51,6 +51,7 @@ struct HipError {
 
 struct NumericError { const char* what; };
 struct NoConvError { const char* what; };
+struct ArenaError { const char* what; };   // the handle's scratch cannot hold the request
 
 constexpr int kMaxSuper = 1024;     // superoperators resident per upload
 constexpr int64_t kMagicAny = 0x4d504f31;        // "MPO1": tensors in any gauge
@@ -112,6 +113,7 @@ struct mpo_handle {
     int centre = 0;
     bool poisoned = false;
     char *X = nullptr, *X2 = nullptr, *R = nullptr, *Mdev = nullptr;
+    size_t x_bytes = 0;          // bytes of X and of X2 each
     JacobiWork jw{};
     double2 *envL = nullptr, *envR = nullptr, *tscr = nullptr, *tmp = nullptr, *vecs = nullptr,
             *dots = nullptr;
@@ -392,6 +394,101 @@ struct Engine {
         const double den = tr.x * tr.x + tr.y * tr.y;
         *re = (num.x * tr.x + num.y * tr.y) / den;
         *im = (num.y * tr.x - num.x * tr.y) / den;
+    }
+
+    // Site vectors of the projectors |0><0| = (1 + Z)/2 and |1><1| = (1 - Z)/2.
+    static void projector_vectors(mpo_basis basis, double2 v[8]) {
+        double2 vi[4], vz[4];
+        dual_vector(basis, 0, vi);
+        dual_vector(basis, 3, vz);
+        for (int k = 0; k < 4; ++k) {
+            v[k] = make_double2(0.5 * (vi[k].x + vz[k].x), 0.5 * (vi[k].y + vz[k].y));
+            v[4 + k] = make_double2(0.5 * (vi[k].x - vz[k].x), 0.5 * (vi[k].y - vz[k].y));
+        }
+    }
+
+    // P(x) = Tr[|x><x| rho] (Sec. III.D): one transfer step per site.
+    static void probability(mpo_handle* h, const unsigned char* bits, double* re, double* im) {
+        const int n = h->n, cap = h->chi_cap;
+        std::vector<double2> hv((size_t)4 * n);
+        double2 pv[8];
+        projector_vectors(h->basis, pv);
+        for (int s = 0; s < n; ++s)
+            for (int k = 0; k < 4; ++k) hv[(size_t)4 * s + k] = pv[4 * bits[s] + k];
+        HIPCHK(hipMemcpyAsync(h->vecs, hv.data(), sizeof(double2) * hv.size(), hipMemcpyHostToDevice, h->st));
+        const double2 one = make_double2(1.0, 0.0);
+        HIPCHK(hipMemcpyAsync(h->envL, &one, sizeof(one), hipMemcpyHostToDevice, h->st));
+        for (int s = 0; s < n; ++s)
+            launch_transfer_left<T>(site(h, s), h->chiL(s), h->chiR(s), h->envL + (size_t)s * cap,
+                                    h->vecs + 4 * s, h->envL + (size_t)(s + 1) * cap, h->st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(h->small_host, h->envL + (size_t)n * cap, sizeof(double2), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+        *re = h->small_host[0].x;
+        *im = h->small_host[0].y;
+    }
+
+    // Sequential conditional sampling (Sec. III.D).  The right environments
+    // sum every later site out (identity vector); per site one GEMM forms the
+    // prefix environments times the site tensor for all samples of a chunk,
+    // and k_sample_site draws the dit.  Chunks are sized to the X / X2 scratch.
+    static void sample(mpo_handle* h, int count, const double* uniforms, unsigned char* bits_out,
+                       double* prob_out, int* clamped_out) {
+        const int n = h->n, cap = h->chi_cap;
+        int chimax = 1;
+        for (int b = 0; b < n - 1; ++b) chimax = std::max(chimax, h->dims[b]);
+        const size_t csz = sizeof(C);
+        const size_t per2 = 2 * (size_t)chimax * csz + (size_t)n * 9 + 16;   // X2 bytes per sample
+        const size_t avail2 = h->x_bytes > 2048 ? h->x_bytes - 2048 : 0;   // alignment slack
+        size_t chunk = std::min(h->x_bytes / (4 * (size_t)chimax * csz), avail2 / per2);
+        chunk = std::min(chunk, (size_t)count);
+        if (chunk < 1) throw ArenaError{"the handle's scratch cannot hold one sample"};
+        // right environments with the identity vector: envR[k] sums sites k..n-1 out
+        double2 hv[12];
+        dual_vector(h->basis, 0, hv);
+        projector_vectors(h->basis, hv + 4);
+        HIPCHK(hipMemcpyAsync(h->vecs, hv, sizeof(hv), hipMemcpyHostToDevice, h->st));
+        const double2 one = make_double2(1.0, 0.0);
+        HIPCHK(hipMemcpyAsync(h->envR + (size_t)n * cap, &one, sizeof(one), hipMemcpyHostToDevice, h->st));
+        for (int s = n - 1; s >= 0; --s)
+            launch_transfer_right<T>(site(h, s), h->chiL(s), h->chiR(s), h->envR + (size_t)(s + 1) * cap,
+                                     h->vecs, h->envR + (size_t)s * cap, h->tscr, h->st);
+        auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+        std::vector<C> last(chunk);
+        std::vector<double> logn(chunk);
+        std::vector<int> clam(chunk);
+        int n_clamped = 0;
+        for (size_t s0 = 0; s0 < (size_t)count; s0 += chunk) {
+            const int S = (int)std::min(chunk, (size_t)count - s0);
+            char* q = h->X2;
+            C* La = (C*)q; q += al((size_t)chimax * S * csz);
+            C* Lb = (C*)q; q += al((size_t)chimax * S * csz);
+            double* u = (double*)q; q += al((size_t)S * n * 8);
+            unsigned char* bits = (unsigned char*)q; q += al((size_t)S * n);
+            double* logN = (double*)q; q += al((size_t)S * 8);
+            int* clamped = (int*)q;
+            C* Y = (C*)h->X;
+            HIPCHK(hipMemcpyAsync(u, uniforms + s0 * n, (size_t)S * n * 8, hipMemcpyHostToDevice, h->st));
+            launch_sample_init<T>(La, logN, clamped, S, h->st);
+            for (int k = 0; k < n; ++k) {
+                const int cl = h->chiL(k), cr = h->chiR(k);
+                launch_cgemm<T>(1, 0, 4 * cr, S, cl, site(h, k), cl, La, cl, Y, 4 * cr, h->st, h->bf3);
+                launch_sample_site<T>(Y, cr, S, h->envR + (size_t)(k + 1) * cap, h->vecs + 4, u, n, k,
+                                      Lb, bits, logN, clamped, h->st);
+                std::swap(La, Lb);
+            }
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(bits_out + s0 * n, bits, (size_t)S * n, hipMemcpyDeviceToHost, h->st));
+            HIPCHK(hipMemcpyAsync(last.data(), La, (size_t)S * csz, hipMemcpyDeviceToHost, h->st));
+            HIPCHK(hipMemcpyAsync(logn.data(), logN, (size_t)S * 8, hipMemcpyDeviceToHost, h->st));
+            HIPCHK(hipMemcpyAsync(clam.data(), clamped, (size_t)S * 4, hipMemcpyDeviceToHost, h->st));
+            HIPCHK(hipStreamSynchronize(h->st));
+            for (int i = 0; i < S; ++i) {
+                if (prob_out) prob_out[s0 + i] = (double)last[i].x * std::exp(logn[i]);
+                n_clamped += clam[i];
+            }
+        }
+        if (clamped_out) *clamped_out = n_clamped;
     }
 
     static void init_product(mpo_handle* h, const unsigned char* bits) {
@@ -761,6 +858,8 @@ mpo_status guarded(mpo_handle* h, F&& f) {
     } catch (const NoConvError& e) {
         if (h) h->poisoned = true;
         return fail(MPO_ERR_NOCONV, "%s", e.what);
+    } catch (const ArenaError& e) {
+        return fail(MPO_ERR_ARENA, "%s", e.what);
     }
 }
 
@@ -829,6 +928,7 @@ mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis, v
     h->site_slot.resize(n);
     for (int s = 0; s < n; ++s) h->site_slot[s] = s;
     h->spare = {n, n + 1};
+    h->x_bytes = L.x_bytes;
     h->X = p; p += L.x_bytes;
     h->X2 = p; p += L.x_bytes;
     h->R = p; p += L.r_bytes;
@@ -971,6 +1071,26 @@ mpo_status mpo_trace(mpo_handle* h, double* re, double* im) {
     if (st != MPO_OK) return st;
     if (!re || !im) return fail(MPO_ERR_ARG, "null argument");
     return guarded(h, [&] { DISPATCH(h, E::observables(h, nullptr, re, im)); });
+}
+
+mpo_status mpo_probability(mpo_handle* h, const unsigned char* bits, double* re, double* im) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    if (!bits || !re || !im) return fail(MPO_ERR_ARG, "null argument");
+    for (int s = 0; s < h->n; ++s)
+        if (bits[s] > 1) return fail(MPO_ERR_ARG, "bits[%d] = %d is not 0/1", s, bits[s]);
+    return guarded(h, [&] { DISPATCH(h, E::probability(h, bits, re, im)); });
+}
+
+mpo_status mpo_sample(mpo_handle* h, int n_samples, const double* uniforms, unsigned char* bits,
+                      double* prob, int* clamped) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    if (n_samples < 1 || !uniforms || !bits) return fail(MPO_ERR_ARG, "bad sampling arguments");
+    for (size_t i = 0; i < (size_t)n_samples * h->n; ++i)
+        if (!(uniforms[i] >= 0.0 && uniforms[i] < 1.0))
+            return fail(MPO_ERR_ARG, "uniforms[%zu] = %g is not in [0, 1)", i, uniforms[i]);
+    return guarded(h, [&] { DISPATCH(h, E::sample(h, n_samples, uniforms, bits, prob, clamped)); });
 }
 
 mpo_status mpo_expect_z_all(mpo_handle* h, double* z, double* trace) {

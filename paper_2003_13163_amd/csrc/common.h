@@ -203,6 +203,15 @@ void launch_identity_site(C2<T>* A, int chiA, hipStream_t st);
 template <typename T>
 void launch_local_grad(const C2<T>* X, const C2<T>* Y, int chiA, int chiC, double2* out,
                        hipStream_t st);
+// Sequential conditional sampling (Sec. III.D): L = 1, logN = 0, clamped = 0 for
+// count samples; then per site the marginals of both dits, the draw and the new
+// environment (one work-group per sample).
+template <typename T>
+void launch_sample_init(C2<T>* L, double* logN, int* clamped, int count, hipStream_t st);
+template <typename T>
+void launch_sample_site(const C2<T>* Ybar, int chiR, int count, const double2* Rk, const double2* v,
+                        const double* u, int n, int site, C2<T>* Lnew, unsigned char* bits,
+                        double* logN, int* clamped, hipStream_t st);
 // out[slot] = sum_a x[a] * y[a]
 void launch_dot(const double2* x, const double2* y, int len, double2* out, hipStream_t st);
 }  // namespace mpo

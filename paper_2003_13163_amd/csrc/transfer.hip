@@ -120,6 +120,119 @@ __global__ __launch_bounds__(256) void k_local_grad(const C2<T>* __restrict__ X,
     if (t == 0) out[(4 * I + J) * 16 + (4 * K + L)] = red[0];
 }
 
+// One site of sequential conditional sampling (Sec. III.D, sampling via
+// marginals), one work-group per sample s.  Ybar[(I + 4c) + 4 chiR s] holds
+// conj of the prefix environment times the site tensor (computed as A^H Lbar by
+// the GEMM), Rk[c] the sites to the right summed out.  The marginals of the
+// two candidate dits are q_b = sum_c (sum_I v_b[I] Y[I + 4c]) Rk[c]; negative
+// ones are taken as 0 (flagged), the dit is 0 when u < p0 / (p0 + p1), and the
+// new environment conj(T_x) / (p0 + p1) keeps its scale near 1 (log of the
+// scale accumulated in logN).  v holds v_0[0..3] then v_1[0..3].
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample_site(const C2<T>* __restrict__ Ybar, int chiR,
+                                                     const double2* __restrict__ Rk,
+                                                     const double2* __restrict__ v,
+                                                     const double* __restrict__ u, int n, int site,
+                                                     C2<T>* __restrict__ Lnew,
+                                                     unsigned char* __restrict__ bits,
+                                                     double* __restrict__ logN,
+                                                     int* __restrict__ clamped) {
+    __shared__ double red[4][256];
+    __shared__ double s_scale;
+    __shared__ int s_x;
+    const int t = threadIdx.x, smp = blockIdx.x;
+    const C2<T>* y = Ybar + (size_t)4 * chiR * smp;
+    double2 vv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) vv[k] = v[k];
+    double q0r = 0.0, q0i = 0.0, q1r = 0.0, q1i = 0.0;
+    for (int c = t; c < chiR; c += 256) {
+        double2 t0 = make_double2(0.0, 0.0), t1 = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int I = 0; I < 4; ++I) {
+            const double2 yb = to_d2(y[I + 4 * c]);
+            const double2 yi = make_double2(yb.x, -yb.y);
+            t0.x += vv[I].x * yi.x - vv[I].y * yi.y;
+            t0.y += vv[I].x * yi.y + vv[I].y * yi.x;
+            t1.x += vv[4 + I].x * yi.x - vv[4 + I].y * yi.y;
+            t1.y += vv[4 + I].x * yi.y + vv[4 + I].y * yi.x;
+        }
+        const double2 r = Rk[c];
+        q0r += t0.x * r.x - t0.y * r.y;
+        q0i += t0.x * r.y + t0.y * r.x;
+        q1r += t1.x * r.x - t1.y * r.y;
+        q1i += t1.x * r.y + t1.y * r.x;
+    }
+    red[0][t] = q0r;
+    red[1][t] = q1r;
+    red[2][t] = q0i;
+    red[3][t] = q1i;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double q0 = red[0][0], q1 = red[1][0];
+        if (q0 < 0.0 || q1 < 0.0) clamped[smp] = 1;
+        const double p0 = fmax(q0, 0.0), p1 = fmax(q1, 0.0), tot = p0 + p1;
+        const int x = (tot == 0.0 || u[(size_t)smp * n + site] < p0 / tot) ? 0 : 1;
+        bits[(size_t)smp * n + site] = (unsigned char)x;
+        const double scale = tot > 0.0 ? tot : 1.0;
+        logN[smp] += log(scale);
+        s_scale = scale;
+        s_x = x;
+    }
+    __syncthreads();
+    const double inv = 1.0 / s_scale;
+    const int off = 4 * s_x;
+    for (int c = t; c < chiR; c += 256) {
+        double2 tx = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int I = 0; I < 4; ++I) {
+            const double2 yb = to_d2(y[I + 4 * c]);
+            const double2 yi = make_double2(yb.x, -yb.y);
+            tx.x += vv[off + I].x * yi.x - vv[off + I].y * yi.y;
+            tx.y += vv[off + I].x * yi.y + vv[off + I].y * yi.x;
+        }
+        Lnew[(size_t)c + (size_t)chiR * smp] = cmake<T>(T(tx.x * inv), T(-tx.y * inv));
+    }
+}
+
+template <typename T>
+__global__ void k_sample_init(C2<T>* __restrict__ L, double* __restrict__ logN,
+                              int* __restrict__ clamped, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    L[i] = cmake<T>(T(1), T(0));
+    logN[i] = 0.0;
+    clamped[i] = 0;
+}
+
+template <typename T>
+void launch_sample_init(C2<T>* L, double* logN, int* clamped, int count, hipStream_t st) {
+    hipLaunchKernelGGL((k_sample_init<T>), dim3((count + 255) / 256), dim3(256), 0, st, L, logN,
+                       clamped, count);
+}
+template <typename T>
+void launch_sample_site(const C2<T>* Ybar, int chiR, int count, const double2* Rk, const double2* v,
+                        const double* u, int n, int site, C2<T>* Lnew, unsigned char* bits,
+                        double* logN, int* clamped, hipStream_t st) {
+    hipLaunchKernelGGL((k_sample_site<T>), dim3(count), dim3(256), 0, st, Ybar, chiR, Rk, v, u, n,
+                       site, Lnew, bits, logN, clamped);
+}
+template void launch_sample_init<double>(double2*, double*, int*, int, hipStream_t);
+template void launch_sample_init<float>(float2*, double*, int*, int, hipStream_t);
+template void launch_sample_site<double>(const double2*, int, int, const double2*, const double2*,
+                                         const double*, int, int, double2*, unsigned char*, double*,
+                                         int*, hipStream_t);
+template void launch_sample_site<float>(const float2*, int, int, const double2*, const double2*,
+                                        const double*, int, int, float2*, unsigned char*, double*,
+                                        int*, hipStream_t);
+
 // A[a, I, b] = [b == a + chiA*I] for a (chiA, 4, 4 chiA) site tensor.
 template <typename T>
 __global__ void k_identity_site(C2<T>* __restrict__ A, int chiA) {
