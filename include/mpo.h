@@ -177,6 +177,24 @@ mpo_status run_brickwork(mpo_handle *h, int depth, const double *superops, int n
                          double *S_out, double *Z_out, double *trace_out,
                          double *discarded_out);
 
+/* Order of the gates within a time step.  Gates of one step act on disjoint
+ * pairs, so without truncation every order gives the same state (Sec. II.A);
+ * under truncation the order is part of the algorithm.  ASCENDING applies them
+ * from the left (the reading of Sec. IV.A's sequential application, and what
+ * run_brickwork does).  SNAKE applies odd time steps ascending and even ones
+ * descending, splitting each descending gate with the centre left on its left
+ * site, so the centre never travels back across the chain between steps.   */
+typedef enum { MPO_ORDER_ASCENDING = 0, MPO_ORDER_SNAKE = 1 } mpo_order;
+
+/* run_brickwork with a chosen gate order.  superops follow the schedule order
+ * of that choice: time step by time step, and within a descending step from
+ * the rightmost gate to the leftmost.  Other arguments, outputs and errors as
+ * run_brickwork; an unknown order is MPO_ERR_ARG.                            */
+mpo_status mpo_run_brickwork_order(mpo_handle *h, int depth, const double *superops, int n_gates,
+                                   int chi_max, double cutoff, mpo_order order, int record_mask,
+                                   double *S_out, double *Z_out, double *trace_out,
+                                   double *discarded_out);
+
 /* Host snapshot of the state.  Format: int64 header {magic, n, basis, center,
  * chi_0 .. chi_{n-2}} then per site the (chi_l, 4, chi_r) tensor, row-major,
  * complex128.  Exports carry magic 0x4d504f32 ("MPO2": sites left of center

@@ -25,6 +25,7 @@ _LIB_PATH = os.path.join(_HERE, "libmpo.so")
 
 FP64, FP32_MFMA, BF16X3 = 0, 1, 2
 PAULI, COMPUTATIONAL = 0, 1
+_ORDER = {"ascending": 0, "snake": 1}
 _PREC = {"fp64": FP64, "fp32": FP32_MFMA, "fp32_mfma": FP32_MFMA, "bf16x3": BF16X3,
          FP64: FP64, FP32_MFMA: FP32_MFMA, BF16X3: BF16X3}
 _BASIS = {"pauli": PAULI, "computational": COMPUTATIONAL, PAULI: PAULI, COMPUTATIONAL: COMPUTATIONAL}
@@ -87,6 +88,7 @@ def library() -> ctypes.CDLL:
         "mpo_expect_z_all": [P, pd, pd],
         "mpo_bond_dims": [P, pi, pi],
         "run_brickwork": [P, I, pd, I, I, D, I, pd, pd, pd, pd],
+        "mpo_run_brickwork_order": [P, I, pd, I, I, D, I, I, pd, pd, pd, pd],
         "mpo_export": [P, P, S, ctypes.POINTER(S)],
         "mpo_import": [P, P, S],
         "mpo_build_superop": [pd, pd, D, I, pd, pd],
@@ -303,7 +305,10 @@ class Mpo:
 
     # ------------------------------------------------------------- evolution
     def run_brickwork(self, depth: int, superops, chi_max: int, cutoff: float = 1e-12,
-                      record: str | None = "all") -> dict:
+                      record: str | None = "all", order: str = "ascending") -> dict:
+        """Brickwork evolution; order "ascending" (every step from the left) or
+        "snake" (even steps from the right; superops then list those steps'
+        gates right to left)."""
         sup = _as_complex_pairs(superops).reshape(-1)
         g = sup.size // 512
         mask = {"all": 1, "last": 2, None: 0}[record]
@@ -312,8 +317,9 @@ class Mpo:
         Z = np.zeros(max(rows, 1) * self.n)
         tr = np.zeros(max(rows, 1))
         disc = np.zeros(max(g, 1))
-        _check(library().run_brickwork(self._h, depth, _dptr(sup), g, chi_max, float(cutoff), mask,
-                                       _dptr(S), _dptr(Z), _dptr(tr), _dptr(disc)))
+        _check(library().mpo_run_brickwork_order(self._h, depth, _dptr(sup), g, chi_max, float(cutoff),
+                                                 _ORDER[order], mask, _dptr(S), _dptr(Z), _dptr(tr),
+                                                 _dptr(disc)))
         return {"S": S[: rows * (self.n - 1)].reshape(rows, self.n - 1),
                 "Z": Z[: rows * self.n].reshape(rows, self.n), "trace": tr[:rows],
                 "discarded": disc[:g]}

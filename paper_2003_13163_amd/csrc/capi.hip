@@ -316,6 +316,43 @@ struct Engine {
         return out;
     }
 
+    // The same gate with the split mirrored, for a sweep that moves left: the
+    // centre comes to s+1, the rows of theta' are orthogonalised (Jacobi on
+    // theta'^H), A_{s+1} <- V_k^H (right isometry) and A_s <- theta' V_k (new
+    // centre, no division by a singular value).  The truncated state is the
+    // same Schmidt truncation at bond s as in apply.
+    static mpo_trunc_info apply_leftward(mpo_handle* h, int s, const C* Mg, int chi_max, double cutoff) {
+        move_centre(h, s + 1);
+        const int chiL = h->chiL(s), chiM = h->dims[s], chiR = h->chiR(s + 1);
+        const int m = 4 * chiL, N = 4 * chiR;
+        h->prof.begin(h->st);
+        launch_theta_channel<T>(chiL, chiM, chiR, site(h, s), site(h, s + 1), Mg, (C*)h->X2, nullptr,
+                                h->st, h->bf3);
+        h->prof.end(h->st, K_THETA, 8.0 * m * chiM * N + 2048.0 * chiL * chiR,
+                    (double)sizeof(C) * (4.0 * chiL * chiM + 4.0 * chiM * chiR + 2.0 * m * N));
+        h->prof.begin(h->st);
+        launch_conj_transpose<T>((C*)h->X2, m, N, (C*)h->X, h->st);
+        h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * N);
+        HIPCHK(hipGetLastError());
+        DevInfo inf = split(h, N, m, chi_max, cutoff);
+        const int k = inf.kept;
+        h->prof.begin(h->st);
+        launch_gather_rows_conj<T>((C*)h->X, N, h->jw.colmap, h->jw.sig2, k, site(h, s + 1), h->st);
+        h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * N * k);
+        h->prof.begin(h->st);
+        launch_cgemm<T>(0, 1, m, k, N, (C*)h->X2, m, site(h, s + 1), k, site(h, s), m, h->st, h->bf3);
+        h->prof.end(h->st, K_GEMM, 8.0 * m * k * N, (double)sizeof(C) * ((double)m * N + (double)k * N + (double)m * k));
+        HIPCHK(hipGetLastError());
+        h->dims[s] = k;
+        h->centre = s;
+        mpo_trunc_info out;
+        out.kept = k;
+        out.discarded_weight = inf.discarded;
+        out.total_weight = inf.total;
+        out.entropy = inf.entropy;
+        return out;
+    }
+
     static void upload_super(mpo_handle* h, const double* superops, int count) {
         T* stage = (T*)h->super_stage;
         for (size_t i = 0; i < (size_t)count * 512; ++i) stage[i] = (T)superops[i];
@@ -1111,6 +1148,14 @@ mpo_status mpo_bond_dims(mpo_handle* h, int* dims, int* center) {
 mpo_status run_brickwork(mpo_handle* h, int depth, const double* superops, int n_gates, int chi_max,
                          double cutoff, int record_mask, double* S_out, double* Z_out,
                          double* trace_out, double* discarded_out) {
+    return mpo_run_brickwork_order(h, depth, superops, n_gates, chi_max, cutoff, MPO_ORDER_ASCENDING,
+                                   record_mask, S_out, Z_out, trace_out, discarded_out);
+}
+
+mpo_status mpo_run_brickwork_order(mpo_handle* h, int depth, const double* superops, int n_gates,
+                                   int chi_max, double cutoff, mpo_order order, int record_mask,
+                                   double* S_out, double* Z_out, double* trace_out,
+                                   double* discarded_out) {
     mpo_status st = check_live(h);
     if (st != MPO_OK) return st;
     const int n = h->n;
@@ -1122,6 +1167,8 @@ mpo_status run_brickwork(mpo_handle* h, int depth, const double* superops, int n
     if (chi_max < 1 || chi_max > h->chi_cap) return fail(MPO_ERR_ARG, "chi_max %d out of [1, %d]", chi_max, h->chi_cap);
     if (!(cutoff >= 0.0) || !std::isfinite(cutoff)) return fail(MPO_ERR_ARG, "cutoff must be finite and >= 0");
     if (record_mask & ~3) return fail(MPO_ERR_ARG, "record_mask has unknown bits");
+    if (order != MPO_ORDER_ASCENDING && order != MPO_ORDER_SNAKE)
+        return fail(MPO_ERR_ARG, "unknown gate order %d", (int)order);
     if (!finite_all(superops, (size_t)n_gates * 512)) {
         h->poisoned = true;
         return fail(MPO_ERR_NUMERIC, "non-finite superoperator entry");
@@ -1132,7 +1179,10 @@ mpo_status run_brickwork(mpo_handle* h, int depth, const double* superops, int n
             int g = 0, resident0 = 0, resident = 0;
             for (int t = 0; t < depth; ++t) {
                 const int first = (t % 2 == 0) ? 0 : 1;
-                for (int s = first; s + 1 < n; s += 2) {
+                const int last = first + 2 * ((n - 2 - first) / 2);
+                const bool down = order == MPO_ORDER_SNAKE && (t % 2 == 1);
+                for (int q = 0; q <= (last - first) / 2; ++q) {
+                    const int s = down ? last - 2 * q : first + 2 * q;
                     if (g >= resident0 + resident) {
                         resident0 = g;
                         resident = std::min(kMaxSuper, n_gates - g);
@@ -1140,7 +1190,8 @@ mpo_status run_brickwork(mpo_handle* h, int depth, const double* superops, int n
                         E::upload_super(h, superops + (size_t)g * 512, resident);
                     }
                     const C* Mg = (const C*)h->Mdev + (size_t)(g - resident0) * 256;
-                    mpo_trunc_info inf = E::apply(h, s, Mg, chi_max, cutoff);
+                    mpo_trunc_info inf = down ? E::apply_leftward(h, s, Mg, chi_max, cutoff)
+                                              : E::apply(h, s, Mg, chi_max, cutoff);
                     if (discarded_out) discarded_out[g] = inf.discarded_weight;
                     ++g;
                 }

@@ -2,7 +2,7 @@
 U(4) gates with two-qubit depolarizing noise (Sec. II.B, Sec. III.B) in
 brickwork order from |0...0>, chi_max = 1024, cutoff 1e-12, the same gates
 (seed 0) for every mode and every p.  Each mode runs the whole circuit on the
-GPU gate by gate (ascending within a time step) and records, after the last
+GPU (gates ascending within a time step, or in snake order) and records, after the last
 time step, the bond entropies (Sec. III.C), their maximum S_max, <Z_i> and
 Tr rho (Sec. III.D).  The FP64 run is the
 reference the reduced-precision modes are compared with.
@@ -20,7 +20,7 @@ import time
 import numpy as np
 
 
-def run(mode: str, n: int, depth: int, p: float, chi: int, seed: int) -> dict:
+def run(mode: str, n: int, depth: int, p: float, chi: int, seed: int, order: str = "ascending") -> dict:
     import torch
     import mpo_inputs as mi
     import paper_2003_13163_amd as pm
@@ -33,19 +33,29 @@ def run(mode: str, n: int, depth: int, p: float, chi: int, seed: int) -> dict:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g, disc = 0, 0.0
-    for t, sites in enumerate(mi.brickwork_sites(n, depth)):
-        for s in sites:          # ascending order within a time step
-            disc += st.apply(s, sup[g], chi, 1e-12).discarded_weight
-            g += 1
-        print(f"{mode}: time step {t + 1}/{depth} done, {time.perf_counter() - t0:.1f} s, "
-              f"max bond {max(st.bond_dims()[0])}", file=sys.stderr, flush=True)
+    layers = mi.brickwork_sites(n, depth)
+    for t in range(0, depth, 2):
+        # two time steps per call (an odd then an even one, as a fresh brickwork
+        # starts), so that progress can be reported; superops in the chosen
+        # order, i.e. right to left within the even step under snake order
+        steps = layers[t:t + 2]
+        chunk = []
+        for j, sites in enumerate(steps):
+            blk = list(sup[g:g + len(sites)])
+            chunk += blk[::-1] if (order == "snake" and j == 1) else blk
+            g += len(sites)
+        res = st.run_brickwork(len(steps), np.array(chunk), chi, 1e-12, record=None, order=order)
+        disc += float(res["discarded"].sum())
+        print(f"{mode} {order}: time steps {t + len(steps)}/{depth} done, "
+              f"{time.perf_counter() - t0:.1f} s, max bond {max(st.bond_dims()[0])}",
+              file=sys.stderr, flush=True)
     S = st.entropy(-1)
     Z, tr = st.expect_z_all()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     dims = st.bond_dims()[0]
     st.close()
-    return {"mode": mode, "n": n, "depth": depth, "p": p, "chi_max": chi, "seed": seed,
+    return {"mode": mode, "order": order, "n": n, "depth": depth, "p": p, "chi_max": chi, "seed": seed,
             "cutoff": 1e-12, "gates": g, "seconds": dt, "S": S.tolist(), "S_max": float(S.max()),
             "Z": Z.tolist(), "trace": float(tr), "discarded_total": disc,
             "bond_dims": [int(d) for d in dims]}
@@ -80,12 +90,13 @@ def main(argv=None):
     r.add_argument("--p", type=float, default=0.01)
     r.add_argument("--chi", type=int, default=1024)
     r.add_argument("--seed", type=int, default=0)
+    r.add_argument("--order", default="ascending", choices=["ascending", "snake"])
     r.add_argument("--out", required=True)
     c = sub.add_parser("compare")
     c.add_argument("files", nargs="+")
     a = ap.parse_args(argv)
     if a.cmd == "run":
-        out = run(a.mode, a.n, a.depth, a.p, a.chi, a.seed)
+        out = run(a.mode, a.n, a.depth, a.p, a.chi, a.seed, a.order)
         json.dump(out, open(a.out, "w"))
         print(json.dumps({k: out[k] for k in ("mode", "depth", "p", "seconds", "S_max", "trace")}),
               flush=True)

@@ -385,3 +385,50 @@ def test_autograd_dO_dp(pm):
     say(f"  dO/dp {p.grad.item():.12f} vs oracle {dp_ref:.12f}")
     assert abs(O.item() - O_ref.real) <= 1e-11
     assert abs(p.grad.item() - dp_ref) <= 1e-9 * max(1.0, abs(dp_ref))
+
+
+# ------------------------------------------------------------- snake gate order
+def snake_layers(n, depth):
+    return [sites[::-1] if t % 2 == 1 else sites for t, sites in enumerate(mi.brickwork_sites(n, depth))]
+
+
+def test_snake_order_vs_oracle(pm):
+    # descending time steps split with the centre on the left site; the oracle
+    # applies the same gates in the same order with its own (rightward) splits
+    n, depth, p, chi = 12, 8, 0.02, 16
+    say(f"case snake order n={n} depth={depth} chi={chi}")
+    draws = mi.ginibre_draws(n, depth, seed=21)
+    sup = gates.circuit_superops(draws, p, "pauli")
+    st = pm.Mpo(n, chi, "fp64", "pauli")
+    res = st.run_brickwork(depth, sup, chi, 1e-12, record="all", order="snake")
+    ref = omp.run_brickwork(n, sup, snake_layers(n, depth), chi, 1e-12, "pauli")
+    dS = np.abs(res["S"] - ref["S"]).max()
+    dZ = np.abs(res["Z"] - ref["Z"]).max()
+    dD = np.abs(res["discarded"] - ref["discarded"]).max()
+    say(f"  max|dS| {dS:.3e} max|dZ| {dZ:.3e} max|d discarded| {dD:.3e}")
+    assert dS <= 1e-10 and dZ <= 1e-10 and dD <= 1e-12
+    st.close()
+
+
+def test_snake_equals_ascending_without_truncation(pm):
+    n, depth, p = 8, 6, 0.02
+    say("case snake = ascending, n8 exact")
+    draws = mi.ginibre_draws(n, depth, seed=22)
+    sup = gates.circuit_superops(draws, p, "pauli")
+    # the same gate on the same pair in both runs: reorder the descending steps
+    asc_sites = [s for sites in mi.brickwork_sites(n, depth) for s in sites]
+    snake_sites = [s for sites in snake_layers(n, depth) for s in sites]
+    order, g0 = [], 0
+    for t, sites in enumerate(mi.brickwork_sites(n, depth)):
+        idx = list(range(g0, g0 + len(sites)))
+        order += idx[::-1] if t % 2 == 1 else idx
+        g0 += len(sites)
+    assert [asc_sites[i] for i in order] == snake_sites
+    a = pm.Mpo(n, 256, "fp64", "pauli")
+    ra = a.run_brickwork(depth, sup, 256, 1e-12, record="last")
+    b = pm.Mpo(n, 256, "fp64", "pauli")
+    rb = b.run_brickwork(depth, sup[order], 256, 1e-12, record="last", order="snake")
+    say(f"  max|dS| {np.abs(ra['S'] - rb['S']).max():.3e} max|dZ| {np.abs(ra['Z'] - rb['Z']).max():.3e}")
+    assert np.abs(ra["S"] - rb["S"]).max() <= 1e-11
+    assert np.abs(ra["Z"] - rb["Z"]).max() <= 1e-11
+    a.close(); b.close()
