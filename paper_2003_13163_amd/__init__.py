@@ -65,6 +65,10 @@ def library() -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: libmpo.so must bind to the HIP runtime torch has loaded (the
+    # arena and the stream come from torch); loaded the other way round, the
+    # process holds two runtimes and the library's pinned allocations fail
+    import torch  # noqa: F401
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is missing: run `python -m paper_2003_13163_amd.build` "
                           "(or __graft_entry__.build()) first; there is no CPU fallback")

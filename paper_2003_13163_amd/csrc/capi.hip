@@ -986,6 +986,7 @@ mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis, v
     h->jw.inner = prec == MPO_FP64 ? 2 : 1;
     if (const char* e = std::getenv("MPO_JACOBI_BLOCK")) h->jw.block = std::atoi(e) == 16 ? 16 : 32;
     if (const char* e = std::getenv("MPO_JACOBI_INNER")) h->jw.inner = std::max(1, std::min(8, std::atoi(e)));
+    h->jw.trace = std::getenv("MPO_JACOBI_TRACE") != nullptr;
     h->envL = (double2*)p; p += L.env_bytes;
     h->envR = (double2*)p; p += L.env_bytes;
     h->tscr = (double2*)p; p += L.tscr_bytes;

@@ -152,7 +152,8 @@ struct JacobiWork {
     Profiler* prof;        // may be off
     int block;             // Jacobi block width: 16 or 32 columns
     int inner;             // inner FP64 sweeps per block pair
-    bool bf3;              // Gram and rotations as split-BF16x3 products (FP32 storage)
+    bool bf3;              // Gram as split-BF16x3 products (FP32 storage)
+    bool trace;            // print each sweep's convergence to stderr
     long long n_splits, n_sweeps, n_rounds, n_rotations;   // running counters
 };
 

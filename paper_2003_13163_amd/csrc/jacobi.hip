@@ -13,6 +13,7 @@
 #include <hip/hip_ext.h>
 
 #include "common.h"
+#include <cstdio>
 #include <cstring>
 
 namespace mpo {
@@ -873,6 +874,9 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
         std::memcpy(&off, &bits, sizeof(off));
         const int rot = w.info_host->rotations;
         w.n_rotations += rot;
+        if (w.trace)
+            std::fprintf(stderr, "jacobi %dx%d sweep %d: max rel off-diagonal %.3e, %d of %d pairs x %d rounds rotated\n",
+                         m, N, sweep, off, rot, P, nb - 1);
         pf.add_work(K_UPDATE, rot * pair_flops, rot * 2.0 * pair_bytes);
         // each inner step applies a two-sided 2x2 transform to all NB^2 entries of G
         // (22 real flops per entry) and a column rotation to W (11 per entry)
