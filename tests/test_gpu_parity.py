@@ -348,6 +348,26 @@ def test_adjoint_vs_oracle_dense(pm, basis, chi):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16x3", 2e-3)])
+def test_adjoint_reduced_precision(pm, prec, tol):
+    # exact regime (no truncation): the forward differs from FP64 by rounding only,
+    # so the gradient carries the mode's relative error
+    from oracle import adjoint as oadj
+    n, depth, p, chi = 6, 4, 0.03, 64
+    say(f"case adjoint n={n} depth={depth} chi={chi} {prec}")
+    draws = mi.ginibre_draws(n, depth, seed=21)
+    sup = gates.circuit_superops(draws, p, "pauli")
+    sites, phis, _ = oadj.record_forward(n, sup, mi.brickwork_sites(n, depth), chi, 1e-12, "pauli")
+    O_ref, g_ref = oadj.frozen_gradient(n, sup, sites, phis, "pauli")
+    st = pm.Mpo(n, chi, prec, "pauli")
+    O, grads, comax = st.adjoint_brickwork(depth, sup, chi, 1e-12)
+    st.close()
+    err = np.abs(grads - g_ref).max() / np.abs(g_ref).max()
+    say(f"  O {O:.8f} vs {O_ref.real:.8f}  max grad err {err:.2e}")
+    assert abs(O - O_ref.real) <= tol * max(1.0, abs(O_ref))
+    assert err <= tol
+
+
 def test_adjoint_euler_identity_larger(pm):
     n, depth, p, chi = 12, 6, 0.01, 24
     say(f"case adjoint Euler identity n={n} depth={depth} chi={chi}")
