@@ -93,15 +93,58 @@ __global__ __launch_bounds__(1024) void k_sort_desc(const double* __restrict__ n
 // ------------------------------------------------------------- pair Gram
 // partials[(pair*splits + split)*NB*NB + i + NB*j] = sum_rows conj(x_i) x_j over
 // this split's row range, for the NB = 2*JB columns of the pair, in FP64.  The
-// Gram matrix is Hermitian, so only its upper 16x16 tiles are computed; each
-// wave takes a quarter of every staged slab of rows and accumulates all upper
-// tiles (TB column tiles loaded once per 4-row step feed TB(TB+1)/2 complex MFMA
-// products), slab sums are added in FP64 and the four waves are reduced in LDS.
-template <typename T, int JB, bool BF>
-__global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, int m, int N,
-                                                   const int* __restrict__ colmap, int nb,
-                                                   int round, int splits, int chunk,
-                                                   double2* __restrict__ partials) {
+// Gram matrix is Hermitian, so only its upper 16x16 tiles are computed (TB
+// column tiles loaded once per step feed TB(TB+1)/2 complex MFMA products) and
+// the lower ones are written as conjugates.  Each wave sums its products in the
+// working precision over a few dozen rows, then in FP64; the four waves of a
+// work-group are added in LDS.  One kernel per mode, each the fastest measured
+// on gfx950 for its operand size.
+
+// Adds the four waves' FP64 tile sums and writes the pair's NB x NB partial.
+template <typename T, int NB>
+__device__ __forceinline__ void gram_finish(const d4* sumR, const d4* sumI, double2* red,
+                                            double2* __restrict__ out) {
+    constexpr int TB = NB / 16, NU = TB * (TB + 1) / 2;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int idx = u * 256 + acc_row<T>(lane, r) + 16 * (lane & 15);
+                    if (w == 0) red[idx] = make_double2(sumR[u][r], sumI[u][r]);
+                    else { red[idx].x += sumR[u][r]; red[idx].y += sumI[u][r]; }
+                }
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < NB * NB; e += 256) {
+        const int i = e % NB, j = e / NB;
+        const int bi = i >> 4, bj = j >> 4;
+        double2 v;
+        if (bi <= bj) {
+            const int u = bi * TB - bi * (bi - 1) / 2 + (bj - bi);
+            v = red[u * 256 + (i & 15) + 16 * (j & 15)];
+        } else {
+            const int u = bj * TB - bj * (bj - 1) / 2 + (bi - bj);
+            const double2 w = red[u * 256 + (j & 15) + 16 * (i & 15)];
+            v = make_double2(w.x, -w.y);
+        }
+        out[i + NB * j] = v;
+    }
+}
+
+// Split-BF16x3 mode: 128-row slabs are staged in LDS by the whole work-group
+// (the next slab is loaded into registers while the current one is reduced);
+// each wave takes a quarter of every slab, 16 rows per step through
+// v_mfma_f32_16x16x16_bf16 with hi/lo operands.
+template <int JB>
+__global__ __launch_bounds__(256) void k_pair_gram_bf3(const float2* __restrict__ X, int m, int N,
+                                                       const int* __restrict__ colmap, int nb,
+                                                       int round, int splits, int chunk,
+                                                       double2* __restrict__ partials) {
+    using T = float;
     constexpr int NB = 2 * JB, TB = NB / 16, NU = TB * (TB + 1) / 2;
     constexpr int RB = 4096 / NB;              // rows per staged slab
     constexpr int RW = RB / 4;                 // rows of a slab per wave
@@ -154,7 +197,7 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
         for (int u = 0; u < NU; ++u)
 #pragma unroll
             for (int r = 0; r < 4; ++r) { accR[u][r] = T(0); accI[u][r] = T(0); }
-        if constexpr (BF) {
+        {
             for (int kk = wave * RW; kk < (wave + 1) * RW; kk += 16) {
                 const bf4 sign = {(short)0x8000, (short)0x8000, (short)0x8000, (short)0x8000};
                 CBF xb[TB], xa[TB];        // x and conj(x), rows kk + 4(l/16) + j
@@ -174,23 +217,6 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
 #pragma unroll
                     for (int bj = bi; bj < TB; ++bj, ++u) cmfma_bf3(accR[u], accI[u], xa[bi], xb[bj]);
             }
-        } else
-#pragma unroll 2
-        for (int kk = wave * RW; kk < (wave + 1) * RW; kk += 4) {
-            C2<T> x[TB];
-#pragma unroll
-            for (int b = 0; b < TB; ++b) x[b] = Xs[kk + (lane >> 4)][b * 16 + (lane & 15)];
-            int u = 0;
-#pragma unroll
-            for (int bi = 0; bi < TB; ++bi)
-#pragma unroll
-                for (int bj = bi; bj < TB; ++bj, ++u) {
-                    // conj(x_bi) x_bj: (ar - i ai)(br + i bi)
-                    accR[u] = mfma16(x[bi].x, x[bj].x, accR[u]);
-                    accR[u] = mfma16(x[bi].y, x[bj].y, accR[u]);
-                    accI[u] = mfma16(x[bi].x, x[bj].y, accI[u]);
-                    accI[u] = mfma16(-x[bi].y, x[bj].x, accI[u]);
-                }
         }
 #pragma unroll
         for (int u = 0; u < NU; ++u)
@@ -201,35 +227,253 @@ __global__ __launch_bounds__(256) void k_pair_gram(const C2<T>* __restrict__ X, 
             }
         __syncthreads();
     }
-    // reduce the four waves' tiles in LDS
-    for (int w = 0; w < 4; ++w) {
-        if (wave == w) {
+    gram_finish<T, NB>(sumR, sumI, red, partials + (size_t)(pair * splits + split) * (NB * NB));
+}
+
+// FP64 mode: every wave works through its own rows with no work-group barrier
+// in the main loop; wave w takes rows [s, s + WR) of every 4*WR-row slab of the
+// split's range.  A slab (NB columns x WR rows, 8 KiB) is read with coalesced
+// 16-byte loads, 16 lanes covering 256 contiguous bytes of one column, and
+// transposed through a wave-private LDS buffer (column pitch 17 x 16 bytes, so
+// that both the stores and the 16-byte operand reads meet the minimum bank
+// multiplicity) into MFMA operand layout.  The rows of a dot product may be
+// summed in any order as long as both operands follow it: lane (i, k) takes 16
+// contiguous bytes of column i (one FP64 row, two FP32 rows) as its k-th
+// operand.  The next slab's loads are in flight while the current one is
+// multiplied.
+template <typename T> struct GramLoad;
+template <> struct GramLoad<float> { using type = float4; };     // re, im of rows r, r+1
+template <> struct GramLoad<double> { using type = double2; };   // re, im of row r
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int JB>
+__global__ __launch_bounds__(256) void k_pair_gram_lds(const C2<T>* __restrict__ X, int m, int N,
+                                                       const int* __restrict__ colmap, int nb,
+                                                       int round, int splits, int chunk,
+                                                       double2* __restrict__ partials) {
+    constexpr int NB = 2 * JB, TB = NB / 16, NU = TB * (TB + 1) / 2;
+    constexpr int E = 16 / (int)sizeof(C2<T>);   // rows per 16-byte unit
+    constexpr int NS = 4;                         // MFMA k-steps per slab
+    constexpr int WR = NS * 4 * E;                // rows per wave and slab (16 units)
+    constexpr int NI = NB / 4;                    // 16-byte loads per lane and slab
+    constexpr int PW = 17;                        // column pitch in 16-byte units
+    using LV = typename GramLoad<T>::type;
+    __shared__ LV slab[4][NB * PW];
+    __shared__ double2 red[NU * 256];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int pair = blockIdx.x, split = blockIdx.y;
+    int p, q;
+    pair_of(round, pair, nb, p, q);
+    // load layout: lane l reads unit (l & 15) of column 4j + (l >> 4) in load j
+    const int lu = lane & 15;
+    const C2<T>* colp[NI];
+    bool live[NI];
 #pragma unroll
-            for (int u = 0; u < NU; ++u)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int idx = u * 256 + acc_row<T>(lane, r) + 16 * (lane & 15);
-                    if (w == 0) red[idx] = make_double2(sumR[u][r], sumI[u][r]);
-                    else { red[idx].x += sumR[u][r]; red[idx].y += sumI[u][r]; }
-                }
-        }
-        __syncthreads();
+    for (int j = 0; j < NI; ++j) {
+        const int c = 4 * j + (lane >> 4);
+        const int lj = c < JB ? p * JB + c : q * JB + (c - JB);
+        const int col = lj < N ? colmap[lj] : -1;
+        live[j] = col >= 0;
+        colp[j] = X + (size_t)m * (live[j] ? col : 0);
     }
-    double2* out = partials + (size_t)(pair * splits + split) * (NB * NB);
-    for (int e = t; e < NB * NB; e += 256) {
-        const int i = e % NB, j = e / NB;
-        const int bi = i >> 4, bj = j >> 4;
-        double2 v;
-        if (bi <= bj) {
-            const int u = bi * TB - bi * (bi - 1) / 2 + (bj - bi);
-            v = red[u * 256 + (i & 15) + 16 * (j & 15)];
+    const int r0 = split * chunk;
+    const int r1 = min(m, r0 + chunk);
+    const bool aligned = (m % E) == 0;            // 16-byte loads need an even column length in FP32
+    auto load = [&](int j, int row) -> LV {
+        if constexpr (E == 2) {
+            if (live[j] && aligned && row + 1 < r1) return *reinterpret_cast<const float4*>(colp[j] + row);
+            const float2 a = (live[j] && row < r1) ? colp[j][row] : make_float2(0.f, 0.f);
+            const float2 c = (live[j] && row + 1 < r1) ? colp[j][row + 1] : make_float2(0.f, 0.f);
+            return make_float4(a.x, a.y, c.x, c.y);
         } else {
-            const int u = bj * TB - bj * (bj - 1) / 2 + (bi - bj);
-            const double2 w = red[u * 256 + (j & 15) + 16 * (i & 15)];
-            v = make_double2(w.x, -w.y);
+            return (live[j] && row < r1) ? colp[j][row] : make_double2(0.0, 0.0);
         }
-        out[i + NB * j] = v;
+    };
+    LV* ls = slab[wave];
+    const int ci = lane & 15, kq = lane >> 4;
+    A4<T> accR[NU], accI[NU];
+    d4 sumR[NU], sumI[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { sumR[u][r] = 0.0; sumI[u][r] = 0.0; }
+    LV nxt[NI];
+    int s = r0 + wave * WR;
+    if (s < r1) {
+#pragma unroll
+        for (int j = 0; j < NI; ++j) nxt[j] = load(j, s + lu * E);
     }
+    for (; s < r1; s += 4 * WR) {
+#pragma unroll
+        for (int j = 0; j < NI; ++j) ls[(4 * j + (lane >> 4)) * PW + lu] = nxt[j];
+        wave_sync();
+        const int sn = s + 4 * WR;
+        if (sn < r1) {
+#pragma unroll
+            for (int j = 0; j < NI; ++j) nxt[j] = load(j, sn + lu * E);
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { accR[u][r] = T(0); accI[u][r] = T(0); }
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            LV v[TB];
+#pragma unroll
+            for (int b = 0; b < TB; ++b) v[b] = ls[(b * 16 + ci) * PW + 4 * st + kq];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                T xr[TB], xi[TB];
+#pragma unroll
+                for (int b = 0; b < TB; ++b) {
+                    if constexpr (E == 2) {
+                        xr[b] = e == 0 ? v[b].x : v[b].z;
+                        xi[b] = e == 0 ? v[b].y : v[b].w;
+                    } else {
+                        xr[b] = v[b].x;
+                        xi[b] = v[b].y;
+                    }
+                }
+                int u = 0;
+#pragma unroll
+                for (int bi = 0; bi < TB; ++bi)
+#pragma unroll
+                    for (int bj = bi; bj < TB; ++bj, ++u) {
+                        // conj(x_bi) x_bj: (ar - i ai)(br + i bi)
+                        accR[u] = mfma16(xr[bi], xr[bj], accR[u]);
+                        accR[u] = mfma16(xi[bi], xi[bj], accR[u]);
+                        accI[u] = mfma16(xr[bi], xi[bj], accI[u]);
+                        accI[u] = mfma16(-xi[bi], xr[bj], accI[u]);
+                    }
+            }
+        }
+        wave_sync();   // the slab buffer is rewritten next
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                sumR[u][r] += (double)accR[u][r];
+                sumI[u][r] += (double)accI[u][r];
+            }
+    }
+    gram_finish<T, NB>(sumR, sumI, red, partials + (size_t)(pair * splits + split) * (NB * NB));
+}
+
+// FP32 mode: as in the FP64 kernel, but lane (i, k) loads its 16 bytes of
+// column i straight into operand registers (16 columns x 64 bytes per load),
+// with no LDS in the main loop.  The loads are less regular than the LDS
+// kernel's (the 16 columns of a load share L1 sets when m is a power of two),
+// but on gfx950 this measured faster for FP32, whose slab carries half the MFMA
+// work of an FP64 one; for FP64 the LDS kernel is faster.
+template <typename T, int JB>
+__global__ __launch_bounds__(256) void k_pair_gram_regs(const C2<T>* __restrict__ X, int m, int N,
+                                                        const int* __restrict__ colmap, int nb,
+                                                        int round, int splits, int chunk,
+                                                        double2* __restrict__ partials) {
+    constexpr int NB = 2 * JB, TB = NB / 16, NU = TB * (TB + 1) / 2;
+    constexpr int E = 16 / (int)sizeof(C2<T>);
+    constexpr int NS = 4;
+    constexpr int WR = NS * 4 * E;
+    using LV = typename GramLoad<T>::type;
+    __shared__ double2 red[NU * 256];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int ci = lane & 15, kq = lane >> 4;
+    const int pair = blockIdx.x, split = blockIdx.y;
+    int p, q;
+    pair_of(round, pair, nb, p, q);
+    const C2<T>* colp[TB];
+    bool live[TB];
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+        const int c = b * 16 + ci;
+        const int lj = c < JB ? p * JB + c : q * JB + (c - JB);
+        const int col = lj < N ? colmap[lj] : -1;
+        live[b] = col >= 0;
+        colp[b] = X + (size_t)m * (live[b] ? col : 0);
+    }
+    const int r0 = split * chunk;
+    const int r1 = min(m, r0 + chunk);
+    const bool aligned = (m % E) == 0;
+    auto load = [&](int b, int row) -> LV {
+        if constexpr (E == 2) {
+            if (live[b] && aligned && row + 1 < r1) return *reinterpret_cast<const float4*>(colp[b] + row);
+            const float2 a = (live[b] && row < r1) ? colp[b][row] : make_float2(0.f, 0.f);
+            const float2 c = (live[b] && row + 1 < r1) ? colp[b][row + 1] : make_float2(0.f, 0.f);
+            return make_float4(a.x, a.y, c.x, c.y);
+        } else {
+            return (live[b] && row < r1) ? colp[b][row] : make_double2(0.0, 0.0);
+        }
+    };
+    A4<T> accR[NU], accI[NU];
+    d4 sumR[NU], sumI[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { sumR[u][r] = 0.0; sumI[u][r] = 0.0; }
+    LV cur[TB][NS], nxt[TB][NS];
+    int s = r0 + wave * WR;
+    if (s < r1) {
+#pragma unroll
+        for (int st = 0; st < NS; ++st)
+#pragma unroll
+            for (int b = 0; b < TB; ++b) cur[b][st] = load(b, s + st * 4 * E + kq * E);
+    }
+    for (; s < r1; s += 4 * WR) {
+        const int sn = s + 4 * WR;
+        if (sn < r1) {
+#pragma unroll
+            for (int st = 0; st < NS; ++st)
+#pragma unroll
+                for (int b = 0; b < TB; ++b) nxt[b][st] = load(b, sn + st * 4 * E + kq * E);
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { accR[u][r] = T(0); accI[u][r] = T(0); }
+#pragma unroll
+        for (int st = 0; st < NS; ++st)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                T xr[TB], xi[TB];
+#pragma unroll
+                for (int b = 0; b < TB; ++b) {
+                    if constexpr (E == 2) {
+                        xr[b] = e == 0 ? cur[b][st].x : cur[b][st].z;
+                        xi[b] = e == 0 ? cur[b][st].y : cur[b][st].w;
+                    } else {
+                        xr[b] = cur[b][st].x;
+                        xi[b] = cur[b][st].y;
+                    }
+                }
+                int u = 0;
+#pragma unroll
+                for (int bi = 0; bi < TB; ++bi)
+#pragma unroll
+                    for (int bj = bi; bj < TB; ++bj, ++u) {
+                        accR[u] = mfma16(xr[bi], xr[bj], accR[u]);
+                        accR[u] = mfma16(xi[bi], xi[bj], accR[u]);
+                        accI[u] = mfma16(xr[bi], xi[bj], accI[u]);
+                        accI[u] = mfma16(-xi[bi], xr[bj], accI[u]);
+                    }
+            }
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                sumR[u][r] += (double)accR[u][r];
+                sumI[u][r] += (double)accI[u][r];
+            }
+#pragma unroll
+        for (int st = 0; st < NS; ++st)
+#pragma unroll
+            for (int b = 0; b < TB; ++b) cur[b][st] = nxt[b][st];
+    }
+    gram_finish<T, NB>(sumR, sumI, red, partials + (size_t)(pair * splits + split) * (NB * NB));
 }
 
 // --------------------------------------------------- NB x NB Hermitian eigen (FP64)
@@ -848,9 +1092,18 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
         for (int r = 0; r < nb - 1; ++r) {
             hipEvent_t a, b;
             pf.stamps(a, b);
-            hipExtLaunchKernelGGL((k_pair_gram<T, JB, BF>), dim3(P, splits), dim3(256), 0, st, a, b, 0,
-                                  X, m, N, (const int*)w.colmap, nb, r, splits, chunk,
-                                  (double2*)w.gram_partials);
+            if constexpr (BF)
+                hipExtLaunchKernelGGL((k_pair_gram_bf3<JB>), dim3(P, splits), dim3(256), 0, st, a, b, 0,
+                                      X, m, N, (const int*)w.colmap, nb, r, splits, chunk,
+                                      (double2*)w.gram_partials);
+            else if constexpr (sizeof(T) == 4)
+                hipExtLaunchKernelGGL((k_pair_gram_regs<T, JB>), dim3(P, splits), dim3(256), 0, st, a,
+                                      b, 0, X, m, N, (const int*)w.colmap, nb, r, splits, chunk,
+                                      (double2*)w.gram_partials);
+            else
+                hipExtLaunchKernelGGL((k_pair_gram_lds<T, JB>), dim3(P, splits), dim3(256), 0, st, a,
+                                      b, 0, X, m, N, (const int*)w.colmap, nb, r, splits, chunk,
+                                      (double2*)w.gram_partials);
             pf.record(K_GRAM, a, b, P * pair_flops, P * pair_bytes + (double)P * splits * NB * NB * 16.0);
             pf.stamps(a, b);
             hipExtLaunchKernelGGL((k_pair_eig<T, JB>), dim3(P), dim3(kEigThreads), 0, st, a, b, 0,
