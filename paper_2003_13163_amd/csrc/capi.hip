@@ -145,9 +145,10 @@ double eps_of(size_t csz) { return csz == 16 ? 2.220446049250313e-16 : 1.1920928
 // Split-BF16x3: every product term carries a relative error up to about
 // 2^-15, so the off-diagonal measure has noise up to about 3e-5; 1e-4 is
 // reachable and keeps the rotations' own error (2^-16 per update) below it.
+// Those sweeps are followed by FP32-MFMA Gram sweeps down to kTolFp32.
 double jacobi_tol(const mpo_handle* h, int m) {
     if (h->csz == 16) return std::fmax(1e-14, 8.0 * std::sqrt((double)m) * eps_of(h->csz));
-    return h->bf3 ? 1e-4 : 2e-6;
+    return h->bf3 ? 1e-4 : kTolFp32;
 }
 // singular values at or below this fraction of ||lambda||_2 carry no weight
 // above rounding and are dropped by exact re-gauging moves

@@ -120,6 +120,7 @@ struct DevInfo {
     unsigned long long offmax_bits;  // max relative off-diagonal of the sweep (bits of a double >= 0)
     int rotations;         // pairs rotated in the sweep
     int inner_steps;       // inner Jacobi steps executed in the sweep (all pairs)
+    int scale_exp;         // X is held scaled by 2^scale_exp during the sweeps (FP32 storage)
 };
 
 }  // namespace mpo
@@ -170,6 +171,12 @@ int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps,
 // the truncation never keeps them.
 template <typename T> constexpr double jacobi_zero_rel2() { return sizeof(T) == 8 ? 1e-30 : 1e-14; }
 constexpr double kZeroRel2Bf3 = 1e-9;   // the same floor for split-BF16x3 products
+// Relative orthogonality the FP32-storage sweeps reach with an FP32-MFMA Gram.
+// In split-BF16x3 mode the sweeps with the BF16x3 Gram stop at the looser
+// tolerance its 16-bit products allow, and sweeps with the FP32-MFMA Gram then
+// polish the columns to this one, so that every isometry the mode produces is
+// as orthonormal as in FP32 mode.
+constexpr double kTolFp32 = 2e-6;
 
 // Truncation + entropy from the sorted squared norms (single work-group).
 void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,

@@ -14,6 +14,7 @@
 
 #include "common.h"
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 
 namespace mpo {
@@ -1058,9 +1059,47 @@ __global__ void k_copy(const C2<T>* __restrict__ s, C2<T>* __restrict__ d, size_
     if (i < n) d[i] = s[i];
 }
 
+// Power-of-two scaling of X in the FP32-storage modes.  FP32 products of
+// entries far below 1 leave the normal range (a state of total weight 1e-27 has
+// entries near 1e-17, whose products are denormal or zero), which corrupts the
+// Gram of the small columns and stalls the sweeps.  Before the first sweep X
+// is scaled by 2^k, k chosen from ||X||_F so that the scaled norm lies in
+// [1/2, 1); after the last one the factor is removed from X, the sorted squared
+// norms and ||X||_F^2.  Scaling by a power of two is exact.
+__global__ void k_scale_exp(DevInfo* info, double* fro2, int undo) {
+    if (threadIdx.x != 0) return;
+    if (!undo) {
+        int e = 0;
+        const double f = *fro2;
+        if (f > 0.0 && isfinite(f)) (void)frexp(sqrt(f), &e);
+        info->scale_exp = -e;
+        *fro2 = ldexp(f, -2 * e);
+    } else {
+        *fro2 = ldexp(*fro2, -2 * info->scale_exp);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale_apply(C2<T>* __restrict__ X, size_t n,
+                                                     const DevInfo* __restrict__ info,
+                                                     double* __restrict__ sig2, int N, int undo) {
+    const int k = undo ? -info->scale_exp : info->scale_exp;
+    if (k == 0) return;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        C2<T> v = X[i];
+        v.x = ldexp(v.x, k);
+        v.y = ldexp(v.y, k);
+        X[i] = v;
+    }
+    if (undo && sig2)
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)N; i += stride)
+            sig2[i] = ldexp(sig2[i], 2 * k);
+}
+
 // ------------------------------------------------------------------- host side
 template <typename T, int JB, bool BF>
-static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int inner_max,
+static int jacobi_run(C2<T>* X, int m, int N, double tol, double zrel2, int max_sweeps, int inner_max,
                       JacobiWork& w, hipStream_t st) {
     constexpr int NB = 2 * JB;
     int nb = (N + JB - 1) / JB;
@@ -1075,18 +1114,30 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
     chunk = (chunk + RB - 1) / RB * RB;
     splits = (m + chunk - 1) / chunk;
     if (splits < 1) splits = 1;
-    const double zrel2 = BF ? kZeroRel2Bf3 : jacobi_zero_rel2<T>();
     double* fro2 = &w.info->total;   // scratch slot reused for ||X||_F^2
     const dim3 gnorm((N + 3) / 4);
     Profiler& pf = *w.prof;
     const double csz = 2.0 * sizeof(T);
     const double pair_flops = 8.0 * m * NB * NB;      // one NB x NB complex product over m rows
     const double pair_bytes = (double)m * NB * csz;
-    w.n_splits += 1;
+    // FP32 storage: X is held scaled by a power of two during the sweeps
+    constexpr bool scaled = sizeof(T) == 4;
+    const dim3 gscale((unsigned)std::min<size_t>(2048, ((size_t)m * N + 255) / 256));
+    auto unscale = [&](bool with_values) {
+        if (!scaled) return;
+        hipLaunchKernelGGL((k_scale_apply<T>), gscale, dim3(256), 0, st, X, (size_t)m * N,
+                           (const DevInfo*)w.info, with_values ? w.sig2 : (double*)nullptr, N, 1);
+        hipLaunchKernelGGL(k_scale_exp, dim3(1), dim3(64), 0, st, w.info, fro2, 1);
+    };
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         pf.begin(st);
         hipLaunchKernelGGL((k_colnorm2<T>), gnorm, dim3(256), 0, st, X, m, N, w.nrm2);
         hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, w.nrm2, N, w.colmap, w.sig2, fro2);
+        if (scaled && sweep == 0) {
+            hipLaunchKernelGGL(k_scale_exp, dim3(1), dim3(64), 0, st, w.info, fro2, 0);
+            hipLaunchKernelGGL((k_scale_apply<T>), gscale, dim3(256), 0, st, X, (size_t)m * N,
+                               (const DevInfo*)w.info, (double*)nullptr, N, 0);
+        }
         pf.end(st, K_NORMSORT, 8.0 * m * N, (double)m * N * csz);
         (void)hipMemsetAsync(&w.info->offmax_bits, 0, sizeof(unsigned long long) + 2 * sizeof(int), st);
         for (int r = 0; r < nb - 1; ++r) {
@@ -1138,24 +1189,37 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, int max_sweeps, int in
             pf.begin(st);
             hipLaunchKernelGGL((k_colnorm2<T>), gnorm, dim3(256), 0, st, X, m, N, w.nrm2);
             hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, w.nrm2, N, w.colmap, w.sig2, fro2);
+            unscale(true);
             pf.end(st, K_NORMSORT, 8.0 * m * N, (double)m * N * csz);
             return sweep + 1;
         }
     }
+    unscale(false);
     return -1;
 }
 
 template <typename T>
 int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, JacobiWork& w,
                          hipStream_t st) {
+    w.n_splits += 1;
     if constexpr (sizeof(T) == 4) {
         if (w.bf3) {
-            if (w.block == 16) return jacobi_run<T, 16, true>(X, m, N, tol, max_sweeps, w.inner, w, st);
-            return jacobi_run<T, 32, true>(X, m, N, tol, max_sweeps, w.inner, w, st);
+            // BF16x3 Gram down to tol, then the FP32-MFMA Gram down to kTolFp32,
+            // both with the BF16x3 zero floor
+            const int s1 = w.block == 16
+                ? jacobi_run<T, 16, true>(X, m, N, tol, kZeroRel2Bf3, max_sweeps, w.inner, w, st)
+                : jacobi_run<T, 32, true>(X, m, N, tol, kZeroRel2Bf3, max_sweeps, w.inner, w, st);
+            if (s1 < 0) return s1;
+            if (tol <= kTolFp32) return s1;
+            const int s2 = w.block == 16
+                ? jacobi_run<T, 16, false>(X, m, N, kTolFp32, kZeroRel2Bf3, max_sweeps - s1, w.inner, w, st)
+                : jacobi_run<T, 32, false>(X, m, N, kTolFp32, kZeroRel2Bf3, max_sweeps - s1, w.inner, w, st);
+            return s2 < 0 ? s2 : s1 + s2;
         }
     }
-    if (w.block == 16) return jacobi_run<T, 16, false>(X, m, N, tol, max_sweeps, w.inner, w, st);
-    return jacobi_run<T, 32, false>(X, m, N, tol, max_sweeps, w.inner, w, st);
+    const double zrel2 = jacobi_zero_rel2<T>();
+    if (w.block == 16) return jacobi_run<T, 16, false>(X, m, N, tol, zrel2, max_sweeps, w.inner, w, st);
+    return jacobi_run<T, 32, false>(X, m, N, tol, zrel2, max_sweeps, w.inner, w, st);
 }
 
 void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,

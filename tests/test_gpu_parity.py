@@ -163,6 +163,45 @@ def test_bulk_gate_singular_values(pm, chi, prec, tol):
     st.close()
 
 
+def test_bulk_gate_full_size_all_modes(pm):
+    # the benchmarked shape: chi_L = chi_M = chi_R = 1024, theta' 4096 x 4096, the
+    # same split and kernel launches as a timed bulk gate; the oracle gate (a
+    # complex128 SVD of theta') runs once and every precision mode is checked
+    # against it: kept count, entropy, the Schmidt values of the bond, and the
+    # trace and discarded weight
+    n, chi = 12, 1024
+    dims = [min(chi, 4 ** min(b + 1, n - b - 1)) for b in range(n - 1)]
+    ts = random_mps(n, dims, seed=chi)
+    for s in range(n):
+        ts[s] *= np.exp(-0.01 * np.arange(ts[s].shape[2]))[None, None, :]
+    s0 = n // 2 - 1
+    sup = gates.circuit_superops(mi.ginibre_draws(2, 1, seed=5), 0.01, "pauli")[0]
+    say(f"case bulk gate chi={chi}: oracle gate on the CPU (about a minute)")
+    ref = oracle_from(ts)
+    rinfo = ref.apply_gate(s0, sup, chi, 1e-12)
+    lam_ref = ref.schmidt_sweep()[s0]
+    say(f"  oracle kept {rinfo.kept} S {rinfo.entropy:.6f}")
+    # BF16x3 stops its sweeps at a relative orthogonality of 1e-4, so each of
+    # the ~2(n-1) re-gauging moves that canonicalise the imported state leaves
+    # the isometries exact to ~1e-4: a few 1e-3 in weight, 1e-3 in entropy
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4), ("bf16x3", 1e-3)):
+        st = pm.Mpo(n, chi, prec, "pauli")
+        st.import_state(pm.tensors_to_snapshot(ts))
+        info = st.apply(s0, sup, chi, 1e-12)
+        lam_gpu = st.singular_values(s0)
+        k = min(lam_ref.size, lam_gpu.size)
+        dlam = np.abs(lam_gpu[:k] - lam_ref[:k]).max() / lam_ref[0]
+        say(f"  {prec}: kept {info.kept} dS {info.entropy - rinfo.entropy:.3e} dlam {dlam:.3e}")
+        assert info.kept == rinfo.kept
+        assert abs(info.entropy - rinfo.entropy) <= tol
+        assert dlam <= tol
+        assert abs(info.total_weight - rinfo.total_weight) <= 10 * tol * rinfo.total_weight
+        assert abs(info.discarded_weight - rinfo.discarded_weight) <= 10 * tol * rinfo.total_weight
+        if prec != "bf16x3":
+            assert abs(info.total_weight - rinfo.total_weight) <= tol * rinfo.total_weight
+        st.close()
+
+
 # -------------------------------------------------------- truncating circuit n=32
 def test_n32_truncating_fp64_vs_oracle(pm):
     path = os.path.join(HERE, "golden", "oracle_n32_d32_p0.01_chi256.json")
