@@ -177,6 +177,7 @@ constexpr double kZeroRel2Bf3 = 1e-9;   // the same floor for split-BF16x3 produ
 // polish the columns to this one, so that every isometry the mode produces is
 // as orthonormal as in FP32 mode.
 constexpr double kTolFp32 = 2e-6;
+constexpr double kBf3Handoff = 3e-3;
 
 // Truncation + entropy from the sorted squared norms (single work-group).
 void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,

@@ -1099,8 +1099,8 @@ __global__ __launch_bounds__(256) void k_scale_apply(C2<T>* __restrict__ X, size
 
 // ------------------------------------------------------------------- host side
 template <typename T, int JB, bool BF>
-static int jacobi_run(C2<T>* X, int m, int N, double tol, double zrel2, int max_sweeps, int inner_max,
-                      JacobiWork& w, hipStream_t st) {
+static int jacobi_run(C2<T>* X, int m, int N, double tol, double stop_off, double zrel2, int max_sweeps,
+                      int inner_max, JacobiWork& w, hipStream_t st) {
     constexpr int NB = 2 * JB;
     int nb = (N + JB - 1) / JB;
     if (nb < 2) nb = 2;
@@ -1185,7 +1185,7 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, double zrel2, int max_
         // each inner step applies a two-sided 2x2 transform to all NB^2 entries of G
         // (22 real flops per entry) and a column rotation to W (11 per entry)
         pf.add_work(K_EIG, 33.0 * NB * NB * (double)w.info_host->inner_steps, 0.0);
-        if (rot == 0 || off <= tol) {
+        if (rot == 0 || off <= stop_off) {
             pf.begin(st);
             hipLaunchKernelGGL((k_colnorm2<T>), gnorm, dim3(256), 0, st, X, m, N, w.nrm2);
             hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, w.nrm2, N, w.colmap, w.sig2, fro2);
@@ -1198,28 +1198,34 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, double zrel2, int max_
     return -1;
 }
 
+// Sweeps stop when no pair rotated or when the largest relative off-diagonal
+// met at the start of the pairs is at most stop_off (= tol, except for the
+// first phase of split-BF16x3 mode).
 template <typename T>
 int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, JacobiWork& w,
                          hipStream_t st) {
     w.n_splits += 1;
     if constexpr (sizeof(T) == 4) {
         if (w.bf3) {
-            // BF16x3 Gram down to tol, then the FP32-MFMA Gram down to kTolFp32,
-            // both with the BF16x3 zero floor
+            // BF16x3 Gram until a sweep starts within kBf3Handoff of orthogonal
+            // (convergence is quadratic there, so it ends near 1e-5), then the
+            // FP32-MFMA Gram down to kTolFp32; both with the BF16x3 zero floor
+            const double hand = std::fmax(tol, kBf3Handoff);
             const int s1 = w.block == 16
-                ? jacobi_run<T, 16, true>(X, m, N, tol, kZeroRel2Bf3, max_sweeps, w.inner, w, st)
-                : jacobi_run<T, 32, true>(X, m, N, tol, kZeroRel2Bf3, max_sweeps, w.inner, w, st);
-            if (s1 < 0) return s1;
-            if (tol <= kTolFp32) return s1;
+                ? jacobi_run<T, 16, true>(X, m, N, tol, hand, kZeroRel2Bf3, max_sweeps, w.inner, w, st)
+                : jacobi_run<T, 32, true>(X, m, N, tol, hand, kZeroRel2Bf3, max_sweeps, w.inner, w, st);
+            if (s1 < 0 || tol <= kTolFp32) return s1;
             const int s2 = w.block == 16
-                ? jacobi_run<T, 16, false>(X, m, N, kTolFp32, kZeroRel2Bf3, max_sweeps - s1, w.inner, w, st)
-                : jacobi_run<T, 32, false>(X, m, N, kTolFp32, kZeroRel2Bf3, max_sweeps - s1, w.inner, w, st);
+                ? jacobi_run<T, 16, false>(X, m, N, kTolFp32, kTolFp32, kZeroRel2Bf3, max_sweeps - s1,
+                                           w.inner, w, st)
+                : jacobi_run<T, 32, false>(X, m, N, kTolFp32, kTolFp32, kZeroRel2Bf3, max_sweeps - s1,
+                                           w.inner, w, st);
             return s2 < 0 ? s2 : s1 + s2;
         }
     }
     const double zrel2 = jacobi_zero_rel2<T>();
-    if (w.block == 16) return jacobi_run<T, 16, false>(X, m, N, tol, zrel2, max_sweeps, w.inner, w, st);
-    return jacobi_run<T, 32, false>(X, m, N, tol, zrel2, max_sweeps, w.inner, w, st);
+    if (w.block == 16) return jacobi_run<T, 16, false>(X, m, N, tol, tol, zrel2, max_sweeps, w.inner, w, st);
+    return jacobi_run<T, 32, false>(X, m, N, tol, tol, zrel2, max_sweeps, w.inner, w, st);
 }
 
 void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,
