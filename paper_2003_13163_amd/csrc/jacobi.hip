@@ -242,6 +242,7 @@ __global__ __launch_bounds__(256) void k_pair_gram_bf3(const float2* __restrict_
 // contiguous bytes of column i (one FP64 row, two FP32 rows) as its k-th
 // operand.  The next slab's loads are in flight while the current one is
 // multiplied.
+// 16 bytes of one column: two FP32 rows or one FP64 row (Gram and update loads)
 template <typename T> struct GramLoad;
 template <> struct GramLoad<float> { using type = float4; };     // re, im of rows r, r+1
 template <> struct GramLoad<double> { using type = double2; };   // re, im of row r
@@ -810,7 +811,7 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
     const int pair = blockIdx.x;
     if (skip[pair]) return;
     __shared__ C2<T> Ws[NB][NB + 1];   // Ws[k][j] = W[k][j]
-    __shared__ C2<T> Xt[NB][64 + 1];   // Xt[col][row]
+    __shared__ __align__(16) C2<T> Xt[NB][64 + 2];   // Xt[col][row], rows in 16-byte aligned pairs
     __shared__ int cols[NB];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
@@ -825,17 +826,29 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
     constexpr int kUpdateSlabs = update_slabs<T>();
     // W stays in LDS for kUpdateSlabs consecutive 64-row slabs; the next slab
     // is loaded into registers while the current one is multiplied
-    constexpr int LE = NB * 64 / 256;
-    C2<T> pre[LE];
+    // each lane moves 16 bytes: two FP32 rows or one FP64 row of a column
+    constexpr int E = 16 / (int)sizeof(C2<T>), RU = 64 / E;   // rows per unit, units per column
+    constexpr int LE = NB * RU / 256;
+    using LV = typename GramLoad<T>::type;
+    const bool even = (m % E) == 0;
+    auto gload = [&](int r0, int e) -> LV {
+        const int row = (e % RU) * E, c = cols[e / RU];
+        const C2<T>* src = X + (size_t)m * (c >= 0 ? c : 0) + r0 + row;
+        if constexpr (E == 2) {
+            if (c >= 0 && even && r0 + row + 1 < m) return *reinterpret_cast<const float4*>(src);
+            const float2 a = (c >= 0 && r0 + row < m) ? src[0] : make_float2(0.f, 0.f);
+            const float2 b = (c >= 0 && r0 + row + 1 < m) ? src[1] : make_float2(0.f, 0.f);
+            return make_float4(a.x, a.y, b.x, b.y);
+        } else {
+            return (c >= 0 && r0 + row < m) ? src[0] : make_double2(0.0, 0.0);
+        }
+    };
+    LV pre[LE];
     __syncthreads();
     {
         const int r0 = blockIdx.y * kUpdateSlabs * 64;
 #pragma unroll
-        for (int r = 0; r < LE; ++r) {
-            const int e = t + 256 * r;
-            const int row = e & 63, c = cols[e >> 6];
-            pre[r] = (c >= 0 && r0 + row < m) ? X[(size_t)(r0 + row) + (size_t)m * c] : czero<T>();
-        }
+        for (int r = 0; r < LE; ++r) pre[r] = gload(r0, t + 256 * r);
     }
     for (int slab = 0; slab < kUpdateSlabs; ++slab) {
         const int r0 = (blockIdx.y * kUpdateSlabs + slab) * 64;
@@ -844,17 +857,13 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
 #pragma unroll
         for (int r = 0; r < LE; ++r) {
             const int e = t + 256 * r;
-            Xt[e >> 6][e & 63] = pre[r];
+            *reinterpret_cast<LV*>(&Xt[e / RU][(e % RU) * E]) = pre[r];
         }
         __syncthreads();
         if (slab + 1 < kUpdateSlabs && r0 + 64 < m) {
             const int r1 = r0 + 64;
 #pragma unroll
-            for (int r = 0; r < LE; ++r) {
-                const int e = t + 256 * r;
-                const int row = e & 63, c = cols[e >> 6];
-                pre[r] = (c >= 0 && r1 + row < m) ? X[(size_t)(r1 + row) + (size_t)m * c] : czero<T>();
-            }
+            for (int r = 0; r < LE; ++r) pre[r] = gload(r1, t + 256 * r);
         }
         // wave (wm, wn): rows wm*32 .. +32, columns wn*NB/2 .. +NB/2
         A4<T> accR[2][MB], accI[2][MB];
@@ -893,10 +902,17 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
                     Xt[col][row] = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
                 }
         __syncthreads();
-        for (int e = t; e < NB * 64; e += 256) {
-            const int row = e & 63, col = e >> 6;
+        for (int e = t; e < NB * RU; e += 256) {
+            const int row = (e % RU) * E, col = e / RU;
             const int c = cols[col];
-            if (c >= 0 && r0 + row < m) X[(size_t)(r0 + row) + (size_t)m * c] = Xt[col][row];
+            if (c < 0 || r0 + row >= m) continue;
+            C2<T>* dst = X + (size_t)m * c + r0 + row;
+            if (E == 1 || (even && r0 + row + E - 1 < m)) {
+                *reinterpret_cast<LV*>(dst) = *reinterpret_cast<const LV*>(&Xt[col][row]);
+            } else {
+                for (int u = 0; u < E; ++u)
+                    if (r0 + row + u < m) dst[u] = Xt[col][row + u];
+            }
         }
     }
 }
