@@ -52,16 +52,25 @@ typedef enum {
 typedef enum {
     MPO_FP64 = 0,       /* complex128 tensors, FP64 MFMA contractions        */
     MPO_FP32_MFMA = 1,  /* complex64 tensors and contractions on FP32 MFMA;
-                           truncation weights and entropy in FP64            */
+                           truncation weights and entropy in FP64.  Singular
+                           values with lambda^2 / sum lambda^2 <= 1e-10 are
+                           at the mode's rounding floor and are never kept.
+                           Any overall scale of the state is accepted: each
+                           decomposition works on a power-of-two rescaled
+                           copy of its matrix.                               */
     MPO_BF16X3 = 2      /* complex64 tensors; the two-site product, the
                            channel-fused theta, the centre moves and the
                            Jacobi Gram split each FP32 operand into BF16
                            hi + lo and sum three BF16 MFMA products in FP32
                            (about 16 significant bits, relative error of a
-                           product up to about 3e-5).  The Jacobi rotations,
-                           applied hundreds of times to each column, stay on
-                           FP32 MFMA; the eigen core, weights and entropy stay
-                           FP64.  Singular values with
+                           product up to about 3e-5).  Once the columns are
+                           within 3e-3 of orthogonal the Jacobi Gram switches
+                           to FP32 MFMA and the sweeps end at the FP32
+                           tolerance, so isometries are as orthonormal as in
+                           FP32 mode.  The Jacobi rotations, applied hundreds
+                           of times to each column, stay on FP32 MFMA; the
+                           eigen core, weights and entropy stay FP64.
+                           Singular values with
                            lambda^2 / sum lambda^2 <= 1e-9 are at the mode's
                            rounding floor and are never kept.                 */
 } mpo_precision;
