@@ -202,6 +202,38 @@ def test_bulk_gate_full_size_all_modes(pm):
         st.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-4)])
+def test_overall_scale_does_not_matter(pm, prec, tol):
+    # FP32 storage spans about 1e+-38: at an overall scale of 1e-16 the entries
+    # of theta are near 1e-19 and FP32 products of small columns would fall into
+    # the denormal range; each decomposition works on a power-of-two rescaled
+    # copy, so entropy and relative Schmidt values must not depend on the scale
+    n, chi = 8, 64
+    dims = [min(chi, 4 ** min(b + 1, n - b - 1)) for b in range(n - 1)]
+    ts = random_mps(n, dims, seed=11)
+    for s in range(n):
+        ts[s] *= np.exp(-0.05 * np.arange(ts[s].shape[2]))[None, None, :]
+    sup = gates.circuit_superops(mi.ginibre_draws(2, 1, seed=9), 0.01, "pauli")[0]
+    s0 = n // 2 - 1
+    say(f"case overall scale {prec}")
+    res = []
+    for f in (1.0, 0.01):   # per site: the state scales by f**n
+        st = pm.Mpo(n, chi, prec, "pauli")
+        st.import_state(pm.tensors_to_snapshot([t * f for t in ts]))
+        info = st.apply(s0, sup, chi, 1e-12)
+        lam = st.singular_values(s0)
+        res.append((info, lam / lam[0]))
+        st.close()
+    (i1, l1), (i2, l2) = res
+    k = min(l1.size, l2.size)
+    say(f"  dS {i2.entropy - i1.entropy:.3e} dlam {np.abs(l1[:k] - l2[:k]).max():.3e} "
+        f"weight ratio {i2.total_weight / i1.total_weight:.6e}")
+    assert i1.kept == i2.kept
+    assert abs(i1.entropy - i2.entropy) <= tol
+    assert np.abs(l1[:k] - l2[:k]).max() <= tol
+    assert abs(i2.total_weight / i1.total_weight / 0.01 ** (2 * n) - 1.0) <= 10 * tol
+
+
 # -------------------------------------------------------- truncating circuit n=32
 def test_n32_truncating_fp64_vs_oracle(pm):
     path = os.path.join(HERE, "golden", "oracle_n32_d32_p0.01_chi256.json")
