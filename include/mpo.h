@@ -53,7 +53,7 @@ typedef enum {
     MPO_FP64 = 0,       /* complex128 tensors, FP64 MFMA contractions        */
     MPO_FP32_MFMA = 1,  /* complex64 tensors and contractions on FP32 MFMA;
                            truncation weights and entropy in FP64.  Singular
-                           values with lambda^2 / sum lambda^2 <= 1e-10 are
+                           values with lambda^2 / sum lambda^2 <= 1e-9 are
                            at the mode's rounding floor and are never kept.
                            Any overall scale of the state is accepted: each
                            decomposition works on a power-of-two rescaled

@@ -154,7 +154,7 @@ double jacobi_tol(const mpo_handle* h, int m) {
 // above rounding and are dropped by exact re-gauging moves
 double regauge_cut(const mpo_handle* h) {
     if (h->bf3) return std::sqrt(kZeroRel2Bf3);
-    return h->csz == 16 ? 1e-15 : 1e-5;
+    return h->csz == 16 ? 1e-15 : std::sqrt(jacobi_zero_rel2<float>());
 }
 
 // Site dual vectors v[J] = Tr[P B_J] for the basis operators B_J.

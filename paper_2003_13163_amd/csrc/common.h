@@ -169,9 +169,11 @@ int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps,
 // Columns whose squared norm is at most this fraction of ||X||_F^2 are at the
 // rounding floor of the working precision: the sweep never rotates them and
 // the truncation never keeps them.  In FP32 storage the rounding of rotated
-// columns leaves noise near (2^-24 sqrt(#rotations))^2 ~ 4e-12 of ||X||_F^2.
-template <typename T> constexpr double jacobi_zero_rel2() { return sizeof(T) == 8 ? 1e-30 : 1e-10; }
-constexpr double kZeroRel2Bf3 = 1e-9;   // the same floor for split-BF16x3 products
+// columns leaves noise near (2^-24 sqrt(#rotations))^2 ~ 4e-12 of ||X||_F^2,
+// and the gates' own FP32 rounding accumulates above that; both FP32-storage
+// modes use 1e-9.
+template <typename T> constexpr double jacobi_zero_rel2() { return sizeof(T) == 8 ? 1e-30 : 1e-9; }
+constexpr double kZeroRel2Bf3 = jacobi_zero_rel2<float>();   // split-BF16x3 uses the same floor
 // Relative orthogonality the FP32-storage sweeps reach with an FP32-MFMA Gram.
 // In split-BF16x3 mode the sweeps with the BF16x3 Gram stop at the looser
 // tolerance its 16-bit products allow, and sweeps with the FP32-MFMA Gram then
