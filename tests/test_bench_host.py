@@ -1,0 +1,65 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU contract, the roofline
+bound chosen from a kernel's algorithmic intensity, and the HBM traffic that is
+reported only for the kernel source the counters were taken on."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode != 0
+    assert "one GPU" in (res.stdout + res.stderr)
+
+
+def _prof(**kernels):
+    return {"kernels": {k: {"ms": ms, "launches": 10, "flops": fl, "bytes": by}
+                        for k, (ms, fl, by) in kernels.items()}}
+
+
+def test_roofline_bound_follows_intensity():
+    # intensity 30 flop/B is above the FP32 ridge (157.3 TF / 8 TB/s = 19.7): MFMA
+    name, r = bench.roofline(_prof(jacobi_gram=(40.0, 30e9, 1e9), jacobi_update=(10.0, 1e9, 1e9)),
+                             "fp32")
+    assert name == "jacobi_gram" and r["bound"] == "mfma" and r["unit"] == "TFLOP/s"
+    assert r["achieved"] == pytest.approx(30e9 / 40e-3 / 1e12)
+    assert r["frac"] == pytest.approx(30e9 / 40e-3 / 157.3e12)
+    # 16 flop/B is below the FP32 ridge: HBM, achieved in GB/s
+    name, r = bench.roofline(_prof(jacobi_update=(40.0, 16e9, 1e9)), "fp32")
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert r["achieved"] == pytest.approx(1e9 / 40e-3 / 1e9)
+    assert r["frac"] == pytest.approx(1e9 / 40e-3 / 8e12)
+    # the same 16 flop/B is above the FP64 ridge (9.8): MFMA against the FP64 peak
+    _, r = bench.roofline(_prof(jacobi_update=(40.0, 16e9, 1e9)), "fp64")
+    assert r["bound"] == "mfma" and r["peak"] == pytest.approx(78.6)
+    # the pair eigen-solver is FP64 vector work in every mode
+    _, r = bench.roofline(_prof(jacobi_eig64=(40.0, 1e9, 1e6)), "fp32")
+    assert r["bound"] == "alu" and r["peak"] == pytest.approx(78.6)
+
+
+def test_traffic_only_for_the_measured_source(tmp_path, monkeypatch):
+    # a copy of the tree's layout: the kernel source and the counter record
+    src = tmp_path / "paper_2003_13163_amd" / "csrc"
+    src.mkdir(parents=True)
+    (tmp_path / "profiles").mkdir()
+    (src / "jacobi.hip").write_text("kernel source A\n")
+    import hashlib
+    sha = hashlib.sha256(b"kernel source A\n").hexdigest()
+    rec = {"source_sha256": {"paper_2003_13163_amd/csrc/jacobi.hip": sha}, "precision": "fp32",
+           "kernels": {"jacobi_gram": {"bytes_per_launch": 1.25e8}}}
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("jacobi_gram", "fp32") == pytest.approx(1.25e8)
+    assert bench.measured_traffic("jacobi_gram", "fp64") is None       # other precision
+    assert bench.measured_traffic("jacobi_update", "fp32") is None     # kernel not measured
+    (src / "jacobi.hip").write_text("kernel source B\n")                # source changed
+    assert bench.measured_traffic("jacobi_gram", "fp32") is None
