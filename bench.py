@@ -211,6 +211,29 @@ def cpu_baseline(snap_bytes, pm, site, sup, chi):
     return dt, info, cores
 
 
+def host_description():
+    """CPU model, logical CPUs and BLAS library of the host the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        libs = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if libs:
+            blas = f"{libs[0].get('internal_api')} {libs[0].get('version')}"
+    except Exception:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "blas": blas,
+            "numpy": np.__version__}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,7 +342,7 @@ def main():
         log("cpu baseline: oracle on the first bulk gate of the snapshot")
         dt, info, cores = cpu_baseline(snap, pm, sites[0], sups[0], chi)
         out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "updates/s", "cores": cores,
-                               "kind": "oracle",
+                               "kind": "oracle", "host": host_description(),
                                "sample": f"1 bulk gate (site {sites[0]}, chi={chi}) of the same "
                                          f"snapshot, numpy complex128 gesdd, {dt:.1f} s"}
         err = out.setdefault("entropy_error", {})
