@@ -115,6 +115,39 @@ def roofline(prof, prec):
                   "measured_in": "second pass over the same gates with per-launch HIP events"}
 
 
+def nominal_gate_work(chi, prec):
+    """Nominal real flops of one bulk gate at bond dimension chi (N = 4 chi, k = chi
+    kept), split by the unit that bounds each phase, and the roofline time:
+      theta 128 chi^3 + channel 2048 chi^2 + Gram 4 N^3 (Hermitian half)
+      + right factor 8 k N^2 + centre move (QR + R A) 91 chi^3   -> contractions
+      + eigen core (16/3) N^3 + 8 N^2 k (tridiagonalisation + back-transform) -> FP64
+    Contractions run at the mode's MFMA peak (BF16x3: three BF16 products), the
+    eigen core at the FP64 peak in every mode.  The fused lower bound on bytes
+    reads and writes the two site tensors once: 16 chi^2 complex values."""
+    N, k = 4 * chi, chi
+    contr = 128.0 * chi ** 3 + 2048.0 * chi ** 2 + 4.0 * N ** 3 + 8.0 * k * N ** 2 + 91.0 * chi ** 3
+    eig = (16.0 / 3.0) * N ** 3 + 8.0 * N ** 2 * k
+    cpeak = {"fp64": PEAK["fp64"], "fp32": PEAK["fp32"], "bf16x3": PEAK["bf16x3"] / 3.0}[prec]
+    csz = 16 if prec == "fp64" else 8
+    t_roof = contr / cpeak + eig / PEAK["fp64"]
+    return {"nominal_flops": contr + eig, "contraction_flops": contr, "eigen_core_flops": eig,
+            "t_roof_ms": 1e3 * t_roof, "fused_min_bytes": 16.0 * chi * chi * csz}
+
+
+def per_gate_roofline(prof, prec, chi, ms_per_gate, gates):
+    """Whole-gate roofline: nominal work / measured time, plus the algorithmic bytes
+    the kernels of one gate actually move (all launches) against the fused bound."""
+    w = nominal_gate_work(chi, prec)
+    ks = prof["kernels"]
+    alg_bytes = sum(v["bytes"] for v in ks.values()) / max(1, gates)
+    alg_flops = sum(v["flops"] for v in ks.values()) / max(1, gates)
+    return {"t_roof_ms": w["t_roof_ms"], "ms_per_gate": ms_per_gate, "frac": w["t_roof_ms"] / ms_per_gate,
+            "nominal_flops_per_gate": w["nominal_flops"],
+            "counted_flops_per_gate": alg_flops, "flops_ratio_counted_to_nominal": alg_flops / w["nominal_flops"],
+            "algorithmic_bytes_per_gate": alg_bytes, "fused_min_bytes_per_gate": w["fused_min_bytes"],
+            "bytes_ratio_to_fused_min": alg_bytes / w["fused_min_bytes"]}
+
+
 def measured_traffic(kernel, prec):
     """HBM bytes per launch from the committed rocprofv3 counter runs, or None
     when the kernel source changed since they were taken."""
@@ -317,12 +350,17 @@ def main():
                    "chi": chi, "n": n, "p": p, "cutoff": 1e-12, "basis": "pauli",
                    "bond_dims": dims},
         "roofline": rl,
+        "roofline_per_gate": per_gate_roofline(res[head]["prof"], head, chi,
+                                               1e3 * res[head]["seconds"] / args.steps, args.steps),
     }
     for other, dt_name in (("fp64", "f64"), ("bf16x3", "f32 storage, split-bf16x3 products")):
         if other in res and other != head:
             out[other] = {"value": args.steps / res[other]["seconds"],
                           "ms_per_step": 1e3 * res[other]["seconds"] / args.steps, "dtype": dt_name,
-                          "roofline": roofline(res[other]["prof"], other)[1]}
+                          "roofline": roofline(res[other]["prof"], other)[1],
+                          "roofline_per_gate": per_gate_roofline(res[other]["prof"], other, chi,
+                                                                 1e3 * res[other]["seconds"] / args.steps,
+                                                                 args.steps)}
     if "fp64" in res:
         err = out.setdefault("entropy_error", {})
         for prec in res:

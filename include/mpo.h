@@ -114,9 +114,11 @@ mpo_status mpo_init_product(mpo_handle *h, const unsigned char *bits);
  * handle's basis) to sites (site, site+1): move the orthogonality centre to
  * `site` (exact), contract the two sites, apply the map, split by a truncated
  * SVD (App. A truncation; "Note added" local update).  Afterwards site is a
- * left isometry and site+1 the centre.  info != NULL synchronises the stream
- * and fills it; info == NULL leaves the call stream-ordered except for one
- * small device-to-host read of the kept count.                              */
+ * left isometry and site+1 the centre.  The host sequences the SVD: it reads
+ * the convergence measure of every Jacobi sweep and the kept count of every
+ * split back from the device, so the call synchronises the handle's stream a
+ * few times per split whether info is NULL or not (the call is not capturable
+ * in a HIP graph).  info != NULL receives the split's result.               */
 mpo_status mpo_apply_2q_channel(mpo_handle *h, int site, const double *superop,
                                 int chi_max, double cutoff, mpo_trunc_info *info);
 
@@ -129,8 +131,12 @@ mpo_status mpo_canonicalize(mpo_handle *h, int center);
  * all n-1 values (one canonical sweep).  Synchronises.                       */
 mpo_status mpo_bond_entropy(mpo_handle *h, int bond, double *S);
 
-/* Schmidt values at bond b, descending, at most cap of them; *count = number
- * available.  Synchronises.                                                  */
+/* Schmidt values lambda^[b+1] of the vectorised state at bond b (Sec. III.A:
+ * the MPO written in Vidal's form, lambda as Schmidt coefficients; the same
+ * values give S_b of Sec. III.C), descending, from a fresh exact re-gauge of
+ * the current state; at most cap of them are written, *count = number
+ * available.  Errors: MPO_ERR_ARG for a bond outside [0, n-2], a NULL count,
+ * or cap > 0 with lam NULL.  Synchronises.                                   */
 mpo_status mpo_singular_values(mpo_handle *h, int bond, double *lam, int cap, int *count);
 
 /* Tr[P rho] / Tr[rho] for a Pauli string (n codes 0=I 1=X 2=Y 3=Z) by
@@ -168,41 +174,36 @@ mpo_status mpo_probability(mpo_handle *h, const unsigned char *bits, double *re,
 mpo_status mpo_sample(mpo_handle *h, int n_samples, const double *uniforms, unsigned char *bits,
                       double *prob, int *clamped);
 
-/* Current bond dimensions (n-1 values) and orthogonality centre.            */
+/* Current bond dimensions chi_b (n-1 values; the range of the alpha_b index
+ * of Sec. III.A, dynamic here instead of a fixed padded chi) and the site of
+ * the orthogonality centre of the mixed canonical form ("Note added").  dims
+ * and center may be NULL.  Host bookkeeping only: no GPU work.              */
 mpo_status mpo_bond_dims(mpo_handle *h, int *dims, int *center);
 
+/* Order of the gates within a time step.  Gates of one step act on disjoint
+ * pairs, so without truncation every order gives the same state (Sec. II.A);
+ * under truncation the order is part of the algorithm.  ASCENDING applies them
+ * from the left (the reading of Sec. IV.A's sequential application).  SNAKE
+ * applies odd time steps ascending and even ones descending, splitting each
+ * descending gate with the centre left on its left site, so the centre never
+ * travels back across the chain between steps.                             */
+typedef enum { MPO_ORDER_ASCENDING = 0, MPO_ORDER_SNAKE = 1 } mpo_order;
+
 /* Brickwork evolution (Sec. II.A, Sec. IV.A): time step t = 1..depth puts a
- * gate on (0,1),(2,3),... for odd t and on (1,2),(3,4),... for even t, applied
- * in ascending site order.  superops: n_gates x 16 x 16 complex in schedule
- * order, n_gates = ceil(D/2) n/2 + floor(D/2) (n/2-1), else MPO_ERR_ARG.
+ * gate on (0,1),(2,3),... for odd t and on (1,2),(3,4),... for even t, in the
+ * given order.  superops: n_gates x 16 x 16 complex in schedule order (time
+ * step by time step; within a descending step from the rightmost gate to the
+ * leftmost), n_gates = ceil(D/2) n/2 + floor(D/2) (n/2-1), else MPO_ERR_ARG.
  * record_mask bit 0: after every time step write S_b for all n-1 bonds to
  * S_out[t*(n-1)+b], <Z_i> to Z_out[t*n+i] and Tr rho to trace_out[t];
  * bit 1: the same only after the last time step (index 0).  Outputs may be
  * NULL when not recorded.  discarded_out (n_gates values or NULL) receives
  * the discarded weight of every gate.  Evolution continues from the current
- * state.                                                                     */
+ * state.  An unknown order or record bit is MPO_ERR_ARG.  Synchronises.     */
 mpo_status run_brickwork(mpo_handle *h, int depth, const double *superops, int n_gates,
-                         int chi_max, double cutoff, int record_mask,
+                         int chi_max, double cutoff, mpo_order order, int record_mask,
                          double *S_out, double *Z_out, double *trace_out,
                          double *discarded_out);
-
-/* Order of the gates within a time step.  Gates of one step act on disjoint
- * pairs, so without truncation every order gives the same state (Sec. II.A);
- * under truncation the order is part of the algorithm.  ASCENDING applies them
- * from the left (the reading of Sec. IV.A's sequential application, and what
- * run_brickwork does).  SNAKE applies odd time steps ascending and even ones
- * descending, splitting each descending gate with the centre left on its left
- * site, so the centre never travels back across the chain between steps.   */
-typedef enum { MPO_ORDER_ASCENDING = 0, MPO_ORDER_SNAKE = 1 } mpo_order;
-
-/* run_brickwork with a chosen gate order.  superops follow the schedule order
- * of that choice: time step by time step, and within a descending step from
- * the rightmost gate to the leftmost.  Other arguments, outputs and errors as
- * run_brickwork; an unknown order is MPO_ERR_ARG.                            */
-mpo_status mpo_run_brickwork_order(mpo_handle *h, int depth, const double *superops, int n_gates,
-                                   int chi_max, double cutoff, mpo_order order, int record_mask,
-                                   double *S_out, double *Z_out, double *trace_out,
-                                   double *discarded_out);
 
 /* Host snapshot of the state.  Format: int64 header {magic, n, basis, center,
  * chi_0 .. chi_{n-2}} then per site the (chi_l, 4, chi_r) tensor, row-major,
@@ -271,9 +272,10 @@ mpo_status mpo_batch_run(const mpo_batch_desc *circuits, int count,
  *     mpo_adjoint_workspace_bytes(n, depth, chi_max, prec) bytes.
  * The handle ends in the forward's final state.  Synchronises.               */
 mpo_status mpo_adjoint_workspace_bytes(int n, int depth, int chi_max, mpo_precision prec,
-                                       size_t *bytes);
+                                       int checkpoint_every, size_t *bytes);
 mpo_status mpo_adjoint_brickwork(mpo_handle *h, int depth, const double *superops, int n_gates,
-                                 int chi_max, double cutoff, void *dev_work, size_t work_bytes,
+                                 int chi_max, double cutoff, int checkpoint_every,
+                                 void *dev_work, size_t work_bytes,
                                  double *O_out, double *dO_dsuperop, int *costate_max_bond);
 
 /* Instrumentation: per-kernel-class timing with HIP events recorded on the

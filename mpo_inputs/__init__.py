@@ -18,7 +18,7 @@ import dataclasses
 import numpy as np
 
 __all__ = ["brickwork_sites", "n_gates", "ginibre_draws", "CircuitSpec",
-           "batch_specs", "batch_circuit"]
+           "batch_specs", "batch_circuit", "sampling_uniforms", "gradient_directions"]
 
 
 def brickwork_sites(n: int, depth: int) -> list[list[int]]:
@@ -95,3 +95,12 @@ def batch_circuit(i: int, chi_choices=(64, 128, 256, 512)):
     chi = int(chi_choices[int(rng.integers(0, len(chi_choices)))])
     spec = CircuitSpec(seed=i, n=n, depth=depth, p=p, chi_max=chi)
     return spec, ginibre_draws(n, depth, rng=rng)
+
+
+def gradient_directions(n_gates: int, count: int, seed: int) -> np.ndarray:
+    """Random directions in superoperator space for directional finite
+    differences: array (count, n_gates, 16, 16) of i.i.d. N(0,1) float64, each
+    direction scaled to unit Frobenius norm over all gates, from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = rng.standard_normal((count, n_gates, 16, 16))
+    return d / np.sqrt(np.sum(d * d, axis=(1, 2, 3)))[:, None, None, None]

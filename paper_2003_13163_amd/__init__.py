@@ -91,15 +91,14 @@ def library() -> ctypes.CDLL:
         "mpo_trace": [P, pd, pd],
         "mpo_expect_z_all": [P, pd, pd],
         "mpo_bond_dims": [P, pi, pi],
-        "run_brickwork": [P, I, pd, I, I, D, I, pd, pd, pd, pd],
-        "mpo_run_brickwork_order": [P, I, pd, I, I, D, I, I, pd, pd, pd, pd],
+        "run_brickwork": [P, I, pd, I, I, D, I, I, pd, pd, pd, pd],
         "mpo_export": [P, P, S, ctypes.POINTER(S)],
         "mpo_import": [P, P, S],
         "mpo_build_superop": [pd, pd, D, I, pd, pd],
         "mpo_batch_workspace_bytes": [P, I, I, I, ctypes.POINTER(S)],
         "mpo_batch_run": [P, I, pd, S, I, I, P, S, P, I, pd],
-        "mpo_adjoint_workspace_bytes": [I, I, I, I, ctypes.POINTER(S)],
-        "mpo_adjoint_brickwork": [P, I, pd, I, I, D, P, S, pd, pd, pi],
+        "mpo_adjoint_workspace_bytes": [I, I, I, I, I, ctypes.POINTER(S)],
+        "mpo_adjoint_brickwork": [P, I, pd, I, I, D, I, P, S, pd, pd, pi],
         "mpo_profile_enable": [P, I],
         "mpo_profile_read": [P, ctypes.POINTER(_KernelStat), I, pi, ctypes.POINTER(ctypes.c_longlong)],
         "mpo_last_error": [],
@@ -271,21 +270,25 @@ class Mpo:
         buf = ctypes.create_string_buffer(data, len(data))
         _check(library().mpo_import(self._h, buf, len(data)))
 
-    def adjoint_brickwork(self, depth: int, superops, chi_max: int, cutoff: float = 1e-12):
+    def adjoint_brickwork(self, depth: int, superops, chi_max: int, cutoff: float = 1e-12,
+                          checkpoint_every: int = 0):
         """(O, dO/dM of every gate (G,16,16) complex, largest co-state bond) with the
-        truncation projectors frozen; the state advances to the final one."""
+        truncation projectors frozen; the state advances to the final one.
+        checkpoint_every = K > 0 keeps the state every K time steps and recomputes
+        one K-step segment at a time for the backward (0: the whole tape at once)."""
         import torch
         lib = library()
         sup = _as_complex_pairs(superops).reshape(-1)
         g = sup.size // 512
         nbytes = ctypes.c_size_t()
-        _check(lib.mpo_adjoint_workspace_bytes(self.n, depth, chi_max, self.precision, ctypes.byref(nbytes)))
+        _check(lib.mpo_adjoint_workspace_bytes(self.n, depth, chi_max, self.precision,
+                                               int(checkpoint_every), ctypes.byref(nbytes)))
         work = torch.empty(nbytes.value, dtype=torch.uint8, device=self.arena.device)
         O = ctypes.c_double()
         grads = np.zeros(g * 512)
         comax = ctypes.c_int()
         _check(lib.mpo_adjoint_brickwork(self._h, depth, _dptr(sup), g, chi_max, float(cutoff),
-                                         ctypes.c_void_p(work.data_ptr()), nbytes.value,
+                                         int(checkpoint_every), ctypes.c_void_p(work.data_ptr()), nbytes.value,
                                          ctypes.byref(O), _dptr(grads), ctypes.byref(comax)))
         del work
         return O.value, grads.view(np.complex128).reshape(g, 16, 16), comax.value
@@ -321,9 +324,8 @@ class Mpo:
         Z = np.zeros(max(rows, 1) * self.n)
         tr = np.zeros(max(rows, 1))
         disc = np.zeros(max(g, 1))
-        _check(library().mpo_run_brickwork_order(self._h, depth, _dptr(sup), g, chi_max, float(cutoff),
-                                                 _ORDER[order], mask, _dptr(S), _dptr(Z), _dptr(tr),
-                                                 _dptr(disc)))
+        _check(library().run_brickwork(self._h, depth, _dptr(sup), g, chi_max, float(cutoff),
+                                       _ORDER[order], mask, _dptr(S), _dptr(Z), _dptr(tr), _dptr(disc)))
         return {"S": S[: rows * (self.n - 1)].reshape(rows, self.n - 1),
                 "Z": Z[: rows * self.n].reshape(rows, self.n), "trace": tr[:rows],
                 "discarded": disc[:g]}

@@ -95,7 +95,7 @@ extern "C" mpo_status mpo_batch_run(const mpo_batch_desc* circuits, int count,
                 std::vector<double> disc((size_t)std::max(g, 1));
                 double* out = results + c.result_offset;
                 s = run_brickwork(h, c.depth, superops_concat + 512 * c.gate_offset, g, c.chi_max,
-                                  c.cutoff, 2, out, out + (c.n - 1), out + (2 * c.n - 1),
+                                  c.cutoff, MPO_ORDER_ASCENDING, 2, out, out + (c.n - 1), out + (2 * c.n - 1),
                                   disc.data());
                 if (s == MPO_OK) {
                     double tot = 0.0;

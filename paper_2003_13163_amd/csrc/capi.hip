@@ -185,6 +185,11 @@ void product_site(mpo_basis basis, int bit, double v[8]) {
     }
 }
 
+// Scratch of the transfer contraction (FP64 environments, vectors, dot results).
+struct ObsScratch {
+    double2 *envL, *envR, *tscr, *tmp, *vecs, *dots;
+};
+
 template <typename T>
 struct Engine {
     using C = C2<T>;
@@ -368,33 +373,41 @@ struct Engine {
 
     // Tr rho and all <Z_i> numerators by transfer contraction (Sec. III.D).
     static void observables(mpo_handle* h, double* z, double* trace_re, double* trace_im) {
+        observables_in(h, ObsScratch{h->envL, h->envR, h->tscr, h->tmp, h->vecs, h->dots}, z, trace_re,
+                       trace_im);
+    }
+    // The same contraction with its environments in the given scratch.
+    static void observables_in(mpo_handle* h, const ObsScratch& w, double* z, double* trace_re,
+                               double* trace_im) {
         const int n = h->n, cap = h->chi_cap;
+        double2 *const envL = w.envL, *const envR = w.envR, *const tscr = w.tscr, *const tmp = w.tmp,
+                       *const vecs = w.vecs, *const dots = w.dots;
         double2 hv[8];
         dual_vector(h->basis, 0, hv);
         dual_vector(h->basis, 3, hv + 4);
-        HIPCHK(hipMemcpyAsync(h->vecs, hv, sizeof(hv), hipMemcpyHostToDevice, h->st));
+        HIPCHK(hipMemcpyAsync(vecs, hv, sizeof(hv), hipMemcpyHostToDevice, h->st));
         const double2 one = make_double2(1.0, 0.0);
-        HIPCHK(hipMemcpyAsync(h->envL, &one, sizeof(one), hipMemcpyHostToDevice, h->st));
-        HIPCHK(hipMemcpyAsync(h->envR + (size_t)n * cap, &one, sizeof(one), hipMemcpyHostToDevice, h->st));
+        HIPCHK(hipMemcpyAsync(envL, &one, sizeof(one), hipMemcpyHostToDevice, h->st));
+        HIPCHK(hipMemcpyAsync(envR + (size_t)n * cap, &one, sizeof(one), hipMemcpyHostToDevice, h->st));
         for (int s = 0; s < n; ++s)
-            launch_transfer_left<T>(site(h, s), h->chiL(s), h->chiR(s), h->envL + (size_t)s * cap,
-                                    h->vecs, h->envL + (size_t)(s + 1) * cap, h->st);
+            launch_transfer_left<T>(site(h, s), h->chiL(s), h->chiR(s), envL + (size_t)s * cap,
+                                    vecs, envL + (size_t)(s + 1) * cap, h->st);
         if (z) {
             for (int s = n - 1; s >= 0; --s)
                 launch_transfer_right<T>(site(h, s), h->chiL(s), h->chiR(s),
-                                         h->envR + (size_t)(s + 1) * cap, h->vecs,
-                                         h->envR + (size_t)s * cap, h->tscr, h->st);
+                                         envR + (size_t)(s + 1) * cap, vecs,
+                                         envR + (size_t)s * cap, tscr, h->st);
             for (int i = 0; i < n; ++i) {
-                launch_transfer_left<T>(site(h, i), h->chiL(i), h->chiR(i), h->envL + (size_t)i * cap,
-                                        h->vecs + 4, h->tmp, h->st);
-                launch_dot(h->tmp, h->envR + (size_t)(i + 1) * cap, h->chiR(i), h->dots + i, h->st);
+                launch_transfer_left<T>(site(h, i), h->chiL(i), h->chiR(i), envL + (size_t)i * cap,
+                                        vecs + 4, tmp, h->st);
+                launch_dot(tmp, envR + (size_t)(i + 1) * cap, h->chiR(i), dots + i, h->st);
             }
         }
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(h->small_host, h->envL + (size_t)n * cap, sizeof(double2),
+        HIPCHK(hipMemcpyAsync(h->small_host, envL + (size_t)n * cap, sizeof(double2),
                               hipMemcpyDeviceToHost, h->st));
         if (z)
-            HIPCHK(hipMemcpyAsync(h->small_host + 1, h->dots, sizeof(double2) * n,
+            HIPCHK(hipMemcpyAsync(h->small_host + 1, dots, sizeof(double2) * n,
                                   hipMemcpyDeviceToHost, h->st));
         HIPCHK(hipStreamSynchronize(h->st));
         const double2 tr = h->small_host[0];
@@ -618,18 +631,26 @@ struct Engine {
 // isometries, so only one projection (an environment sweep) per layer is
 // needed, and the left overlap of lambda_g with rho_{g-1} is the identity.
 struct AdjLayout {
-    size_t slot_bytes, tape_slots, mu_bytes, env_bytes, y_bytes, t1_bytes, th_bytes, mh_bytes, total;
-    int chi_mu;
+    size_t slot_bytes, tape_slots, ckpt_slots, mu_bytes, env_bytes, y_bytes, t1_bytes, th_bytes, mh_bytes,
+        total;
+    int chi_mu, seg;           // co-state bond cap; time steps per recomputed segment
 };
 
-AdjLayout adj_layout(int n, int depth, int chi_max, mpo_precision prec, int n_gates) {
+// Slots per recorded time step: the n sites at its start, every pre-gate centre
+// (at most n/2) and the sites 0..last after its last gate (at most n), plus one.
+size_t adj_tape_slots_per_step(int n) { return 2 * (size_t)n + (size_t)n / 2 + 1; }
+
+AdjLayout adj_layout(int n, int depth, int chi_max, mpo_precision prec, int n_gates, int checkpoint_every) {
     AdjLayout L{};
     const size_t csz = prec == MPO_FP64 ? 16 : 8;
     const size_t cm = (size_t)chi_max;
     L.chi_mu = std::min(1024, 4 * chi_max);
+    L.seg = (checkpoint_every <= 0 || checkpoint_every > depth) ? depth : checkpoint_every;
     const size_t cu = (size_t)L.chi_mu;
     L.slot_bytes = align256(4 * cm * cm * csz);
-    L.tape_slots = (size_t)depth * (2 * (size_t)n + (size_t)n / 2 + 1);
+    L.tape_slots = (size_t)L.seg * adj_tape_slots_per_step(n);
+    // one state of n sites at the start of every segment, plus the final state
+    L.ckpt_slots = ((size_t)(depth + L.seg - 1) / L.seg + 1) * (size_t)n;
     size_t mu = 0;
     mpo_workspace_bytes(n, L.chi_mu, prec, &mu);
     L.mu_bytes = align256(mu);
@@ -638,8 +659,8 @@ AdjLayout adj_layout(int n, int depth, int chi_max, mpo_precision prec, int n_ga
     L.t1_bytes = align256(4 * cm * cu * csz);
     L.th_bytes = align256(16 * cm * cu * csz);
     L.mh_bytes = align256(((size_t)n_gates + 1) * 256 * csz);
-    L.total = L.slot_bytes * L.tape_slots + L.mu_bytes + 4 * L.env_bytes + L.y_bytes + L.t1_bytes +
-              2 * L.th_bytes + L.mh_bytes + align256(256 * sizeof(double2));
+    L.total = L.slot_bytes * (L.tape_slots + L.ckpt_slots) + L.mu_bytes + 4 * L.env_bytes + L.y_bytes +
+              L.t1_bytes + 2 * L.th_bytes + L.mh_bytes + align256(256 * sizeof(double2));
     return L;
 }
 
@@ -717,6 +738,8 @@ struct Adjoint {
         char* p = work;
         char* tape_base = p;
         p += L.slot_bytes * L.tape_slots;
+        char* ckpt_base = p;
+        p += L.slot_bytes * L.ckpt_slots;
         char* mu_arena = p; p += L.mu_bytes;
         C* env[4];
         for (int k = 0; k < 4; ++k) { env[k] = (C*)p; p += L.env_bytes; }
@@ -726,45 +749,87 @@ struct Adjoint {
         C* TH = (C*)p; p += L.th_bytes;
         C* MH = (C*)p; p += L.mh_bytes;
         double2* gdev = (double2*)p;
+        // first gate of every time step
+        std::vector<int> g_first(depth + 1, 0);
+        for (int t = 0; t < depth; ++t) g_first[t + 1] = g_first[t] + ((t % 2 == 0) ? n / 2 : n / 2 - 1);
+        // superoperators resident on the device, uploaded in windows of kMaxSuper gates
+        int resident0 = 0, resident = 0;
+        auto gate_ptr = [&](int g) -> const C* {
+            if (g < resident0 || g >= resident0 + resident) {
+                resident0 = g;
+                resident = std::min(kMaxSuper, n_gates - g);
+                HIPCHK(hipStreamSynchronize(h->st));   // the pinned staging buffer is reused
+                E::upload_super(h, superops + (size_t)g * 512, resident);
+            }
+            return (const C*)h->Mdev + (size_t)(g - resident0) * 256;
+        };
+        // Checkpoint c holds the state at the start of time step c * seg, the last
+        // one the final state.  The backward recomputes one segment of seg time
+        // steps at a time from its checkpoint, recording the tape of that segment
+        // only; the kernels are deterministic, so the recomputed steps repeat the
+        // first forward bit for bit and the frozen projectors are the forward's.
+        const int n_seg = (depth + L.seg - 1) / L.seg;
+        std::vector<std::vector<int>> ck_dims(n_seg + 1);
+        std::vector<int> ck_centre(n_seg + 1, 0);
+        auto ck_site = [&](int c, int s) { return (C*)(ckpt_base + L.slot_bytes * ((size_t)c * n + s)); };
+        auto save = [&](int c) {
+            ck_dims[c] = h->dims;
+            ck_centre[c] = h->centre;
+            for (int s = 0; s < n; ++s) copy_site(h, s, ck_site(c, s), h->chiL(s), h->chiR(s));
+        };
+        auto restore = [&](int c) {
+            h->dims = ck_dims[c];
+            h->centre = ck_centre[c];
+            for (int s = 0; s < n; ++s)
+                launch_copy<T>(ck_site(c, s), E::site(h, s), (size_t)h->chiL(s) * 4 * h->chiR(s), h->st);
+            HIPCHK(hipGetLastError());
+        };
         size_t next_slot = 0;
         auto take = [&]() -> C* {
             if (next_slot >= L.tape_slots) throw HipError{hipErrorOutOfMemory, "adjoint tape"};
             return (C*)(tape_base + L.slot_bytes * next_slot++);
         };
-        // ---- forward with tape
-        std::vector<Tape> tape(depth);
-        int g = 0, resident0 = 0, resident = 0;
-        for (int t = 0; t < depth; ++t) {
-            Tape& tp = tape[t];
-            tp.first = (t % 2 == 0) ? 0 : 1;
-            E::move_centre(h, tp.first);
-            tp.pre_dims = h->dims;
-            for (int s = 0; s < n; ++s) {
-                tp.pre.push_back(take());
-                copy_site(h, s, tp.pre.back(), h->chiL(s), h->chiR(s));
-            }
-            for (int s = tp.first; s + 1 < n; s += 2) {
-                if (g >= resident0 + resident) {
-                    resident0 = g;
-                    resident = std::min(kMaxSuper, n_gates - g);
-                    HIPCHK(hipStreamSynchronize(h->st));
-                    E::upload_super(h, superops + (size_t)g * 512, resident);
+        // One forward time step; with a tape, the state at its start, every
+        // pre-gate centre and the left isometries after its last gate.  Both
+        // forms make the same moves and launches in the same order.
+        auto step = [&](int t, Tape* tp) {
+            const int first = (t % 2 == 0) ? 0 : 1;
+            int g = g_first[t];
+            if (tp) {
+                tp->first = first;
+                E::move_centre(h, first);
+                tp->pre_dims = h->dims;
+                for (int s = 0; s < n; ++s) {
+                    tp->pre.push_back(take());
+                    copy_site(h, s, tp->pre.back(), h->chiL(s), h->chiR(s));
                 }
+            }
+            for (int s = first; s + 1 < n; s += 2, ++g) {
+                const C* Mg = gate_ptr(g);
                 E::move_centre(h, s);
-                tp.cen.push_back(take());
-                tp.cen_l.push_back(h->chiL(s));
-                tp.cen_r.push_back(h->dims[s]);
-                copy_site(h, s, tp.cen.back(), h->chiL(s), h->dims[s]);
-                E::apply(h, s, (const C*)h->Mdev + (size_t)(g - resident0) * 256, chi_max, cutoff);
-                tp.last = s;
-                ++g;
+                if (tp) {
+                    tp->cen.push_back(take());
+                    tp->cen_l.push_back(h->chiL(s));
+                    tp->cen_r.push_back(h->dims[s]);
+                    copy_site(h, s, tp->cen.back(), h->chiL(s), h->dims[s]);
+                }
+                E::apply(h, s, Mg, chi_max, cutoff);
+                if (tp) tp->last = s;
             }
-            for (int s = 0; s <= tp.last; ++s) {
-                tp.post.push_back(take());
-                copy_site(h, s, tp.post.back(), h->chiL(s), h->chiR(s));
+            if (tp) {
+                for (int s = 0; s <= tp->last; ++s) {
+                    tp->post.push_back(take());
+                    copy_site(h, s, tp->post.back(), h->chiL(s), h->chiR(s));
+                }
+                tp->post_dims.assign(h->dims.begin(), h->dims.begin() + tp->last + 1);
             }
-            tp.post_dims.assign(h->dims.begin(), h->dims.begin() + tp.last + 1);
+        };
+        // ---- forward, keeping only the checkpoints
+        for (int t = 0; t < depth; ++t) {
+            if (t % L.seg == 0) save(t / L.seg);
+            step(t, nullptr);
         }
+        save(n_seg);
         HIPCHK(hipGetLastError());
         {
             std::vector<double> z(n);
@@ -794,10 +859,19 @@ struct Adjoint {
         }
         const C* Id = MH + (size_t)n_gates * 256;
         int co_max = 2;
-        // ---- backward
-        g = n_gates;
+        // ---- backward, one recomputed segment at a time
+        std::vector<Tape> tape;
+        int g = n_gates;
         for (int t = depth - 1; t >= 0; --t) {
-            Tape& tp = tape[t];
+            if (t == depth - 1 || (t + 1) % L.seg == 0) {
+                const int c = t / L.seg, t0 = c * L.seg;
+                restore(c);
+                tape.assign(t - t0 + 1, Tape());
+                next_slot = 0;
+                for (int u = t0; u <= t; ++u) step(u, &tape[u - t0]);
+                HIPCHK(hipGetLastError());
+            }
+            Tape& tp = tape[t % L.seg];
             const int m_gates = (int)tp.cen.size();
             const int sm = tp.last;
             auto pre_l = [&](int s) { return s == 0 ? 1 : tp.pre_dims[s - 1]; };
@@ -878,6 +952,7 @@ struct Adjoint {
                 HIPCHK(hipGetLastError());
             }
         }
+        restore(n_seg);
         HIPCHK(hipStreamSynchronize(h->st));
         if (costate_max_bond) *costate_max_bond = co_max;
     }
@@ -1148,16 +1223,8 @@ mpo_status mpo_bond_dims(mpo_handle* h, int* dims, int* center) {
 }
 
 mpo_status run_brickwork(mpo_handle* h, int depth, const double* superops, int n_gates, int chi_max,
-                         double cutoff, int record_mask, double* S_out, double* Z_out,
+                         double cutoff, mpo_order order, int record_mask, double* S_out, double* Z_out,
                          double* trace_out, double* discarded_out) {
-    return mpo_run_brickwork_order(h, depth, superops, n_gates, chi_max, cutoff, MPO_ORDER_ASCENDING,
-                                   record_mask, S_out, Z_out, trace_out, discarded_out);
-}
-
-mpo_status mpo_run_brickwork_order(mpo_handle* h, int depth, const double* superops, int n_gates,
-                                   int chi_max, double cutoff, mpo_order order, int record_mask,
-                                   double* S_out, double* Z_out, double* trace_out,
-                                   double* discarded_out) {
     mpo_status st = check_live(h);
     if (st != MPO_OK) return st;
     const int n = h->n;
@@ -1243,20 +1310,23 @@ mpo_status mpo_profile_read(mpo_handle* h, mpo_kernel_stat* out, int cap, int* c
     return MPO_OK;
 }
 
-mpo_status mpo_adjoint_workspace_bytes(int n, int depth, int chi_max, mpo_precision prec, size_t* bytes) {
+mpo_status mpo_adjoint_workspace_bytes(int n, int depth, int chi_max, mpo_precision prec,
+                                       int checkpoint_every, size_t* bytes) {
     if (!bytes) return fail(MPO_ERR_ARG, "bytes is NULL");
     size_t dummy = 0;
     mpo_status st = mpo_workspace_bytes(n, std::max(1, std::min(1024, 4 * chi_max)), prec, &dummy);
     if (st != MPO_OK) return st;
     if (depth < 1 || chi_max < 1 || chi_max > 1024) return fail(MPO_ERR_ARG, "depth >= 1 and 1 <= chi_max <= 1024 required");
+    if (checkpoint_every < 0) return fail(MPO_ERR_ARG, "checkpoint_every must be >= 0 (0 = no recompute)");
     const int g = ((depth + 1) / 2) * (n / 2) + (depth / 2) * (n / 2 - 1);
-    *bytes = adj_layout(n, depth, chi_max, prec, g).total;
+    *bytes = adj_layout(n, depth, chi_max, prec, g, checkpoint_every).total;
     return MPO_OK;
 }
 
 mpo_status mpo_adjoint_brickwork(mpo_handle* h, int depth, const double* superops, int n_gates,
-                                 int chi_max, double cutoff, void* dev_work, size_t work_bytes,
-                                 double* O_out, double* dO_dsuperop, int* costate_max_bond) {
+                                 int chi_max, double cutoff, int checkpoint_every, void* dev_work,
+                                 size_t work_bytes, double* O_out, double* dO_dsuperop,
+                                 int* costate_max_bond) {
     mpo_status st = check_live(h);
     if (st != MPO_OK) return st;
     const int n = h->n;
@@ -1267,9 +1337,14 @@ mpo_status mpo_adjoint_brickwork(mpo_handle* h, int depth, const double* superop
     if (!superops || !O_out || !dO_dsuperop || !dev_work) return fail(MPO_ERR_ARG, "null argument");
     if (((uintptr_t)dev_work) & 255) return fail(MPO_ERR_ARG, "dev_work must be 256-byte aligned");
     if (chi_max < 1 || chi_max > h->chi_cap) return fail(MPO_ERR_ARG, "chi_max %d out of [1, %d]", chi_max, h->chi_cap);
+    if (checkpoint_every < 0) return fail(MPO_ERR_ARG, "checkpoint_every must be >= 0 (0 = no recompute)");
+    // tape slots, checkpoints and environments are sized by chi_max
+    for (int b = 0; b < n - 1; ++b)
+        if (h->dims[b] > chi_max)
+            return fail(MPO_ERR_ARG, "bond %d of the current state has dimension %d > chi_max %d", b, h->dims[b], chi_max);
     if (!(cutoff >= 0.0) || !std::isfinite(cutoff)) return fail(MPO_ERR_ARG, "cutoff must be finite and >= 0");
     if (!finite_all(superops, (size_t)n_gates * 512)) return fail(MPO_ERR_ARG, "non-finite superoperator entry");
-    const AdjLayout L = adj_layout(n, depth, chi_max, h->prec, n_gates);
+    const AdjLayout L = adj_layout(n, depth, chi_max, h->prec, n_gates, checkpoint_every);
     if (work_bytes < L.total) return fail(MPO_ERR_ARENA, "adjoint workspace has %zu bytes, %zu needed", work_bytes, L.total);
     return guarded(h, [&] {
         DISPATCH(h, Adjoint<typename E::C::value_type>::run(h, depth, superops, n_gates, chi_max, cutoff,

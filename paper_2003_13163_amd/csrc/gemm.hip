@@ -71,6 +71,39 @@ __device__ __forceinline__ void mma_step(const C2<T> (*As)[BM + 1], const C2<T> 
     else mma_tile<T>(As, Bs, lane, wm, wn, accR, accI);
 }
 
+// FP32 storage: the MFMA accumulators hold partial sums over at most kChunkK
+// terms of K and are then added into FP64 sums.  One FP32 accumulator chain
+// over the whole K (up to 4096 here) rounds once per 4 terms into a growing
+// partial sum; for the cancelling sums of a re-gauge (rows of U^H A scale with
+// the singular values) that rounding, relative to the result, grows with
+// sigma_1 / sigma_k and was measured to dominate the FP32 mode's entropy error.
+constexpr int kChunkK = 32;
+
+__device__ __forceinline__ void flush_acc(f4 (&accR)[2][2], f4 (&accI)[2][2], d4 (&sumR)[2][2],
+                                          d4 (&sumI)[2][2]) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                sumR[bi][bj][r] += (double)accR[bi][bj][r];
+                sumI[bi][bj][r] += (double)accI[bi][bj][r];
+                accR[bi][bj][r] = 0.f;
+                accI[bi][bj][r] = 0.f;
+            }
+}
+
+// Sum-side accumulator: FP64 for FP32 storage with FP32-MFMA products, none otherwise.
+template <typename T, bool BF> struct SumAcc {
+    static constexpr bool on = false;
+    d4 R[1][1], I[1][1];
+};
+template <> struct SumAcc<float, false> {
+    static constexpr bool on = true;
+    d4 R[2][2], I[2][2];
+};
+
 template <typename T>
 __device__ __forceinline__ void zero_acc(A4<T> (&accR)[2][2], A4<T> (&accI)[2][2]) {
 #pragma unroll
@@ -79,6 +112,15 @@ __device__ __forceinline__ void zero_acc(A4<T> (&accR)[2][2], A4<T> (&accI)[2][2
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = T(0); accI[bi][bj][r] = T(0); }
+}
+
+__device__ __forceinline__ void zero_sum(d4 (&sR)[2][2], d4 (&sI)[2][2]) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { sR[bi][bj][r] = 0.0; sI[bi][bj][r] = 0.0; }
 }
 
 // C (M x N) = op(A) (M x K) * op(B) (K x N); op 0 = as stored, 1 = conj-transpose.
@@ -93,6 +135,8 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, const C2<T>*
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
     A4<T> accR[2][2], accI[2][2];
     zero_acc<T>(accR, accI);
+    SumAcc<T, BF> sum;
+    if constexpr (SumAcc<T, BF>::on) zero_sum(sum.R, sum.I);
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -119,6 +163,8 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, const C2<T>*
         __syncthreads();
         mma_step<T, BF>(As, Bs, lane, wm, wn, accR, accI);
         __syncthreads();
+        if constexpr (SumAcc<T, BF>::on)
+            if ((k0 + BK) % kChunkK == 0 || k0 + BK >= K) flush_acc(accR, accI, sum.R, sum.I);
     }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -128,8 +174,12 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, const C2<T>*
             for (int r = 0; r < 4; ++r) {
                 const int i = m0 + wm * 32 + bi * 16 + acc_row<T>(lane, r);
                 const int j = n0 + wn * 32 + bj * 16 + (lane & 15);
-                if (i < M && j < N)
-                    Cm[i + (size_t)j * ldc] = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
+                if (i < M && j < N) {
+                    if constexpr (SumAcc<T, BF>::on)
+                        Cm[i + (size_t)j * ldc] = cmake<T>((T)sum.R[bi][bj][r], (T)sum.I[bi][bj][r]);
+                    else
+                        Cm[i + (size_t)j * ldc] = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
+                }
             }
 }
 
@@ -176,6 +226,8 @@ __global__ __launch_bounds__(256) void k_theta_channel(int chiL, int chiM, int c
     Ms[t >> 4][t & 15] = Mdev[t];
     A4<T> accR[2][2], accI[2][2];
     zero_acc<T>(accR, accI);
+    SumAcc<T, BF> sum;
+    if constexpr (SumAcc<T, BF>::on) zero_sum(sum.R, sum.I);
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -198,15 +250,20 @@ __global__ __launch_bounds__(256) void k_theta_channel(int chiL, int chiM, int c
         __syncthreads();
         mma_step<T, BF>(As, Bs, lane, wm, wn, accR, accI);
         __syncthreads();
+        if constexpr (SumAcc<T, BF>::on)
+            if ((k0 + BK) % kChunkK == 0 || k0 + BK >= K) flush_acc(accR, accI, sum.R, sum.I);
     }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                Cs[wm * 32 + bi * 16 + acc_row<T>(lane, r)][wn * 32 + bj * 16 + (lane & 15)] =
-                    cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
+            for (int r = 0; r < 4; ++r) {
+                C2<T> v;
+                if constexpr (SumAcc<T, BF>::on) v = cmake<T>((T)sum.R[bi][bj][r], (T)sum.I[bi][bj][r]);
+                else v = cmake<T>(accR[bi][bj][r], accI[bi][bj][r]);
+                Cs[wm * 32 + bi * 16 + acc_row<T>(lane, r)][wn * 32 + bj * 16 + (lane & 15)] = v;
+            }
     __syncthreads();
     const int al = t & 15, cl = t >> 4;
     const int a = a0 + al, c = c0 + cl;

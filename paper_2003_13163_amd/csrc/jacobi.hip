@@ -1135,6 +1135,10 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, double stop_off, doubl
     Profiler& pf = *w.prof;
     const double csz = 2.0 * sizeof(T);
     const double pair_flops = 8.0 * m * NB * NB;      // one NB x NB complex product over m rows
+    // the Gram kernels form only the TB(TB+1)/2 upper 16x16 tiles of the Hermitian
+    // NB x NB product (TB = NB/16): credit those tiles, not the full product
+    constexpr int kTB = NB / 16, kNU = kTB * (kTB + 1) / 2;
+    const double gram_flops = 8.0 * m * 256.0 * kNU;
     const double pair_bytes = (double)m * NB * csz;
     // FP32 storage: X is held scaled by a power of two during the sweeps
     constexpr bool scaled = sizeof(T) == 4;
@@ -1171,7 +1175,7 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, double stop_off, doubl
                 hipExtLaunchKernelGGL((k_pair_gram_lds<T, JB>), dim3(P, splits), dim3(256), 0, st, a,
                                       b, 0, X, m, N, (const int*)w.colmap, nb, r, splits, chunk,
                                       (double2*)w.gram_partials);
-            pf.record(K_GRAM, a, b, P * pair_flops, P * pair_bytes + (double)P * splits * NB * NB * 16.0);
+            pf.record(K_GRAM, a, b, P * gram_flops, P * pair_bytes + (double)P * splits * NB * NB * 16.0);
             pf.stamps(a, b);
             hipExtLaunchKernelGGL((k_pair_eig<T, JB>), dim3(P), dim3(kEigThreads), 0, st, a, b, 0,
                                   (const double2*)w.gram_partials, splits, tol, zrel2,

@@ -63,3 +63,22 @@ def test_traffic_only_for_the_measured_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("jacobi_update", "fp32") is None     # kernel not measured
     (src / "jacobi.hip").write_text("kernel source B\n")                # source changed
     assert bench.measured_traffic("jacobi_gram", "fp32") is None
+
+
+def test_nominal_gate_work_and_per_gate_fraction():
+    """Nominal work of a bulk gate at chi = 1024: about 1.15e12 real flops
+    (about 1074 chi^3), FP64 roofline time about 14.6 ms, FP32 (contractions on
+    FP32 MFMA, eigen core on FP64) about 10.5 ms; fused bytes 16 chi^2 values."""
+    w64 = bench.nominal_gate_work(1024, "fp64")
+    w32 = bench.nominal_gate_work(1024, "fp32")
+    assert w64["nominal_flops"] == pytest.approx(1.154e12, rel=2e-3)
+    assert w64["nominal_flops"] / 1024 ** 3 == pytest.approx(1074.7, rel=1e-3)
+    assert w64["t_roof_ms"] == pytest.approx(14.68, rel=2e-3)
+    assert w32["t_roof_ms"] == pytest.approx(10.54, rel=2e-3)
+    assert w64["fused_min_bytes"] == 16 * 1024 ** 2 * 16
+    assert w32["fused_min_bytes"] == 16 * 1024 ** 2 * 8
+    prof = _prof(jacobi_gram=(40.0, 3e12, 1e11), gemm=(10.0, 1e11, 1e10))
+    r = bench.per_gate_roofline(prof, "fp32", 1024, 500.0, 10)
+    assert r["frac"] == pytest.approx(w32["t_roof_ms"] / 500.0)
+    assert r["counted_flops_per_gate"] == pytest.approx(3.1e11)
+    assert r["algorithmic_bytes_per_gate"] == pytest.approx(1.1e10)

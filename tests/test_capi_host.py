@@ -84,3 +84,29 @@ def test_superop_builder_rejects_bad_p(pm):
     optr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     assert lib.mpo_build_superop(ptr, ptr, -0.1, 0, optr, None) == 1
     assert lib.mpo_build_superop(ptr, ptr, float("nan"), 0, optr, None) == 1
+
+
+def test_adjoint_workspace_shrinks_with_checkpointing(pm):
+    """Segment recompute (checkpoint_every = K) keeps a K-step tape plus one
+    state per segment instead of the whole depth's tape."""
+    lib = pm.library()
+    full, ck4, ck1 = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.mpo_adjoint_workspace_bytes(32, 24, 256, 0, 0, ctypes.byref(full)) == 0
+    assert lib.mpo_adjoint_workspace_bytes(32, 24, 256, 0, 4, ctypes.byref(ck4)) == 0
+    assert lib.mpo_adjoint_workspace_bytes(32, 24, 256, 0, 1, ctypes.byref(ck1)) == 0
+    # tape + checkpoint slots of 4 chi^2 complex128 values (4 MiB): 24 x 81 + 2 x 32
+    # = 2008 against 4 x 81 + 7 x 32 = 548 (K = 1: 81 + 25 x 32 = 881); the
+    # co-state handle and the contraction buffers are the same in all three
+    slot = 4 * 256 * 256 * 16
+    assert full.value - ck4.value == (2008 - 548) * slot
+    assert ck1.value - ck4.value == (881 - 548) * slot
+    assert lib.mpo_adjoint_workspace_bytes(32, 24, 256, 0, -1, ctypes.byref(full)) == 1
+    assert b"checkpoint_every" in lib.mpo_last_error()
+
+
+def test_run_brickwork_signature_has_order():
+    """run_brickwork takes the gate order as its seventh argument (after the cutoff)."""
+    text = open(os.path.join(ROOT, "include", "mpo.h")).read()
+    decl = re.search(r"mpo_status run_brickwork\((.*?)\);", text, flags=re.S).group(1)
+    args = [a.strip() for a in decl.split(",")]
+    assert args[6].startswith("mpo_order"), args

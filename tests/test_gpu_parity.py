@@ -439,6 +439,41 @@ def test_adjoint_reduced_precision(pm, prec, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("every", [1, 2, 3])
+def test_adjoint_checkpointed_equals_full_tape(pm, every):
+    """Segment recompute from checkpoints repeats the forward bit for bit, so
+    the gradient equals the one from the whole tape exactly."""
+    n, depth, p, chi = 8, 5, 0.02, 12
+    say(f"case adjoint checkpoint_every={every} n={n} depth={depth} chi={chi}")
+    draws = mi.ginibre_draws(n, depth, seed=33)
+    sup = pm.build_superops(draws, p, "pauli")
+    outs = []
+    for k in (0, every):
+        st = pm.Mpo(n, chi, "fp64", "pauli")
+        O, grads, comax = st.adjoint_brickwork(depth, sup, chi, 1e-12, checkpoint_every=k)
+        S_end = st.entropy(-1)
+        st.close()
+        outs.append((O, grads, comax, S_end))
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+    assert np.array_equal(outs[0][3], outs[1][3])     # the handle ends in the final state
+
+
+def test_adjoint_rejects_bonds_above_chi_max(pm):
+    """The tape and environments are sized by chi_max: a current state with a
+    larger bond is an argument error, found before any launch."""
+    n, depth = 6, 3
+    say("case adjoint bond check")
+    st = pm.Mpo(n, 64, "fp64", "pauli")
+    sup = pm.build_superops(mi.ginibre_draws(n, depth, seed=2), 0.01, "pauli")
+    st.run_brickwork(depth, sup, 64, 1e-12, record=None)
+    assert max(st.bond_dims()[0]) > 8
+    with pytest.raises(pm.MpoError, match="chi_max"):
+        st.adjoint_brickwork(depth, sup, 8, 1e-12)
+    st.close()
+
+
 def test_adjoint_euler_identity_larger(pm):
     n, depth, p, chi = 12, 6, 0.01, 24
     say(f"case adjoint Euler identity n={n} depth={depth} chi={chi}")
