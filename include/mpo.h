@@ -149,6 +149,21 @@ mpo_status mpo_trace(mpo_handle *h, double *re, double *im);
 /* All <Z_i> = Tr[Z_i rho]/Tr[rho] (n values) and Tr[rho].                    */
 mpo_status mpo_expect_z_all(mpo_handle *h, double *z, double *trace);
 
+/* mpo_expect_z_all for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same transfer contraction, with its FP64 environments in a static
+ * device array of the library (8 MiB per GPU, held until the process ends)
+ * instead of the handle's arena.  The call allocates nothing and performs no
+ * allocating library call; the array's device address is looked up on the
+ * first call on each device.  Needs 2 (n+1) chi_cap + 65 chi_cap + 5 (n+2)
+ * complex FP64 values of scratch (each part 256-byte aligned), at most 8 MiB:
+ * a larger handle is MPO_ERR_ARENA before any launch.  Every call on a GPU
+ * shares that GPU's array and leaves its contents behind (every value the
+ * contraction reads is written first in the same call): calls that overlap on
+ * one GPU, from several threads or streams, race and must not be issued.
+ * The current device must be the handle's.  Synchronises.                   */
+mpo_status mpo_expect_z_all_noalloc(mpo_handle *h, double *z, double *trace);
+
 /* Output probability of a computational-basis measurement (Sec. III.D):
  * P(x) = Tr[|x><x| rho], a contraction of the MPO with one projector vector
  * per site.  bits: n values in {0,1}, bits[0] is the leftmost qubit.  The value

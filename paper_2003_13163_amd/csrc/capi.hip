@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -996,6 +997,62 @@ bool finite_all(const double* v, size_t n) {
 
 }  // namespace
 
+// ------------------------------------------------- allocation-free scratch
+// Device scratch for mpo_expect_z_all_noalloc: a file-scope device array, one
+// copy per GPU, resident while the library is loaded.  Host code must never
+// pass the array's own name to a kernel or a copy (on the host it is only a
+// stand-in symbol): its device address is looked up once per device with
+// hipGetSymbolAddress and that address is used everywhere.
+constexpr size_t kStaticScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device); nullptr with the error message set on failure.
+void* static_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        fail(MPO_ERR_HIP, "no current HIP device for the static scratch");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            fail(MPO_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_dev[dev] = ptr;
+    }
+    return g_scratch_dev[dev];
+}
+
+// Transfer-contraction scratch of an n-site handle with bond cap `cap`, carved
+// from `base` (or only measured when base is null); returns the bytes used.
+size_t carve_obs_scratch(char* base, int n, int cap, ObsScratch* w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return (double2*)p;
+    };
+    ObsScratch o;
+    o.envL = take((size_t)(n + 1) * cap * sizeof(double2));
+    o.envR = take((size_t)(n + 1) * cap * sizeof(double2));
+    o.tscr = take((size_t)kRightChunksMax * cap * sizeof(double2));
+    o.tmp = take((size_t)cap * sizeof(double2));
+    o.vecs = take((size_t)(n + 2) * 4 * sizeof(double2));
+    o.dots = take((size_t)(n + 2) * sizeof(double2));
+    if (w) *w = o;
+    return off;
+}
+}  // namespace
+
 void mpo_internal_set_error(const char* msg) { g_err = msg ? msg : ""; }
 
 // ==================================================================== C ABI
@@ -1212,6 +1269,21 @@ mpo_status mpo_expect_z_all(mpo_handle* h, double* z, double* trace) {
     if (st != MPO_OK) return st;
     if (!z) return fail(MPO_ERR_ARG, "z is NULL");
     return guarded(h, [&] { DISPATCH(h, E::observables(h, z, trace, nullptr)); });
+}
+
+mpo_status mpo_expect_z_all_noalloc(mpo_handle* h, double* z, double* trace) {
+    mpo_status st = check_live(h);
+    if (st != MPO_OK) return st;
+    if (!z) return fail(MPO_ERR_ARG, "z is NULL");
+    const size_t need = carve_obs_scratch(nullptr, h->n, h->chi_cap, nullptr);
+    if (need > kStaticScratchBytes)
+        return fail(MPO_ERR_ARENA, "n = %d, chi_cap = %d needs %zu bytes of scratch; the static scratch has %zu",
+                    h->n, h->chi_cap, need, kStaticScratchBytes);
+    char* base = (char*)static_scratch();
+    if (!base) return MPO_ERR_HIP;
+    ObsScratch w;
+    carve_obs_scratch(base, h->n, h->chi_cap, &w);
+    return guarded(h, [&] { DISPATCH(h, E::observables_in(h, w, z, trace, nullptr)); });
 }
 
 mpo_status mpo_bond_dims(mpo_handle* h, int* dims, int* center) {
