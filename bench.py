@@ -3,21 +3,25 @@
 A step is one noisy two-qubit gate update (centre move + contraction + 16x16
 channel + truncated SVD + entropy) on a saturated bulk bond,
 chi_L = chi_M = chi_R = 1024, theta' of size 4096 x 4096.  The state is an
-in-situ one: a 16-qubit chain evolved from |0..0> (in FP64) by a depth-10
-brickwork of Haar gates with two-qubit depolarizing noise p = 0.01 (seeded),
-which saturates bonds 4..10 at chi = 1024.  Timed gates then continue the brickwork
-on sites 5..9 (odd time steps 5, 7, 9; even time steps 6, 8) with fresh Haar
-gates, so every timed gate has the full 4096 x 4096 split and the centre
-moves a real brickwork needs.  Inputs are resident in HBM before timing.
+in-situ one from the precision workload: a 64-qubit chain evolved from
+|0..0> by a depth-12 brickwork of Haar gates, each followed by two-qubit
+depolarizing noise p = 0.01 (seed 0, chi_max = 1024, cutoff 1e-12; built in
+FP32 mode, the fastest, and exported), where every bond of sites 4..59 sits at
+chi = 1024.  Timed gates continue the brickwork on the bulk sites 16..46 with
+fresh Haar gates (seed 1): one time step puts 16 gates on 16, 18, .., 46, the
+next 15 on 17, .., 45, and the centre moves the brickwork needs (one per gate
+within a step, back across the bulk between steps) are part of every step.
+Inputs are resident in HBM before timing.
 
 The FP32-MFMA path is the headline `value`; the FP64 path on the same gates
 and snapshot is reported beside it, with the entropy error between the two
 and against the CPU oracle on the first timed gate.  `roofline` is for the
-kernel class with the largest event-measured time in the FP32 timed region;
+kernel class with the largest event-measured time in the FP32 timed region,
+`roofline_per_gate` for the whole gate against its nominal work;
 `cpu_baseline` times the oracle on one bulk gate of the same snapshot.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--chi 1024]
-                       [--no-cpu-baseline] [--profile-only]
+                       [--no-cpu-baseline] [--cpu-single-thread]
 """
 import argparse
 import json
@@ -52,10 +56,10 @@ def bulk_schedule(lo, hi, count, start_parity=1):
     return out
 
 
-def build_snapshot(pm, mi, n, depth, p, chi, seed):
+def build_snapshot(pm, mi, n, depth, p, chi, seed, prec="fp64"):
     draws = mi.ginibre_draws(n, depth, seed=seed)
     sup = pm.build_superops(draws, p, "pauli")
-    st = pm.Mpo(n, chi, "fp64", "pauli")
+    st = pm.Mpo(n, chi, prec, "pauli")
     t0 = time.time()
     st.run_brickwork(depth, sup, chi, 1e-12, record=None)
     dims, centre = st.bond_dims()
@@ -168,11 +172,13 @@ def measured_traffic(kernel, prec):
     return rec["kernels"][kernel]["bytes_per_launch"]
 
 
-def batch_measurement(pm, mi, torch, count, depth_cap=6, chi_cap=64, streams=16):
-    """Independent circuits of the batched workload (circuit i: n even in 16..96,
-    depth in [n/2, n], p in [0.005, 0.03], chi_max in {64..512}, all from
-    PCG64(i)), with depth and chi_max capped so the run stays short: aggregate
-    updates/s on one stream vs `streams` concurrent streams (mpo_batch_run)."""
+def batch_measurement(pm, mi, torch, count, depth_cap=4, chi_cap=64, streams=16):
+    """The batched workload's 128 circuits (circuit i: n even in 16..96, depth in
+    [n/2, n], p in [0.005, 0.03], chi_max in {64..512}, all from PCG64(i)) with
+    depth and chi_max capped so that the run stays short: aggregate updates/s
+    on one stream (the circuits one after the other), on `streams` concurrent
+    streams, and on `streams` streams with the Jacobi sweeps replayed from
+    captured HIP graphs; the three must agree bit for bit."""
     circuits, sups, ngates = [], [], 0
     for i in range(count):
         spec, draws = mi.batch_circuit(i)
@@ -183,18 +189,23 @@ def batch_measurement(pm, mi, torch, count, depth_cap=6, chi_cap=64, streams=16)
         ngates += g
     res = {}
     outs = {}
-    for ns in (1, streams):
-        log(f"batch: {count} circuits, {ngates} gates, {ns} stream(s)")
+    for label, ns, graphs in (("sequential", 1, False), (f"streams{streams}", streams, False),
+                              (f"streams{streams}_graphs", streams, True)):
+        log(f"batch: {count} circuits, {ngates} gates, {ns} stream(s), graphs {graphs}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        outs[ns] = pm.batch_run(circuits, sups, "fp32", "pauli", n_streams=ns)
+        outs[label] = pm.batch_run(circuits, sups, "fp32", "pauli", n_streams=ns, use_graph=graphs)
         dt = time.perf_counter() - t0
-        res[ns] = ngates / dt
-    same = all(np.array_equal(a["S"], b["S"]) for a, b in zip(outs[1], outs[streams]))
+        res[label] = ngates / dt
+    ref = outs["sequential"]
+    same = all(np.array_equal(a["S"], b["S"]) and np.array_equal(a["Z"], b["Z"])
+               for o in outs.values() for a, b in zip(ref, o))
     return {"workload": f"{count} circuits of the batched workload (seeds 0..{count - 1}), depth<={depth_cap}, "
                         f"chi_max<={chi_cap}, FP32-MFMA", "gates": ngates,
-            "sequential_updates_per_s": res[1], f"streams{streams}_updates_per_s": res[streams],
-            "speedup": res[streams] / res[1], "results_identical": bool(same)}
+            **{f"{k}_updates_per_s": v for k, v in res.items()},
+            "speedup_streams": res[f"streams{streams}"] / res["sequential"],
+            "speedup_streams_graphs": res[f"streams{streams}_graphs"] / res["sequential"],
+            "results_identical": bool(same)}
 
 
 def adjoint_measurement(pm, mi, torch, n=32, depth=24, p=0.01, chi=256):
@@ -214,33 +225,42 @@ def adjoint_measurement(pm, mi, torch, n=32, depth=24, p=0.01, chi=256):
     st.close()
     st = pm.Mpo(n, chi, "fp64", "pauli")
     t0 = time.perf_counter()
-    O, grads, comax = st.adjoint_brickwork(depth, sup, chi, 1e-12)
+    O, grads, comax = st.adjoint_brickwork(depth, sup, chi, 1e-12, checkpoint_every=4)
     t_adj = time.perf_counter() - t0
     st.close()
     euler = np.einsum("gij,gij->g", sup, grads)
     su = pm.build_superops(draws, 0.0, "pauli")
     dmdp = np.concatenate([[0.0], np.full(15, -16.0 / 15.0)])[None, :, None] * su
     dO_dp = float(np.einsum("gij,gij->", grads, dmdp).real)
-    return {"workload": f"n={n}, depth {depth}, p={p}, chi_max={chi}, seed 0, FP64, O = sum_i Tr[Z_i rho_D]",
+    return {"workload": f"n={n}, depth {depth}, p={p}, chi_max={chi}, seed 0, FP64, O = sum_i Tr[Z_i rho_D], "
+                        f"checkpoints every 4 time steps (segment recompute)",
             "gates": int(len(sup)), "forward_seconds": t_fwd, "forward_plus_adjoint_seconds": t_adj,
             "backward_seconds": t_adj - t_fwd, "O": O, "dO_dp": dO_dp,
             "euler_max_rel_dev": float(np.abs(euler - O).max() / abs(O)), "costate_max_bond": comax}
 
 
-def cpu_baseline(snap_bytes, pm, site, sup, chi):
-    """Oracle (numpy complex128) on one bulk gate of the same snapshot."""
+def cpu_baseline(snap_bytes, pm, site, sup, chi, threads=None):
+    """Oracle (numpy complex128) on one bulk gate of the same snapshot: the
+    centre is first moved to site - 1 (untimed), then the gate is timed with
+    the one QR move it needs, the contraction, the map and the gesdd split.
+    threads: BLAS threads (None = all)."""
     from oracle import mpo as omp
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
+    from threadpoolctl import threadpool_info, threadpool_limits
     n, basis, centre, tensors = pm.snapshot_to_tensors(snap_bytes)
     m = omp.MPO.__new__(omp.MPO)
     m.n, m.basis, m.A, m.centre = n, "pauli", tensors, centre
+    target = max(0, site - 1)
     t0 = time.perf_counter()
-    info = m.apply_gate(site, sup, chi, 1e-12)
-    dt = time.perf_counter() - t0
+    while m.centre != target:      # untimed: bring the centre next to the gate
+        m.move_centre(m.centre + (1 if m.centre < target else -1))
+        if abs(m.centre - target) % 8 == 0:
+            log(f"  oracle centre at {m.centre} ({time.perf_counter() - t0:.0f} s)")
+    log(f"  oracle gate at site {site}")
+    with threadpool_limits(limits=threads, user_api="blas"):
+        cores = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] + [1])
+        t0 = time.perf_counter()
+        info = m.apply_gate(site, sup, chi, 1e-12)
+        dt = time.perf_counter() - t0
     return dt, info, cores
 
 
@@ -270,16 +290,18 @@ def host_description():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-single-thread", action="store_true",
+                    help="also time the oracle gate with one BLAS thread (several minutes)")
     ap.add_argument("--precisions", default="fp32,fp64,bf16x3")
     ap.add_argument("--save-snapshot", default=None, help="write the in-situ snapshot to this file")
     ap.add_argument("--load-snapshot", default=None, help="reuse a snapshot written by --save-snapshot")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--batch-circuits", type=int, default=16)
+    ap.add_argument("--batch-circuits", type=int, default=128)
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy a 256 MiB device buffer 4 times first (traffic-counter calibration)")
     args = ap.parse_args()
@@ -303,21 +325,22 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    n, depth, p, chi, seed = 16, 10, 0.01, args.chi, 0
+    n, depth, p, chi, seed = 64, 12, 0.01, args.chi, 0
     if args.load_snapshot:
         snap = open(args.load_snapshot, "rb").read()
         dims = [int(v) for v in np.frombuffer(snap, dtype=np.int64, count=n - 1, offset=32)]
         log(f"loaded snapshot {args.load_snapshot}: bond dims {dims}")
     else:
         log(f"building in-situ snapshot: n={n} depth={depth} p={p} chi={chi}")
-        snap, dims, t_warm = build_snapshot(pm, mi, n, depth, p, chi, seed)
+        snap, dims, t_warm = build_snapshot(pm, mi, n, depth, p, chi, seed, prec="fp32")
         log(f"  bond dims {dims} ({t_warm:.1f} s)")
         if args.save_snapshot:
             with open(args.save_snapshot, "wb") as f:
                 f.write(snap)
-    lo, hi = 5, 9
+    lo, hi = 16, 46
     total = args.warmup + args.steps
-    sites = bulk_schedule(lo, hi, total)
+    # the next time step (depth + 1) puts gates on even sites when depth is even
+    sites = bulk_schedule(lo, hi, total, start_parity=depth % 2)
     draws = mi.ginibre_draws(n, 2 * total + 4, seed=seed + 1)
     sups = pm.build_superops(draws[:total], p, "pauli")
 
@@ -346,7 +369,8 @@ def main():
         "dtype": "f32" if head == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": f"bulk noisy 2q gate at chi={chi} (theta' {4 * chi}x{4 * chi}) on an "
                                f"in-situ {n}-qubit state (depth-{depth} Haar+depolarizing p={p} "
-                               f"brickwork, seed {seed}), brickwork gates on sites {lo}..{hi}",
+                               f"brickwork, seed {seed}, chi_max={chi}), brickwork gates on sites "
+                               f"{lo}..{hi} with their centre moves",
                    "chi": chi, "n": n, "p": p, "cutoff": 1e-12, "basis": "pauli",
                    "bond_dims": dims},
         "roofline": rl,
@@ -373,16 +397,23 @@ def main():
 
     if not args.no_batch:
         out["batch"] = batch_measurement(pm, mi, torch, args.batch_circuits)
+        log("  " + json.dumps(out["batch"]))
     if not args.no_adjoint:
         out["adjoint"] = adjoint_measurement(pm, mi, torch)
+        log("  " + json.dumps(out["adjoint"]))
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the first bulk gate of the snapshot")
         dt, info, cores = cpu_baseline(snap, pm, sites[0], sups[0], chi)
         out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "updates/s", "cores": cores,
                                "kind": "oracle", "host": host_description(),
-                               "sample": f"1 bulk gate (site {sites[0]}, chi={chi}) of the same "
-                                         f"snapshot, numpy complex128 gesdd, {dt:.1f} s"}
+                               "sample": f"1 bulk gate (site {sites[0]}, chi={chi}, with its one QR "
+                                         f"move) of the same snapshot, numpy complex128 gesdd, {dt:.1f} s"}
+        if args.cpu_single_thread:
+            log("cpu baseline: the same gate with one BLAS thread")
+            dt1, _, c1 = cpu_baseline(snap, pm, sites[0], sups[0], chi, threads=1)
+            out["cpu_baseline"]["single_thread"] = {"value": 1.0 / dt1, "unit": "updates/s", "cores": c1,
+                                                    "seconds": dt1}
         err = out.setdefault("entropy_error", {})
         for prec in res:
             err[f"{prec}_vs_oracle_first_gate"] = abs(float(res[prec]["entropy"][0]) - info.entropy)

@@ -52,8 +52,10 @@ typedef enum {
 typedef enum {
     MPO_FP64 = 0,       /* complex128 tensors, FP64 MFMA contractions        */
     MPO_FP32_MFMA = 1,  /* complex64 tensors and contractions on FP32 MFMA;
+                           the MFMA products are summed in FP32 over at most
+                           32 terms and those partial sums in FP64;
                            truncation weights and entropy in FP64.  Singular
-                           values with lambda^2 / sum lambda^2 <= 1e-9 are
+                           values with lambda^2 / sum lambda^2 <= 1e-11 are
                            at the mode's rounding floor and are never kept.
                            Any overall scale of the state is accepted: each
                            decomposition works on a power-of-two rescaled
@@ -71,7 +73,7 @@ typedef enum {
                            of times to each column, stay on FP32 MFMA; the
                            eigen core, weights and entropy stay FP64.
                            Singular values with
-                           lambda^2 / sum lambda^2 <= 1e-9 are at the mode's
+                           lambda^2 / sum lambda^2 <= 1e-11 are at the mode's
                            rounding floor and are never kept.                 */
 } mpo_precision;
 
@@ -220,6 +222,26 @@ mpo_status run_brickwork(mpo_handle *h, int depth, const double *superops, int n
                          double *S_out, double *Z_out, double *trace_out,
                          double *discarded_out);
 
+/* The paper's own update (App. A) for comparison with the local one: the
+ * state held in the Gamma-lambda form (Sec. III.A, lambda the Schmidt values
+ * of every bond), each noisy gate applied to B = lambda Gamma lambda Gamma
+ * lambda and split by the truncated SVD, then the canonical form of the whole
+ * chain restored by SVD sweeps to the left (B_<-) and to the right (B_->),
+ * with every Gamma recovered by dividing by the new lambda (Gamma <- W /
+ * lambda').  Singular values at or below 1e-14 of the largest are removed
+ * before any division.  n - 1 decompositions per gate, O(n chi^3) per gate
+ * against the O(chi^3) of mpo_apply_2q_channel (the "Note added"); in exact
+ * arithmetic the two truncate the same Schmidt values.  Starts from
+ * |0..0><0..0| (the current state is replaced), applies the ascending
+ * brickwork of run_brickwork (same superops layout and n_gates rule), writes
+ * S_b of every bond after every time step to S_out[t*(n-1)+b] (read from the
+ * lambdas, no extra sweep) and the discarded weight of every gate to
+ * discarded_out (either may be NULL), and leaves the handle in the mixed
+ * canonical form with the centre at n-1.  Errors as run_brickwork.
+ * Synchronises.                                                             */
+mpo_status mpo_run_brickwork_vidal(mpo_handle *h, int depth, const double *superops, int n_gates,
+                                   int chi_max, double cutoff, double *S_out, double *discarded_out);
+
 /* Host snapshot of the state.  Format: int64 header {magic, n, basis, center,
  * chi_0 .. chi_{n-2}} then per site the (chi_l, 4, chi_r) tensor, row-major,
  * complex128.  Exports carry magic 0x4d504f32 ("MPO2": sites left of center
@@ -241,13 +263,18 @@ mpo_status mpo_build_superop(const double *re, const double *im, double p, mpo_b
                              double *out, double *u_out);
 
 /* Batched evolution of independent circuits (the paper averages over N_s
- * independent random circuits, Sec. IV.A).  Each circuit is a brickwork as in
- * run_brickwork, starting from |0..0><0..0|.
+ * independent random circuits, Sec. IV.A).  Each circuit is an ascending
+ * brickwork as in run_brickwork, starting from |0..0><0..0|.
+ *   use_graph: 1 = Jacobi sweeps replayed from captured HIP graphs
+ *     (mpo_set_graphs) on every circuit's handle; streams must be non-null.
  *   superops_concat: all circuits' superoperators (16x16 complex each),
  *     circuit c using gates [gate_offset, gate_offset + n_gates(n, depth)).
- *   results: per circuit at result_offset: S_b after the last time step
- *     (n-1 values), <Z_i> (n), Tr rho, summed discarded weight, largest bond
- *     dimension reached (as a double): 2n+2 values.
+ *   record_mask: 0 or 2 = observables after the last time step only, 1 = after
+ *     every time step (R = depth rows; R = 1 for depth 0 or the last step).
+ *   results: per circuit at result_offset, mpo_batch_result_doubles(n, depth,
+ *     record_mask) = 2 n R + 2 values: S_b (R rows of n-1), <Z_i> (R rows of
+ *     n), Tr rho (R), then the summed discarded weight and the largest bond
+ *     dimension reached (as a double).
  * Work is spread over n_streams caller-owned HIP streams (n_streams >= 1),
  * one host worker thread per stream; circuits are taken largest first
  * (n * depth * chi_max^3).  The arena is split into n_streams equal slices,
@@ -262,11 +289,13 @@ typedef struct {
 } mpo_batch_desc;
 mpo_status mpo_batch_workspace_bytes(const mpo_batch_desc *circuits, int count,
                                      mpo_precision prec, int n_streams, size_t *bytes);
+int mpo_batch_result_doubles(int n, int depth, int record_mask);
 mpo_status mpo_batch_run(const mpo_batch_desc *circuits, int count,
                          const double *superops_concat, size_t n_superops,
                          mpo_precision prec, mpo_basis basis,
                          void *dev_arena, size_t arena_bytes,
-                         void *const *hip_streams, int n_streams, double *results);
+                         void *const *hip_streams, int n_streams, int use_graph,
+                         int record_mask, double *results);
 
 /* Gradient of O = sum_i Tr[Z_i rho_D] (unnormalised, so linear in rho) with
  * respect to every gate superoperator, with the truncation projectors frozen.
@@ -292,6 +321,27 @@ mpo_status mpo_adjoint_brickwork(mpo_handle *h, int depth, const double *superop
                                  int chi_max, double cutoff, int checkpoint_every,
                                  void *dev_work, size_t work_bytes,
                                  double *O_out, double *dO_dsuperop, int *costate_max_bond);
+
+/* Launch mode of the Jacobi sweeps of a handle.  on = 1: each sweep (norm
+ * sort, every round's pair Gram / eigen-solver / update launches, and the
+ * convergence test, which runs on the device) is captured once per matrix
+ * shape into a HIP graph and replayed; several sweeps are queued between two
+ * reads of the convergence flag, and the launches of a sweep queued after
+ * convergence return at once.  Results are bit-identical to on = 0 (direct
+ * launches, one read per sweep).  Needs the handle's stream to be non-null
+ * (MPO_ERR_ARG otherwise).  Per-kernel profiling uses direct launches.      */
+mpo_status mpo_set_graphs(mpo_handle *h, int on);
+
+/* Tunables of the blocked one-sided Jacobi: block width (16 or 32 columns, a
+ * block pair is twice that) and inner FP64 sweeps per block pair (1..8).
+ * mpo_set_tuning sets them on one handle; mpo_set_default_tuning records an
+ * entry used by every later mpo_create of that precision whose chi_cap is at
+ * most chi_upto (the smallest such chi_upto wins; environment overrides
+ * MPO_JACOBI_BLOCK / MPO_JACOBI_INNER still apply after it).  Entries come
+ * from the autotuner (paper_2003_13163_amd/autotune.py), which times the
+ * candidates on in-situ gates.  Errors: MPO_ERR_ARG for other values.       */
+mpo_status mpo_set_tuning(mpo_handle *h, int block, int inner);
+mpo_status mpo_set_default_tuning(mpo_precision prec, int chi_upto, int block, int inner);
 
 /* Instrumentation: per-kernel-class timing with HIP events recorded on the
  * handle's stream around every launch, plus the algorithmic flop and byte

@@ -52,8 +52,12 @@ def record_prefixes(n, superops, layers, chi_max, cutoff, basis="pauli"):
 
 
 def _overlap_step(env, phi, r):
-    """E'[a', b'] = sum_{a, I, b} conj(phi[a, I, a']) E[a, b] r[b, I, b']."""
-    return np.einsum("aIx,ab,bIy->xy", phi.conj(), env, r)
+    """E'[a', b'] = sum_{a, I, b} conj(phi[a, I, a']) E[a, b] r[b, I, b'],
+    as two matrix products: T = E r over b, then phi^dagger T over (a, I)."""
+    a, d, x = phi.shape
+    b, _, y = r.shape
+    t = (env @ r.reshape(b, d * y)).reshape(a * d, y)
+    return phi.reshape(a * d, x).conj().T @ t
 
 
 def frozen_replay_value(n, superops, layers, prefixes, basis="pauli") -> complex:
@@ -67,8 +71,8 @@ def frozen_replay_value(n, superops, layers, prefixes, basis="pauli") -> complex
             # 1. noisy gate, exact split
             a, b = R[s], R[s + 1]
             chil, chir = a.shape[0], b.shape[2]
-            th = np.einsum("aIb,bJc->aIJc", a, b)
-            th = np.einsum("IJKL,aKLc->aIJc", np.asarray(superops[g]).reshape(4, 4, 4, 4), th)
+            th = (a.reshape(chil * 4, -1) @ b.reshape(b.shape[0], 4 * chir)).reshape(chil, 16, chir)
+            th = np.einsum("ij,ajc->aic", np.asarray(superops[g]), th, optimize=True)
             q, r = np.linalg.qr(th.reshape(chil * 4, 4 * chir))
             R[s] = q.reshape(chil, 4, q.shape[1])
             R[s + 1] = r.reshape(r.shape[0], 4, chir)
@@ -82,7 +86,8 @@ def frozen_replay_value(n, superops, layers, prefixes, basis="pauli") -> complex
                 env = _overlap_step(env, pre[q], R[q])
             for q in range(s + 1):
                 R[q] = pre[q]
-            R[s + 1] = np.einsum("xb,bJc->xJc", env, R[s + 1])
+            b1, d1, c1 = R[s + 1].shape
+            R[s + 1] = (env @ R[s + 1].reshape(b1, d1 * c1)).reshape(env.shape[0], d1, c1)
             g += 1
     t_vec = dual_vector(PAULI[0], basis)
     z_vec = dual_vector(PAULI[3], basis)

@@ -96,7 +96,12 @@ def library() -> ctypes.CDLL:
         "mpo_import": [P, P, S],
         "mpo_build_superop": [pd, pd, D, I, pd, pd],
         "mpo_batch_workspace_bytes": [P, I, I, I, ctypes.POINTER(S)],
-        "mpo_batch_run": [P, I, pd, S, I, I, P, S, P, I, pd],
+        "mpo_batch_run": [P, I, pd, S, I, I, P, S, P, I, I, I, pd],
+        "mpo_set_graphs": [P, I],
+        "mpo_run_brickwork_vidal": [P, I, pd, I, I, D, pd, pd],
+        "mpo_set_tuning": [P, I, I],
+        "mpo_set_default_tuning": [I, I, I, I],
+        "mpo_batch_result_doubles": [I, I, I],
         "mpo_adjoint_workspace_bytes": [I, I, I, I, I, ctypes.POINTER(S)],
         "mpo_adjoint_brickwork": [P, I, pd, I, I, D, I, P, S, pd, pd, pi],
         "mpo_profile_enable": [P, I],
@@ -108,7 +113,24 @@ def library() -> ctypes.CDLL:
         fn.argtypes = args
         fn.restype = None if name == "mpo_destroy" else (ctypes.c_char_p if name == "mpo_last_error" else ctypes.c_int)
     _lib = lib
+    _load_tuning(lib)
     return lib
+
+
+_TUNING_PATH = os.path.join(_HERE, "tuning.json")
+
+
+def _load_tuning(lib):
+    """Hand the autotuner's table (tuning.json, if present) to the library."""
+    import json
+    try:
+        with open(_TUNING_PATH) as f:
+            entries = json.load(f).get("entries", [])
+    except (OSError, ValueError):
+        return
+    for e in entries:
+        _check(lib.mpo_set_default_tuning(_PREC[e["precision"]], int(e["chi_upto"]), int(e["block"]),
+                                          int(e["inner"])))
 
 
 def _check(status: int):
@@ -293,6 +315,10 @@ class Mpo:
         del work
         return O.value, grads.view(np.complex128).reshape(g, 16, 16), comax.value
 
+    def set_graphs(self, on: bool = True):
+        """Replay the Jacobi sweeps from captured HIP graphs (needs a non-null stream)."""
+        _check(library().mpo_set_graphs(self._h, 1 if on else 0))
+
     # ------------------------------------------------------------- instrumentation
     def profile(self, on: bool = True):
         """Enable (and reset) per-kernel HIP-event timing on this handle's stream."""
@@ -331,23 +357,39 @@ class Mpo:
                 "discarded": disc[:g]}
 
 
+    def run_brickwork_vidal(self, depth: int, superops, chi_max: int, cutoff: float = 1e-12) -> dict:
+        """The paper's global Gamma-lambda update (App. A) from |0..0>: S_b after
+        every time step (from the lambdas) and the discarded weight per gate."""
+        sup = _as_complex_pairs(superops).reshape(-1)
+        g = sup.size // 512
+        S = np.zeros(max(depth, 1) * (self.n - 1))
+        disc = np.zeros(max(g, 1))
+        _check(library().mpo_run_brickwork_vidal(self._h, depth, _dptr(sup), g, chi_max, float(cutoff),
+                                                 _dptr(S), _dptr(disc)))
+        return {"S": S[: depth * (self.n - 1)].reshape(depth, self.n - 1), "discarded": disc[:g]}
+
+
 class _BatchDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("depth", ctypes.c_int), ("chi_max", ctypes.c_int),
                 ("cutoff", ctypes.c_double), ("gate_offset", ctypes.c_size_t),
                 ("result_offset", ctypes.c_size_t)]
 
 
-def batch_run(circuits, superops, precision="fp32", basis="pauli", n_streams=8, device=None):
+def batch_run(circuits, superops, precision="fp32", basis="pauli", n_streams=8, device=None,
+              record="last", use_graph=False):
     """Evolve independent circuits concurrently (mpo_batch_run).
 
     circuits: list of (n, depth, chi_max, cutoff); superops: list of arrays
-    (n_gates(n, depth), 16, 16) per circuit.  Returns one dict per circuit with
-    S (n-1 bond entropies after the last time step), Z, trace, discarded (sum
-    over gates) and max_bond."""
+    (n_gates(n, depth), 16, 16) per circuit.  record: "last" (observables after
+    the last time step) or "all" (after every time step).  use_graph: replay the
+    Jacobi sweeps from captured HIP graphs (mpo_set_graphs).  Returns one dict per
+    circuit with S (rows x (n-1) bond entropies), Z (rows x n), trace (rows),
+    discarded (sum over gates) and max_bond; rows = 1 for "last"."""
     import torch
     lib = library()
     count = len(circuits)
     descs = (_BatchDesc * count)()
+    mask = {"last": 2, "all": 1}[record]
     g_off, r_off = 0, 0
     for i, (n, depth, chi, cut) in enumerate(circuits):
         g = n_schedule_gates(n, depth)
@@ -355,7 +397,7 @@ def batch_run(circuits, superops, precision="fp32", basis="pauli", n_streams=8, 
             raise ValueError(f"circuit {i}: {superops[i].shape[0]} superoperators, {g} expected")
         descs[i] = _BatchDesc(n, depth, chi, float(cut), g_off, r_off)
         g_off += g
-        r_off += 2 * n + 2
+        r_off += lib.mpo_batch_result_doubles(n, depth, mask)
     sup = np.ascontiguousarray(np.concatenate([np.asarray(s, dtype=np.complex128).reshape(-1, 16, 16)
                                                for s in superops]))
     prec = _PREC[precision]
@@ -370,12 +412,20 @@ def batch_run(circuits, superops, precision="fp32", basis="pauli", n_streams=8, 
     torch.cuda.synchronize(dev)
     _check(lib.mpo_batch_run(dptr, count, _dptr(sup.view(np.float64)), g_off, prec, _BASIS[basis],
                              ctypes.c_void_p(arena.data_ptr()), nbytes.value,
-                             ctypes.cast(handles, ctypes.c_void_p), n_streams, _dptr(res)))
+                             ctypes.cast(handles, ctypes.c_void_p), n_streams, 1 if use_graph else 0, mask,
+                             _dptr(res)))
     out = []
     for i, (n, depth, chi, cut) in enumerate(circuits):
-        r = res[descs[i].result_offset: descs[i].result_offset + 2 * n + 2]
-        out.append({"S": r[: n - 1].copy(), "Z": r[n - 1: 2 * n - 1].copy(), "trace": r[2 * n - 1],
-                    "discarded": r[2 * n], "max_bond": int(r[2 * n + 1])})
+        rows = depth if (mask == 1 and depth > 0) else 1
+        o = descs[i].result_offset
+        S = res[o: o + rows * (n - 1)].reshape(rows, n - 1)
+        Z = res[o + rows * (n - 1): o + rows * (2 * n - 1)].reshape(rows, n)
+        tr = res[o + rows * (2 * n - 1): o + rows * 2 * n]
+        tail = res[o + rows * 2 * n: o + rows * 2 * n + 2]
+        if mask == 2:
+            S, Z, tr = S[0], Z[0], float(tr[0])
+        out.append({"S": S.copy(), "Z": Z.copy(), "trace": tr if mask == 2 else tr.copy(),
+                    "discarded": tail[0], "max_bond": int(tail[1])})
     del arena
     return out
 

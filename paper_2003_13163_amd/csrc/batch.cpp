@@ -47,14 +47,29 @@ extern "C" mpo_status mpo_batch_workspace_bytes(const mpo_batch_desc* circuits, 
     return MPO_OK;
 }
 
+extern "C" int mpo_batch_result_doubles(int n, int depth, int record_mask) {
+    const int rows = ((record_mask & 1) && depth > 0) ? depth : 1;
+    return rows * 2 * n + 2;
+}
+
 extern "C" mpo_status mpo_batch_run(const mpo_batch_desc* circuits, int count,
                                     const double* superops_concat, size_t n_superops,
                                     mpo_precision prec, mpo_basis basis, void* dev_arena,
                                     size_t arena_bytes, void* const* hip_streams, int n_streams,
-                                    double* results) {
+                                    int use_graph, int record_mask, double* results) {
     if (!circuits || count < 1 || !superops_concat || !dev_arena || !results || n_streams < 1 ||
         !hip_streams)
         return MPO_ERR_ARG;
+    if (use_graph)
+        for (int w = 0; w < n_streams; ++w)
+            if (!hip_streams[w]) {
+                mpo_internal_set_error("use_graph needs non-null streams (a capture cannot use the null stream)");
+                return MPO_ERR_ARG;
+            }
+    if (record_mask != 0 && record_mask != 1 && record_mask != 2) {
+        mpo_internal_set_error("record_mask must be 0 or 2 (last time step) or 1 (every time step)");
+        return MPO_ERR_ARG;
+    }
     for (int i = 0; i < count; ++i) {
         const mpo_batch_desc& c = circuits[i];
         if (c.n < 2 || (c.n & 1) || c.depth < 0 || c.chi_max < 1 || c.chi_max > 1024 ||
@@ -90,25 +105,29 @@ extern "C" mpo_status mpo_batch_run(const mpo_batch_desc* circuits, int count,
             const mpo_batch_desc& c = circuits[order[k]];
             mpo_handle* h = nullptr;
             mpo_status s = mpo_create(c.n, c.chi_max, prec, basis, base, slice, hip_streams[w], &h);
+            if (s == MPO_OK && use_graph) s = mpo_set_graphs(h, 1);
             if (s == MPO_OK) {
                 const int g = (int)gates_of(c.n, c.depth);
                 std::vector<double> disc((size_t)std::max(g, 1));
                 double* out = results + c.result_offset;
+                // rows recorded: every time step (record_mask 1) or the last one
+                const bool every = (record_mask & 1) && c.depth > 0;
+                const int rows = every ? c.depth : 1;
+                double* S = out;
+                double* Z = out + (size_t)rows * (c.n - 1);
+                double* tr = Z + (size_t)rows * c.n;
                 s = run_brickwork(h, c.depth, superops_concat + 512 * c.gate_offset, g, c.chi_max,
-                                  c.cutoff, MPO_ORDER_ASCENDING, 2, out, out + (c.n - 1), out + (2 * c.n - 1),
-                                  disc.data());
+                                  c.cutoff, MPO_ORDER_ASCENDING, every ? 1 : 2, S, Z, tr, disc.data());
                 if (s == MPO_OK) {
                     double tot = 0.0;
                     for (int q = 0; q < g; ++q) tot += disc[q];
-                    out[2 * c.n] = tot;
+                    tr[rows] = tot;
                     std::vector<int> dims(c.n - 1);
                     mpo_bond_dims(h, dims.data(), nullptr);
-                    out[2 * c.n + 1] = dims.empty() ? 1.0 : (double)*std::max_element(dims.begin(), dims.end());
+                    tr[rows + 1] = dims.empty() ? 1.0 : (double)*std::max_element(dims.begin(), dims.end());
                     if (c.depth == 0) {   // nothing recorded: product state values
-                        for (int b = 0; b < c.n - 1; ++b) out[b] = 0.0;
-                        double tr = 0.0;
-                        mpo_expect_z_all(h, out + (c.n - 1), &tr);
-                        out[2 * c.n - 1] = tr;
+                        for (int b = 0; b < c.n - 1; ++b) S[b] = 0.0;
+                        s = mpo_expect_z_all(h, Z, tr);
                     }
                 }
                 if (s != MPO_OK) errs[w] = mpo_last_error();

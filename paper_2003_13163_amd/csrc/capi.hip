@@ -63,6 +63,11 @@ constexpr int kRightChunksMax = 64;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Column stride of the SVD work matrices X, X2 with m rows: m + 8 (rounded up
+// to even) complex values.  A power-of-two stride (m = 4 chi) puts the columns
+// that one MFMA operand load touches into the same L1 cache sets.
+inline int work_ld(int m) { return ((m + 1) & ~1) + 8; }
+
 struct Layout {
     size_t slot_bytes, slots, x_bytes, r_bytes, partial_bytes, w_bytes, skip_bytes, vecN_bytes,
         info_bytes, env_bytes, tscr_bytes, vec_bytes, dot_bytes, super_bytes, total;
@@ -75,7 +80,7 @@ Layout make_layout(int n, int chi_cap, mpo_precision prec) {
     const size_t cc = (size_t)chi_cap * chi_cap;
     L.slot_bytes = align256(4 * cc * csz);
     L.slots = (size_t)n + 2;
-    L.x_bytes = align256(16 * cc * csz);
+    L.x_bytes = align256((size_t)work_ld(4 * chi_cap) * 4 * chi_cap * csz);
     L.r_bytes = align256(cc * csz);
     int nb = (4 * chi_cap + 31) / 32;
     if (nb < 2) nb = 2;
@@ -92,13 +97,16 @@ Layout make_layout(int n, int chi_cap, mpo_precision prec) {
     L.dot_bytes = align256((size_t)(n + 2) * sizeof(double2));
     L.super_bytes = align256((size_t)kMaxSuper * 256 * csz);
     L.total = L.slot_bytes * L.slots + 2 * L.x_bytes + L.r_bytes + L.partial_bytes + L.w_bytes +
-              L.skip_bytes + 3 * L.vecN_bytes + L.info_bytes + 2 * L.env_bytes + L.tscr_bytes +
+              L.skip_bytes + 3 * L.vecN_bytes + 2 * align256((size_t)chi_cap * sizeof(double)) +
+              L.info_bytes + 2 * L.env_bytes + L.tscr_bytes +
               align256((size_t)chi_cap * sizeof(double2)) + L.vec_bytes + L.dot_bytes +
               L.super_bytes;
     return L;
 }
 
 }  // namespace
+
+void tuned_jacobi(mpo_precision prec, int chi_cap, int* block, int* inner);
 
 struct mpo_handle {
     int n = 0, chi_cap = 0;
@@ -119,6 +127,7 @@ struct mpo_handle {
     double2 *envL = nullptr, *envR = nullptr, *tscr = nullptr, *tmp = nullptr, *vecs = nullptr,
             *dots = nullptr;
     double* sig2_all = nullptr;  // copy of the last split's sorted squared values
+    double *lamA = nullptr, *lamB = nullptr;   // lambda vectors of the Gamma-lambda update
     // pinned host staging
     DevInfo* info_host = nullptr;
     void* super_stage = nullptr;
@@ -204,7 +213,8 @@ struct Engine {
 
     // Orthogonalise the columns of X (m x N); truncation with (chi_max, cutoff).
     static DevInfo split(mpo_handle* h, int m, int N, int chi_max, double cutoff) {
-        const int sw = jacobi_orthogonalize<T>((C*)h->X, m, N, jacobi_tol(h, m), kMaxSweeps, h->jw, h->st);
+        const int sw = jacobi_orthogonalize<T>((C*)h->X, m, N, work_ld(m), jacobi_tol(h, m), kMaxSweeps,
+                                               h->jw, h->st);
         if (sw == -2) HIPCHK(hipGetLastError());
         if (sw == -3) throw HipError{hipErrorInvalidValue, "jacobi pair capacity"};
         if (sw < 0) throw NoConvError{"one-sided Jacobi SVD did not converge"};
@@ -218,20 +228,32 @@ struct Engine {
         return inf;
     }
 
+    // The first r sorted singular values of the last split, to the host.
+    static void read_values(mpo_handle* h, int r, std::vector<double>& lam) {
+        HIPCHK(hipMemcpyAsync(h->sig_host, h->jw.sig2, sizeof(double) * r, hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+        lam.resize(r);
+        for (int i = 0; i < r; ++i) lam[i] = std::sqrt(std::fmax(h->sig_host[i], 0.0));
+    }
+
     // Centre c -> c+1: L(A_c) = U R exactly; A_c <- U, A_{c+1} <- R A_{c+1}.
-    static void move_right(mpo_handle* h, int c) {
+    // keep_values stores the singular values found (Schmidt values of bond c
+    // when sites right of c+1 are right isometries) in last_lam[c]; cut < 0 is
+    // the mode's re-gauge cut.
+    static void move_right(mpo_handle* h, int c, bool keep_values = false, double cut = -1.0) {
         const int chiL = h->chiL(c), chiR = h->dims[c], chiR2 = h->chiR(c + 1);
         const int m = 4 * chiL, N = chiR;
         h->prof.begin(h->st);
-        launch_copy<T>(site(h, c), (C*)h->X, (size_t)m * N, h->st);
+        launch_copy_cols<T>(site(h, c), m, N, m, (C*)h->X, work_ld(m), h->st);
         h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * N);
-        DevInfo inf = split(h, m, N, N, regauge_cut(h));
+        DevInfo inf = split(h, m, N, N, cut < 0.0 ? regauge_cut(h) : cut);
         const int r = inf.kept;
+        if (keep_values) read_values(h, r, h->last_lam[c]);
         const int s1 = h->take_spare(), s2 = h->take_spare();
         C* U = (C*)h->slot[s1];
         C* Anext = (C*)h->slot[s2];
         h->prof.begin(h->st);
-        launch_gather_cols<T>((C*)h->X, m, h->jw.colmap, h->jw.sig2, r, U, m, h->st);
+        launch_gather_cols<T>((C*)h->X, m, work_ld(m), h->jw.colmap, h->jw.sig2, r, U, m, h->st);
         h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * r);
         h->prof.begin(h->st);
         launch_cgemm<T>(1, 0, r, chiR, m, U, m, site(h, c), m, (C*)h->R, r, h->st, h->bf3);
@@ -249,27 +271,21 @@ struct Engine {
 
     // Centre c -> c-1: R(A_c) = L Q exactly; the singular values found on the
     // way are the Schmidt values of bond c-1 (all other sites are isometries).
-    static DevInfo move_left(mpo_handle* h, int c, bool keep_values) {
+    static DevInfo move_left(mpo_handle* h, int c, bool keep_values, double cut = -1.0) {
         const int chiL = h->dims[c - 1], chiR = h->chiR(c), chiLL = h->chiL(c - 1);
         const int m = 4 * chiR, N = chiL;
         h->prof.begin(h->st);
-        launch_conj_transpose<T>(site(h, c), chiL, m, (C*)h->X, h->st);
+        launch_conj_transpose<T>(site(h, c), chiL, m, chiL, (C*)h->X, work_ld(m), h->st);
         h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * chiL);
-        DevInfo inf = split(h, m, N, N, regauge_cut(h));
+        DevInfo inf = split(h, m, N, N, cut < 0.0 ? regauge_cut(h) : cut);
         const int r = inf.kept;
-        if (keep_values) {
-            HIPCHK(hipMemcpyAsync(h->sig_host, h->jw.sig2, sizeof(double) * r, hipMemcpyDeviceToHost, h->st));
-            HIPCHK(hipStreamSynchronize(h->st));
-            std::vector<double>& lam = h->last_lam[c - 1];
-            lam.resize(r);
-            for (int i = 0; i < r; ++i) lam[i] = std::sqrt(std::fmax(h->sig_host[i], 0.0));
-        }
+        if (keep_values) read_values(h, r, h->last_lam[c - 1]);
         h->last_S[c - 1] = inf.entropy;
         const int s1 = h->take_spare(), s2 = h->take_spare();
         C* Q = (C*)h->slot[s1];
         C* Aprev = (C*)h->slot[s2];
         h->prof.begin(h->st);
-        launch_gather_rows_conj<T>((C*)h->X, m, h->jw.colmap, h->jw.sig2, r, Q, h->st);
+        launch_gather_rows_conj<T>((C*)h->X, m, work_ld(m), h->jw.colmap, h->jw.sig2, r, Q, h->st);
         h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * r);
         h->prof.begin(h->st);
         launch_cgemm<T>(0, 1, chiL, r, m, site(h, c), chiL, Q, r, (C*)h->R, chiL, h->st, h->bf3);
@@ -299,7 +315,7 @@ struct Engine {
         const int m = 4 * chiL, N = 4 * chiR;
         h->prof.begin(h->st);
         launch_theta_channel<T>(chiL, chiM, chiR, site(h, s), site(h, s + 1), Mg, (C*)h->X,
-                                (C*)h->X2, h->st, h->bf3);
+                                (C*)h->X2, work_ld(m), h->st, h->bf3);
         h->prof.end(h->st, K_THETA, 8.0 * m * chiM * N + 2048.0 * chiL * chiR,
                     (double)sizeof(C) * (4.0 * chiL * chiM + 4.0 * chiM * chiR + 2.0 * m * N));
         HIPCHK(hipGetLastError());
@@ -307,10 +323,11 @@ struct Engine {
         const int k = inf.kept;
         // A_s <- U_k (left isometry, in place); A_{s+1} <- U_k^H theta' (new centre)
         h->prof.begin(h->st);
-        launch_gather_cols<T>((C*)h->X, m, h->jw.colmap, h->jw.sig2, k, site(h, s), m, h->st);
+        launch_gather_cols<T>((C*)h->X, m, work_ld(m), h->jw.colmap, h->jw.sig2, k, site(h, s), m, h->st);
         h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * k);
         h->prof.begin(h->st);
-        launch_cgemm<T>(1, 0, k, N, m, site(h, s), m, (C*)h->X2, m, site(h, s + 1), k, h->st, h->bf3);
+        launch_cgemm<T>(1, 0, k, N, m, site(h, s), m, (C*)h->X2, work_ld(m), site(h, s + 1), k, h->st,
+                        h->bf3);
         h->prof.end(h->st, K_GEMM, 8.0 * k * N * m, (double)sizeof(C) * ((double)m * k + (double)m * N + (double)k * N));
         HIPCHK(hipGetLastError());
         h->dims[s] = k;
@@ -334,20 +351,22 @@ struct Engine {
         const int m = 4 * chiL, N = 4 * chiR;
         h->prof.begin(h->st);
         launch_theta_channel<T>(chiL, chiM, chiR, site(h, s), site(h, s + 1), Mg, (C*)h->X2, nullptr,
-                                h->st, h->bf3);
+                                work_ld(m), h->st, h->bf3);
         h->prof.end(h->st, K_THETA, 8.0 * m * chiM * N + 2048.0 * chiL * chiR,
                     (double)sizeof(C) * (4.0 * chiL * chiM + 4.0 * chiM * chiR + 2.0 * m * N));
         h->prof.begin(h->st);
-        launch_conj_transpose<T>((C*)h->X2, m, N, (C*)h->X, h->st);
+        launch_conj_transpose<T>((C*)h->X2, m, N, work_ld(m), (C*)h->X, work_ld(N), h->st);
         h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * N);
         HIPCHK(hipGetLastError());
         DevInfo inf = split(h, N, m, chi_max, cutoff);
         const int k = inf.kept;
         h->prof.begin(h->st);
-        launch_gather_rows_conj<T>((C*)h->X, N, h->jw.colmap, h->jw.sig2, k, site(h, s + 1), h->st);
+        launch_gather_rows_conj<T>((C*)h->X, N, work_ld(N), h->jw.colmap, h->jw.sig2, k, site(h, s + 1),
+                                   h->st);
         h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * N * k);
         h->prof.begin(h->st);
-        launch_cgemm<T>(0, 1, m, k, N, (C*)h->X2, m, site(h, s + 1), k, site(h, s), m, h->st, h->bf3);
+        launch_cgemm<T>(0, 1, m, k, N, (C*)h->X2, work_ld(m), site(h, s + 1), k, site(h, s), m, h->st,
+                        h->bf3);
         h->prof.end(h->st, K_GEMM, 8.0 * m * k * N, (double)sizeof(C) * ((double)m * N + (double)k * N + (double)m * k));
         HIPCHK(hipGetLastError());
         h->dims[s] = k;
@@ -358,6 +377,142 @@ struct Engine {
         out.total_weight = inf.total;
         out.entropy = inf.entropy;
         return out;
+    }
+
+    // ------------------------------------------------ the paper's own update
+    // App. A: the state in the Gamma-lambda form (Sec. III.A), a noisy gate on
+    // the block B = lambda Gamma lambda Gamma lambda, its truncated SVD, then SVD
+    // sweeps that restore the canonical form of the whole chain, every Gamma
+    // recovered by dividing by the new lambda (Gamma <- W / lambda').  n - 1
+    // decompositions per gate: O(n chi^3) per gate, against the local update's
+    // O(chi^3) (the "Note added").  Sites hold the Gammas; lam[b] the lambdas.
+    static void upload_lam(mpo_handle* h, const std::vector<double>& v, double* dst) {
+        std::copy(v.begin(), v.end(), h->sig_host);   // pinned staging, reused: wait below
+        HIPCHK(hipMemcpyAsync(dst, h->sig_host, sizeof(double) * v.size(), hipMemcpyHostToDevice, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+    }
+
+    static double vidal_gate(mpo_handle* h, int s, const C* Mg, int chi_max, double cutoff, double drop,
+                             std::vector<std::vector<double>>& lam) {
+        const int n = h->n;
+        const int chiL = h->chiL(s), chiM = h->dims[s], chiR = h->chiR(s + 1);
+        const int m = 4 * chiL, N = 4 * chiR;
+        // B = lambda_{s-1} Gamma_s lambda_s Gamma_{s+1} lambda_{s+1} (scalings applied in place)
+        if (s > 0) upload_lam(h, lam[s - 1], h->lamA);
+        upload_lam(h, lam[s], h->lamB);
+        launch_scale_site<T>(site(h, s), chiL, chiM, s > 0 ? h->lamA : nullptr, h->lamB, false, false, h->st);
+        if (s + 1 < n - 1) {
+            upload_lam(h, lam[s + 1], h->lamA);
+            launch_scale_site<T>(site(h, s + 1), chiM, chiR, nullptr, h->lamA, false, false, h->st);
+        }
+        launch_theta_channel<T>(chiL, chiM, chiR, site(h, s), site(h, s + 1), Mg, (C*)h->X, (C*)h->X2,
+                                work_ld(m), h->st, h->bf3);
+        HIPCHK(hipGetLastError());
+        DevInfo inf = split(h, m, N, chi_max, cutoff);
+        std::vector<double> lp;
+        read_values(h, inf.kept, lp);
+        // Gamma = W / lambda' is undefined for lambda' = 0: values at or below
+        // drop * lambda'_max are removed before any division
+        int k = 0;
+        while (k < (int)lp.size() && lp[k] > drop * lp[0]) ++k;
+        k = std::max(1, k);
+        lp.resize(k);
+        // site s <- U lambda' (the columns as they are), site s+1 <- U^H theta' = lambda' V^H
+        const int su = h->take_spare();
+        C* U = (C*)h->slot[su];
+        launch_gather_cols<T>((C*)h->X, m, work_ld(m), h->jw.colmap, h->jw.sig2, k, U, m, h->st, true);
+        launch_cgemm<T>(1, 0, k, N, m, U, m, (C*)h->X2, work_ld(m), site(h, s + 1), k, h->st, h->bf3);
+        launch_gather_cols<T>((C*)h->X, m, work_ld(m), h->jw.colmap, h->jw.sig2, k, site(h, s), m, h->st,
+                              false);
+        HIPCHK(hipGetLastError());
+        h->give_spare(su);
+        h->dims[s] = k;
+        lam[s] = lp;
+        // left sweep (B_<-): bonds s-1 .. 0
+        std::vector<double> cur = lp;
+        for (int j = s; j >= 1; --j) {
+            if (j - 1 >= 1) {   // site j-1 <- lambda_{j-2} Gamma_{j-1}
+                upload_lam(h, lam[j - 2], h->lamA);
+                launch_scale_site<T>(site(h, j - 1), h->chiL(j - 1), h->dims[j - 1], h->lamA, nullptr, false,
+                                     false, h->st);
+            }
+            h->centre = j;
+            move_left(h, j, true, drop);            // site j <- W, site j-1 <- site j-1 . (V L)
+            upload_lam(h, cur, h->lamB);            // Gamma_j = W / lambda_j
+            launch_scale_site<T>(site(h, j), h->dims[j - 1], h->chiR(j), nullptr, h->lamB, false, true, h->st);
+            lam[j - 1] = h->last_lam[j - 1];
+            cur = lam[j - 1];
+        }
+        // site 0 ends as Gamma_0 lambda_0 (the last move multiplied it by V L):
+        // Gamma_0 = site 0 / lambda_0; for s = 0 it holds U lambda', Gamma_0 = U
+        upload_lam(h, s == 0 ? lp : lam[0], h->lamB);
+        launch_scale_site<T>(site(h, 0), 1, h->dims[0], nullptr, h->lamB, false, true, h->st);
+        // right sweep (B_->): bonds s+1 .. n-2
+        cur = lp;
+        for (int j = s + 1; j <= n - 2; ++j) {
+            if (j + 1 <= n - 2) {   // site j+1 <- Gamma_{j+1} lambda_{j+1}
+                upload_lam(h, lam[j + 1], h->lamA);
+                launch_scale_site<T>(site(h, j + 1), h->dims[j], h->chiR(j + 1), nullptr, h->lamA, false, false,
+                                     h->st);
+            }
+            h->centre = j;
+            move_right(h, j, true, drop);           // site j <- Q, site j+1 <- (L W) . site j+1
+            upload_lam(h, cur, h->lamB);            // Gamma_j = Q / lambda_{j-1}
+            launch_scale_site<T>(site(h, j), h->dims[j - 1], h->dims[j], h->lamB, nullptr, true, false, h->st);
+            lam[j] = h->last_lam[j];
+            cur = lam[j];
+        }
+        // site n-1 ends as lambda_{n-2} Gamma_{n-1} (the last move multiplied it
+        // by L W): Gamma_{n-1} = site n-1 / lambda_{n-2}; for s + 1 = n - 1 it
+        // holds lambda' V^H, Gamma_{n-1} = V^H
+        upload_lam(h, s + 1 == n - 1 ? lp : lam[n - 2], h->lamB);
+        launch_scale_site<T>(site(h, n - 1), h->dims[n - 2], 1, h->lamB, nullptr, true, false, h->st);
+        HIPCHK(hipGetLastError());
+        return inf.discarded;
+    }
+
+    static double entropy_of(const std::vector<double>& l) {
+        double tot = 0.0, S = 0.0;
+        for (double v : l) tot += v * v;
+        if (tot <= 0.0) return 0.0;
+        for (double v : l) {
+            const double w = v * v / tot;
+            if (w > 0.0) S -= w * std::log2(w);
+        }
+        return S;
+    }
+
+    static void run_vidal(mpo_handle* h, int depth, const double* superops, int n_gates, int chi_max,
+                          double cutoff, double* S_out, double* discarded_out) {
+        const int n = h->n;
+        constexpr double drop = 1e-14;
+        init_product(h, nullptr);                    // Gamma = |0><0| site vectors, lambda = (1)
+        std::vector<std::vector<double>> lam(n - 1, std::vector<double>(1, 1.0));
+        int g = 0, resident0 = 0, resident = 0;
+        for (int t = 0; t < depth; ++t) {
+            for (int s = (t % 2 == 0) ? 0 : 1; s + 1 < n; s += 2, ++g) {
+                if (g >= resident0 + resident) {
+                    resident0 = g;
+                    resident = std::min(kMaxSuper, n_gates - g);
+                    HIPCHK(hipStreamSynchronize(h->st));
+                    upload_super(h, superops + (size_t)g * 512, resident);
+                }
+                const double d = vidal_gate(h, s, (const C*)h->Mdev + (size_t)(g - resident0) * 256, chi_max,
+                                            cutoff, drop, lam);
+                if (discarded_out) discarded_out[g] = d;
+            }
+            if (S_out)
+                for (int b = 0; b < n - 1; ++b) S_out[(size_t)t * (n - 1) + b] = entropy_of(lam[b]);
+        }
+        // back to the mixed canonical form: A_s = lambda_{s-1} Gamma_s (left
+        // isometries), the centre at n-1
+        for (int s = 1; s < n; ++s) {
+            upload_lam(h, lam[s - 1], h->lamA);
+            launch_scale_site<T>(site(h, s), h->chiL(s), h->chiR(s), h->lamA, nullptr, false, false, h->st);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(h->st));
+        h->centre = n - 1;
     }
 
     static void upload_super(mpo_handle* h, const double* superops, int count) {
@@ -912,7 +1067,8 @@ struct Adjoint {
                 const int ca = mu->chiL(s), cb = mu->dims[s], cc = mu->chiR(s + 1);
                 if (ca != tp.cen_l[j]) throw HipError{hipErrorInvalidValue, "adjoint bond mismatch"};
                 // theta_lambda and Theta = theta_rho contracted with the right environment
-                launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1), Id, THL, nullptr, h->st, h->bf3);
+                launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1), Id, THL, nullptr, 4 * ca,
+                                        h->st, h->bf3);
                 const int rs = tp.cen_r[j], rr = pre_r(s + 1);
                 launch_cgemm<T>(0, 0, 4 * rs, cc, rr, tp.pre[s + 1], 4 * rs, Sa, rr, T1, 4 * rs, h->st, h->bf3);
                 launch_cgemm<T>(0, 0, 4 * ca, 4 * cc, rs, tp.cen[j], 4 * ca, T1, rs, TH, 4 * ca, h->st, h->bf3);
@@ -927,19 +1083,22 @@ struct Adjoint {
                 if (m <= L.chi_mu) {
                     const int sl = mu->take_spare();
                     launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1),
-                                            MH + (size_t)g * 256, (C*)mu->slot[sl], nullptr, h->st, h->bf3);
+                                            MH + (size_t)g * 256, (C*)mu->slot[sl], nullptr, m, h->st, h->bf3);
                     launch_identity_site<T>(E::site(mu, s), ca, h->st);
                     mu->give_spare(mu->site_slot[s + 1]);
                     mu->site_slot[s + 1] = sl;
                     r = m;
                 } else {
                     launch_theta_channel<T>(ca, cb, cc, E::site(mu, s), E::site(mu, s + 1),
-                                            MH + (size_t)g * 256, (C*)mu->X, (C*)mu->X2, h->st, h->bf3);
+                                            MH + (size_t)g * 256, (C*)mu->X, (C*)mu->X2, work_ld(m), h->st,
+                                            h->bf3);
                     HIPCHK(hipGetLastError());
                     DevInfo inf = E::split(mu, m, N, L.chi_mu, regauge_cut(mu));
                     r = inf.kept;
-                    launch_gather_cols<T>((C*)mu->X, m, mu->jw.colmap, mu->jw.sig2, r, E::site(mu, s), m, h->st);
-                    launch_cgemm<T>(1, 0, r, N, m, E::site(mu, s), m, (C*)mu->X2, m, E::site(mu, s + 1), r, h->st, h->bf3);
+                    launch_gather_cols<T>((C*)mu->X, m, work_ld(m), mu->jw.colmap, mu->jw.sig2, r, E::site(mu, s), m,
+                                          h->st);
+                    launch_cgemm<T>(1, 0, r, N, m, E::site(mu, s), m, (C*)mu->X2, work_ld(m), E::site(mu, s + 1), r,
+                                    h->st, h->bf3);
                 }
                 co_max = std::max(co_max, r);
                 mu->dims[s] = r;
@@ -1055,6 +1214,27 @@ size_t carve_obs_scratch(char* base, int n, int cap, ObsScratch* w) {
 
 void mpo_internal_set_error(const char* msg) { g_err = msg ? msg : ""; }
 
+// ------------------------------------------------------------ tuning table
+// Jacobi block width and inner sweeps per precision and bond cap, filled by
+// the autotuner (mpo_set_default_tuning); a handle picks the first entry of
+// its precision whose chi_upto covers its chi_cap, else the built-in default.
+namespace {
+struct TuneEntry { int prec, chi_upto, block, inner; };
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+}  // namespace
+
+void tuned_jacobi(mpo_precision prec, int chi_cap, int* block, int* inner) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const TuneEntry* best = nullptr;
+    for (const TuneEntry& e : g_tune)
+        if (e.prec == (int)prec && e.chi_upto >= chi_cap && (!best || e.chi_upto < best->chi_upto)) best = &e;
+    if (best) {
+        *block = best->block;
+        *inner = best->inner;
+    }
+}
+
 // ==================================================================== C ABI
 extern "C" {
 
@@ -1108,6 +1288,8 @@ mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis, v
     h->jw.nrm2 = (double*)p; p += L.vecN_bytes;
     h->jw.sig2 = (double*)p; p += L.vecN_bytes;
     h->jw.colmap = (int*)p; p += L.vecN_bytes;
+    h->lamA = (double*)p; p += align256((size_t)chi_cap * sizeof(double));
+    h->lamB = (double*)p; p += align256((size_t)chi_cap * sizeof(double));
     h->jw.info = (DevInfo*)p; p += L.info_bytes;
     h->jw.max_pairs = L.max_pairs;
     h->jw.splits = kSplitsMax;
@@ -1117,9 +1299,12 @@ mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis, v
     // one inner sweep per block pair is the faster setting wherever the outer
     // tolerance is loose (FP32, BF16x3); FP64 gains nothing from it
     h->jw.inner = prec == MPO_FP64 ? 2 : 1;
+    tuned_jacobi(prec, chi_cap, &h->jw.block, &h->jw.inner);
     if (const char* e = std::getenv("MPO_JACOBI_BLOCK")) h->jw.block = std::atoi(e) == 16 ? 16 : 32;
     if (const char* e = std::getenv("MPO_JACOBI_INNER")) h->jw.inner = std::max(1, std::min(8, std::atoi(e)));
     h->jw.trace = std::getenv("MPO_JACOBI_TRACE") != nullptr;
+    h->jw.graphs = false;
+    h->jw.graph_cache = jacobi_graph_cache_new();
     h->envL = (double2*)p; p += L.env_bytes;
     h->envR = (double2*)p; p += L.env_bytes;
     h->tscr = (double2*)p; p += L.tscr_bytes;
@@ -1151,6 +1336,7 @@ void mpo_destroy(mpo_handle* h) {
     if (h->super_stage) (void)hipHostFree(h->super_stage);
     if (h->small_host) (void)hipHostFree(h->small_host);
     if (h->sig_host) (void)hipHostFree(h->sig_host);
+    jacobi_graph_cache_free(h->jw.graph_cache);
     delete h;
 }
 
@@ -1350,6 +1536,53 @@ mpo_status run_brickwork(mpo_handle* h, int depth, const double* superops, int n
             }
         });
     });
+}
+
+mpo_status mpo_set_tuning(mpo_handle* h, int block, int inner) {
+    if (!h) return fail(MPO_ERR_ARG, "null handle");
+    if ((block != 16 && block != 32) || inner < 1 || inner > 8)
+        return fail(MPO_ERR_ARG, "block must be 16 or 32 and inner in [1, 8] (got %d, %d)", block, inner);
+    h->jw.block = block;
+    h->jw.inner = inner;
+    return MPO_OK;
+}
+
+mpo_status mpo_set_default_tuning(mpo_precision prec, int chi_upto, int block, int inner) {
+    if (prec != MPO_FP64 && prec != MPO_FP32_MFMA && prec != MPO_BF16X3)
+        return fail(MPO_ERR_ARG, "unknown precision %d", (int)prec);
+    if (chi_upto < 1 || (block != 16 && block != 32) || inner < 1 || inner > 8)
+        return fail(MPO_ERR_ARG, "bad tuning entry (chi_upto %d, block %d, inner %d)", chi_upto, block, inner);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (TuneEntry& e : g_tune)
+        if (e.prec == (int)prec && e.chi_upto == chi_upto) { e.block = block; e.inner = inner; return MPO_OK; }
+    g_tune.push_back({(int)prec, chi_upto, block, inner});
+    return MPO_OK;
+}
+
+mpo_status mpo_set_graphs(mpo_handle* h, int on) {
+    if (!h) return fail(MPO_ERR_ARG, "null handle");
+    if (on && !h->st) return fail(MPO_ERR_ARG, "captured sweeps need a non-null stream");
+    h->jw.graphs = on != 0;
+    return MPO_OK;
+}
+
+mpo_status mpo_run_brickwork_vidal(mpo_handle* h, int depth, const double* superops, int n_gates, int chi_max,
+                                   double cutoff, double* S_out, double* discarded_out) {
+    if (!h) return fail(MPO_ERR_ARG, "null handle");
+    const int n = h->n;
+    if (depth < 0) return fail(MPO_ERR_ARG, "depth must be >= 0");
+    const long expect = (long)((depth + 1) / 2) * (n / 2) + (long)(depth / 2) * (n / 2 - 1);
+    if (n_gates != expect)
+        return fail(MPO_ERR_ARG, "n_gates = %d but a depth-%d brickwork on %d qubits has %ld", n_gates, depth, n, expect);
+    if (n_gates > 0 && !superops) return fail(MPO_ERR_ARG, "superops is NULL");
+    if (chi_max < 1 || chi_max > h->chi_cap) return fail(MPO_ERR_ARG, "chi_max %d out of [1, %d]", chi_max, h->chi_cap);
+    if (!(cutoff >= 0.0) || !std::isfinite(cutoff)) return fail(MPO_ERR_ARG, "cutoff must be finite and >= 0");
+    if (!finite_all(superops, (size_t)n_gates * 512)) return fail(MPO_ERR_ARG, "non-finite superoperator entry");
+    mpo_status st = guarded(h, [&] {
+        DISPATCH(h, E::run_vidal(h, depth, superops, n_gates, chi_max, cutoff, S_out, discarded_out));
+    });
+    if (st == MPO_OK) h->poisoned = false;
+    return st;
 }
 
 mpo_status mpo_profile_enable(mpo_handle* h, int on) {

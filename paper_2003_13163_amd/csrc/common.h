@@ -121,6 +121,9 @@ struct DevInfo {
     int rotations;         // pairs rotated in the sweep
     int inner_steps;       // inner Jacobi steps executed in the sweep (all pairs)
     int scale_exp;         // X is held scaled by 2^scale_exp during the sweeps (FP32 storage)
+    int done;              // set on the device once the sweeps converged (1) or hit the limit (2)
+    int sweeps;            // sweeps run in this decomposition
+    long long rot_total;   // rotated pairs summed over its sweeps
 };
 
 }  // namespace mpo
@@ -133,11 +136,12 @@ template <typename T>
 void launch_cgemm(int opa, int opb, int M, int N, int K, const C2<T>* A, int lda,
                   const C2<T>* B, int ldb, C2<T>* C, int ldc, hipStream_t st, bool bf3 = false);
 
-// X[(a + chiL*I) + m*(J + 4c)] = sum M[4I+J][4I'+J'] * theta[(I',a),(J',c)],
-// theta = L(As) * R(Bs); also written to X2 when non-null.
+// X[(a + chiL*I) + ldx*(J + 4c)] = sum M[4I+J][4I'+J'] * theta[(I',a),(J',c)],
+// theta = L(As) * R(Bs), ldx >= 4 chiL; also written to X2 (same stride) when non-null.
 template <typename T>
 void launch_theta_channel(int chiL, int chiM, int chiR, const C2<T>* As, const C2<T>* Bs,
-                          const C2<T>* Mdev, C2<T>* X, C2<T>* X2, hipStream_t st, bool bf3 = false);
+                          const C2<T>* Mdev, C2<T>* X, C2<T>* X2, int ldx, hipStream_t st,
+                          bool bf3 = false);
 
 struct JacobiWork {
     void* gram_partials;   // P_max * splits * 64*64 complex (T)
@@ -155,24 +159,30 @@ struct JacobiWork {
     int inner;             // inner FP64 sweeps per block pair
     bool bf3;              // Gram as split-BF16x3 products (FP32 storage)
     bool trace;            // print each sweep's convergence to stderr
+    bool graphs;           // replay captured sweeps (hipGraph) speculatively, one read per batch
+    void* graph_cache;     // captured sweep per shape (owned by the handle)
     long long n_splits, n_sweeps, n_rounds, n_rotations;   // running counters
 };
 
-// One-sided block Jacobi on the columns of X (m x N, ld = m).  On return
+// One-sided block Jacobi on the columns of X (m x N, column stride ld >= m).  On return
 // work.colmap[0..N) lists columns by decreasing norm and work.sig2 holds the
 // sorted squared norms.  Returns the number of sweeps, or -1 if the sweep
 // limit was reached, -2 on a HIP error.
 template <typename T>
-int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps,
+int jacobi_orthogonalize(C2<T>* X, int m, int N, int ld, double tol, int max_sweeps,
                          JacobiWork& w, hipStream_t st);
+// Cache of captured sweeps (JacobiWork::graph_cache), created and freed by the handle.
+void* jacobi_graph_cache_new();
+void jacobi_graph_cache_free(void* cache);
 
 // Columns whose squared norm is at most this fraction of ||X||_F^2 are at the
 // rounding floor of the working precision: the sweep never rotates them and
 // the truncation never keeps them.  In FP32 storage the rounding of rotated
-// columns leaves noise near (2^-24 sqrt(#rotations))^2 ~ 4e-12 of ||X||_F^2,
-// and the gates' own FP32 rounding accumulates above that; both FP32-storage
-// modes use 1e-9.
-template <typename T> constexpr double jacobi_zero_rel2() { return sizeof(T) == 8 ? 1e-30 : 1e-9; }
+// columns leaves noise near (2^-24 sqrt(#rotations))^2 ~ 4e-12 of ||X||_F^2;
+// both FP32-storage modes use 1e-11, just above it.  (A floor of 1e-9 was 7%
+// faster but dropped real Schmidt values of amplitude up to 3e-5 at every
+// re-gauge: <Z_i> on an exact 8-qubit circuit moved by 3.7e-5 against 1.1e-5.)
+template <typename T> constexpr double jacobi_zero_rel2() { return sizeof(T) == 8 ? 1e-30 : 1e-11; }
 constexpr double kZeroRel2Bf3 = jacobi_zero_rel2<float>();   // split-BF16x3 uses the same floor
 // Relative orthogonality the FP32-storage sweeps reach with an FP32-MFMA Gram.
 // In split-BF16x3 mode the sweeps with the BF16x3 Gram stop at the looser
@@ -186,17 +196,23 @@ constexpr double kBf3Handoff = 3e-3;
 void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,
                      DevInfo* info, hipStream_t st);
 
-// dst[i + ldd*b] = X[i + m*colmap[b]] / sqrt(sig2[b]) for b < k  (left factor)
+// dst[i + ldd*b] = X[i + ldx*colmap[b]] / sqrt(sig2[b]) for b < k, i < m  (left factor;
+// without normalize the columns are copied as they are: U Sigma)
 template <typename T>
-void launch_gather_cols(const C2<T>* X, int m, const int* colmap, const double* sig2, int k,
-                        C2<T>* dst, int ldd, hipStream_t st);
-// dst[b + k*i] = conj(X[i + m*colmap[b]]) / sqrt(sig2[b]) for b < k  (right factor, rows)
+void launch_gather_cols(const C2<T>* X, int m, int ldx, const int* colmap, const double* sig2, int k,
+                        C2<T>* dst, int ldd, hipStream_t st, bool normalize = true);
+// dst[b + k*i] = conj(X[i + ldx*colmap[b]]) / sqrt(sig2[b]) for b < k, i < m  (right factor, rows)
 template <typename T>
-void launch_gather_rows_conj(const C2<T>* X, int m, const int* colmap, const double* sig2,
+void launch_gather_rows_conj(const C2<T>* X, int m, int ldx, const int* colmap, const double* sig2,
                              int k, C2<T>* dst, hipStream_t st);
-// Y[j + cols*i] = conj(A[i + rows*j])  (Y is cols x rows)
+// Y[j + ldy*i] = conj(A[i + lda*j])  (A rows x cols with stride lda >= rows, Y cols x rows
+// with stride ldy >= cols)
 template <typename T>
-void launch_conj_transpose(const C2<T>* A, int rows, int cols, C2<T>* Y, hipStream_t st);
+void launch_conj_transpose(const C2<T>* A, int rows, int cols, int lda, C2<T>* Y, int ldy,
+                           hipStream_t st);
+// dst[i + ldd*j] = src[i + lds*j] for i < rows, j < cols
+template <typename T>
+void launch_copy_cols(const C2<T>* src, int rows, int cols, int lds, C2<T>* dst, int ldd, hipStream_t st);
 template <typename T>
 void launch_copy(const C2<T>* src, C2<T>* dst, size_t count, hipStream_t st);
 
@@ -208,6 +224,10 @@ void launch_transfer_left(const C2<T>* A, int chiL, int chiR, const double2* env
 template <typename T>
 void launch_transfer_right(const C2<T>* A, int chiL, int chiR, const double2* env_in,
                            const double2* v, double2* env_out, double2* scratch, hipStream_t st);
+// A[a, I, c] *= fl(a) fr(c), fl = lamL[a] or 1/lamL[a] (invL), fr likewise; null = 1
+template <typename T>
+void launch_scale_site(C2<T>* A, int chiL, int chiR, const double* lamL, const double* lamR, bool invL,
+                       bool invR, hipStream_t st);
 // A[a, I, b] = [b == a + chiA*I]: the (chiA, 4, 4 chiA) identity site tensor
 template <typename T>
 void launch_identity_site(C2<T>* A, int chiA, hipStream_t st);

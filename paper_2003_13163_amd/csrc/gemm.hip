@@ -214,7 +214,8 @@ __global__ __launch_bounds__(256) void k_theta_channel(int chiL, int chiM, int c
                                                        const C2<T>* __restrict__ As_g,
                                                        const C2<T>* __restrict__ Bs_g,
                                                        const C2<T>* __restrict__ Mdev,
-                                                       C2<T>* __restrict__ X, C2<T>* __restrict__ X2) {
+                                                       C2<T>* __restrict__ X, C2<T>* __restrict__ X2,
+                                                       int ldx) {
     __shared__ C2<T> Ms[16][16];
     __shared__ C2<T> As[BK][BM + 1];
     __shared__ C2<T> Bs[BK][BN + 1];
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(256) void k_theta_channel(int chiL, int chiM, int c
                     re += mm.x * th[q].x - mm.y * th[q].y;
                     im += mm.x * th[q].y + mm.y * th[q].x;
                 }
-                const size_t off = (size_t)(a + chiL * I) + (size_t)m * (J + 4 * c);
+                const size_t off = (size_t)(a + chiL * I) + (size_t)ldx * (J + 4 * c);
                 X[off] = cmake<T>(re, im);
                 if (X2) X2[off] = cmake<T>(re, im);
             }
@@ -293,17 +294,17 @@ __global__ __launch_bounds__(256) void k_theta_channel(int chiL, int chiM, int c
 
 template <typename T>
 void launch_theta_channel(int chiL, int chiM, int chiR, const C2<T>* As, const C2<T>* Bs,
-                          const C2<T>* Mdev, C2<T>* X, C2<T>* X2, hipStream_t st, bool bf3) {
+                          const C2<T>* Mdev, C2<T>* X, C2<T>* X2, int ldx, hipStream_t st, bool bf3) {
     dim3 grid((chiL + 15) / 16, (chiR + 15) / 16);
     if constexpr (sizeof(T) == 4) {
         if (bf3) {
             hipLaunchKernelGGL((k_theta_channel<T, true>), grid, dim3(256), 0, st, chiL, chiM, chiR,
-                               As, Bs, Mdev, X, X2);
+                               As, Bs, Mdev, X, X2, ldx);
             return;
         }
     }
     hipLaunchKernelGGL((k_theta_channel<T, false>), grid, dim3(256), 0, st, chiL, chiM, chiR, As, Bs,
-                       Mdev, X, X2);
+                       Mdev, X, X2, ldx);
 }
 
 template void launch_cgemm<double>(int, int, int, int, int, const double2*, int, const double2*,
@@ -311,8 +312,8 @@ template void launch_cgemm<double>(int, int, int, int, int, const double2*, int,
 template void launch_cgemm<float>(int, int, int, int, int, const float2*, int, const float2*, int,
                                   float2*, int, hipStream_t, bool);
 template void launch_theta_channel<double>(int, int, int, const double2*, const double2*,
-                                           const double2*, double2*, double2*, hipStream_t, bool);
+                                           const double2*, double2*, double2*, int, hipStream_t, bool);
 template void launch_theta_channel<float>(int, int, int, const float2*, const float2*,
-                                          const float2*, float2*, float2*, hipStream_t, bool);
+                                          const float2*, float2*, float2*, int, hipStream_t, bool);
 
 }  // namespace mpo

@@ -15,7 +15,10 @@
 #include "common.h"
 #include <cstdio>
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <map>
+#include <tuple>
 
 namespace mpo {
 
@@ -31,12 +34,13 @@ __host__ __device__ __forceinline__ void pair_of(int round, int i, int nb, int& 
 
 // ------------------------------------------------------------- column norms
 template <typename T>
-__global__ __launch_bounds__(256) void k_colnorm2(const C2<T>* __restrict__ X, int m, int N,
-                                                  double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_colnorm2(const C2<T>* __restrict__ X, int m, int N, int ld,
+                                                  double* __restrict__ out, const int* __restrict__ halt) {
+    if (halt && *halt) return;
     const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (col >= N) return;
-    const C2<T>* x = X + (size_t)col * m;
+    const C2<T>* x = X + (size_t)col * ld;
     double s = 0.0;
     for (int i = lane; i < m; i += 64) {
         const double2 v = to_d2(x[i]);
@@ -51,7 +55,9 @@ __global__ __launch_bounds__(256) void k_colnorm2(const C2<T>* __restrict__ X, i
 __global__ __launch_bounds__(1024) void k_sort_desc(const double* __restrict__ nrm2, int N,
                                                     int* __restrict__ colmap,
                                                     double* __restrict__ sig2,
-                                                    double* __restrict__ fro2) {
+                                                    double* __restrict__ fro2,
+                                                    const int* __restrict__ halt) {
+    if (halt && *halt) return;
     __shared__ double key[4096];
     __shared__ int idx[4096];
     __shared__ double red[1024];
@@ -141,10 +147,12 @@ __device__ __forceinline__ void gram_finish(const d4* sumR, const d4* sumI, doub
 // each wave takes a quarter of every slab, 16 rows per step through
 // v_mfma_f32_16x16x16_bf16 with hi/lo operands.
 template <int JB>
-__global__ __launch_bounds__(256) void k_pair_gram_bf3(const float2* __restrict__ X, int m, int N,
+__global__ __launch_bounds__(256) void k_pair_gram_bf3(const float2* __restrict__ X, int m, int N, int ld,
                                                        const int* __restrict__ colmap, int nb,
                                                        int round, int splits, int chunk,
-                                                       double2* __restrict__ partials) {
+                                                       double2* __restrict__ partials,
+                                 const int* __restrict__ halt) {
+    if (*halt) return;
     using T = float;
     constexpr int NB = 2 * JB, TB = NB / 16, NU = TB * (TB + 1) / 2;
     constexpr int RB = 4096 / NB;              // rows per staged slab
@@ -176,7 +184,7 @@ __global__ __launch_bounds__(256) void k_pair_gram_bf3(const float2* __restrict_
     for (int r = 0; r < LE; ++r) {
         const int e = t + 256 * r;
         const int row = e % RB, c = cols[e / RB];
-        pre[r] = (c >= 0 && r0 + row < r1) ? X[(size_t)(r0 + row) + (size_t)m * c] : czero<T>();
+        pre[r] = (c >= 0 && r0 + row < r1) ? X[(size_t)(r0 + row) + (size_t)ld * c] : czero<T>();
     }
     for (int k0 = r0; k0 < r1; k0 += RB) {
 #pragma unroll
@@ -191,7 +199,7 @@ __global__ __launch_bounds__(256) void k_pair_gram_bf3(const float2* __restrict_
             for (int r = 0; r < LE; ++r) {
                 const int e = t + 256 * r;
                 const int row = e % RB, c = cols[e / RB];
-                pre[r] = (c >= 0 && k1 + row < r1) ? X[(size_t)(k1 + row) + (size_t)m * c] : czero<T>();
+                pre[r] = (c >= 0 && k1 + row < r1) ? X[(size_t)(k1 + row) + (size_t)ld * c] : czero<T>();
             }
         }
 #pragma unroll
@@ -254,10 +262,12 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 template <typename T, int JB>
-__global__ __launch_bounds__(256) void k_pair_gram_lds(const C2<T>* __restrict__ X, int m, int N,
+__global__ __launch_bounds__(256) void k_pair_gram_lds(const C2<T>* __restrict__ X, int m, int N, int ld,
                                                        const int* __restrict__ colmap, int nb,
                                                        int round, int splits, int chunk,
-                                                       double2* __restrict__ partials) {
+                                                       double2* __restrict__ partials,
+                                 const int* __restrict__ halt) {
+    if (*halt) return;
     constexpr int NB = 2 * JB, TB = NB / 16, NU = TB * (TB + 1) / 2;
     constexpr int E = 16 / (int)sizeof(C2<T>);   // rows per 16-byte unit
     constexpr int NS = 4;                         // MFMA k-steps per slab
@@ -281,11 +291,11 @@ __global__ __launch_bounds__(256) void k_pair_gram_lds(const C2<T>* __restrict__
         const int lj = c < JB ? p * JB + c : q * JB + (c - JB);
         const int col = lj < N ? colmap[lj] : -1;
         live[j] = col >= 0;
-        colp[j] = X + (size_t)m * (live[j] ? col : 0);
+        colp[j] = X + (size_t)ld * (live[j] ? col : 0);
     }
     const int r0 = split * chunk;
     const int r1 = min(m, r0 + chunk);
-    const bool aligned = (m % E) == 0;            // 16-byte loads need an even column length in FP32
+    const bool aligned = (ld % E) == 0;           // 16-byte loads need an even column stride in FP32
     auto load = [&](int j, int row) -> LV {
         if constexpr (E == 2) {
             if (live[j] && aligned && row + 1 < r1) return *reinterpret_cast<const float4*>(colp[j] + row);
@@ -373,10 +383,12 @@ __global__ __launch_bounds__(256) void k_pair_gram_lds(const C2<T>* __restrict__
 // but on gfx950 this measured faster for FP32, whose slab carries half the MFMA
 // work of an FP64 one; for FP64 the LDS kernel is faster.
 template <typename T, int JB>
-__global__ __launch_bounds__(256) void k_pair_gram_regs(const C2<T>* __restrict__ X, int m, int N,
+__global__ __launch_bounds__(256) void k_pair_gram_regs(const C2<T>* __restrict__ X, int m, int N, int ld,
                                                         const int* __restrict__ colmap, int nb,
                                                         int round, int splits, int chunk,
-                                                        double2* __restrict__ partials) {
+                                                        double2* __restrict__ partials,
+                                 const int* __restrict__ halt) {
+    if (*halt) return;
     constexpr int NB = 2 * JB, TB = NB / 16, NU = TB * (TB + 1) / 2;
     constexpr int E = 16 / (int)sizeof(C2<T>);
     constexpr int NS = 4;
@@ -396,11 +408,11 @@ __global__ __launch_bounds__(256) void k_pair_gram_regs(const C2<T>* __restrict_
         const int lj = c < JB ? p * JB + c : q * JB + (c - JB);
         const int col = lj < N ? colmap[lj] : -1;
         live[b] = col >= 0;
-        colp[b] = X + (size_t)m * (live[b] ? col : 0);
+        colp[b] = X + (size_t)ld * (live[b] ? col : 0);
     }
     const int r0 = split * chunk;
     const int r1 = min(m, r0 + chunk);
-    const bool aligned = (m % E) == 0;
+    const bool aligned = (ld % E) == 0;
     auto load = [&](int b, int row) -> LV {
         if constexpr (E == 2) {
             if (live[b] && aligned && row + 1 < r1) return *reinterpret_cast<const float4*>(colp[b] + row);
@@ -602,6 +614,7 @@ __global__ __launch_bounds__(kEigThreads) void k_pair_eig(const double2* __restr
                                                          const double* __restrict__ fro2,
                                                          int inner_max, C2<T>* __restrict__ Wout,
                                                          int* __restrict__ skip, DevInfo* info) {
+    if (info->done) return;
     constexpr int NT = kEigThreads, NB = 2 * JB, NP = JB, U = NP * NP / 256;   // blocks per thread
     static_assert(NP * NP % 256 == 0, "block count must fill four waves");
     // Row pitch NB + 2 for G: the pair entries G[s+P][s-P] of one step then
@@ -803,13 +816,14 @@ template <typename T> constexpr int update_slabs() { return sizeof(T) == 8 ? 4 :
 // here accumulates in the state, while Gram rounding only perturbs angles.
 
 template <typename T, int JB>
-__global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int m, int N,
+__global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int m, int N, int ld,
                                                      const int* __restrict__ colmap, int nb,
                                                      int round, const C2<T>* __restrict__ Wm,
-                                                     const int* __restrict__ skip) {
+                                                     const int* __restrict__ skip,
+                                                     const int* __restrict__ halt) {
     constexpr int NB = 2 * JB, MB = NB / 32;
     const int pair = blockIdx.x;
-    if (skip[pair]) return;
+    if (*halt || skip[pair]) return;
     __shared__ C2<T> Ws[NB][NB + 1];   // Ws[k][j] = W[k][j]
     __shared__ __align__(16) C2<T> Xt[NB][64 + 2];   // Xt[col][row], rows in 16-byte aligned pairs
     __shared__ int cols[NB];
@@ -830,10 +844,10 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
     constexpr int E = 16 / (int)sizeof(C2<T>), RU = 64 / E;   // rows per unit, units per column
     constexpr int LE = NB * RU / 256;
     using LV = typename GramLoad<T>::type;
-    const bool even = (m % E) == 0;
+    const bool even = (ld % E) == 0;
     auto gload = [&](int r0, int e) -> LV {
         const int row = (e % RU) * E, c = cols[e / RU];
-        const C2<T>* src = X + (size_t)m * (c >= 0 ? c : 0) + r0 + row;
+        const C2<T>* src = X + (size_t)ld * (c >= 0 ? c : 0) + r0 + row;
         if constexpr (E == 2) {
             if (c >= 0 && even && r0 + row + 1 < m) return *reinterpret_cast<const float4*>(src);
             const float2 a = (c >= 0 && r0 + row < m) ? src[0] : make_float2(0.f, 0.f);
@@ -906,7 +920,7 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
             const int row = (e % RU) * E, col = e / RU;
             const int c = cols[col];
             if (c < 0 || r0 + row >= m) continue;
-            C2<T>* dst = X + (size_t)m * c + r0 + row;
+            C2<T>* dst = X + (size_t)ld * c + r0 + row;
             if (E == 1 || (even && r0 + row + E - 1 < m)) {
                 *reinterpret_cast<LV*>(dst) = *reinterpret_cast<const LV*>(&Xt[col][row]);
             } else {
@@ -1004,17 +1018,19 @@ __global__ __launch_bounds__(256) void k_truncate(const double* __restrict__ sig
 
 // ------------------------------------------------------------------ gathers
 template <typename T>
-__global__ void k_gather_cols(const C2<T>* __restrict__ X, int m, const int* __restrict__ colmap,
+__global__ void k_gather_cols(const C2<T>* __restrict__ X, int m, int ld, const int* __restrict__ colmap,
                               const double* __restrict__ sig2, int k, C2<T>* __restrict__ dst,
-                              int ldd) {
+                              int ldd, int normalize) {
     const int b = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= k || i >= m) return;
     const double s2 = sig2[b];
     C2<T> v;
-    if (s2 > 0.0) {
+    if (!normalize) {
+        v = X[(size_t)i + (size_t)ld * colmap[b]];
+    } else if (s2 > 0.0) {
         const double inv = 1.0 / sqrt(s2);
-        const double2 x = to_d2(X[(size_t)i + (size_t)m * colmap[b]]);
+        const double2 x = to_d2(X[(size_t)i + (size_t)ld * colmap[b]]);
         v = cmake<T>(T(x.x * inv), T(x.y * inv));
     } else {
         v = cmake<T>(T(i == b ? 1 : 0), T(0));
@@ -1023,7 +1039,7 @@ __global__ void k_gather_cols(const C2<T>* __restrict__ X, int m, const int* __r
 }
 
 template <typename T>
-__global__ void k_gather_rows_conj(const C2<T>* __restrict__ X, int m,
+__global__ void k_gather_rows_conj(const C2<T>* __restrict__ X, int m, int ld,
                                    const int* __restrict__ colmap,
                                    const double* __restrict__ sig2, int k,
                                    C2<T>* __restrict__ dst) {
@@ -1037,7 +1053,7 @@ __global__ void k_gather_rows_conj(const C2<T>* __restrict__ X, int m,
             const double s2 = sig2[b];
             if (s2 > 0.0) {
                 const double inv = 1.0 / sqrt(s2);
-                const double2 x = to_d2(X[(size_t)i + (size_t)m * colmap[b]]);
+                const double2 x = to_d2(X[(size_t)i + (size_t)ld * colmap[b]]);
                 v = cmake<T>(T(x.x * inv), T(-x.y * inv));
             } else {
                 v = cmake<T>(T(i == b ? 1 : 0), T(0));
@@ -1053,20 +1069,28 @@ __global__ void k_gather_rows_conj(const C2<T>* __restrict__ X, int m,
 }
 
 template <typename T>
-__global__ void k_conj_transpose(const C2<T>* __restrict__ A, int rows, int cols,
-                                 C2<T>* __restrict__ Y) {
+__global__ void k_conj_transpose(const C2<T>* __restrict__ A, int rows, int cols, int lda,
+                                 C2<T>* __restrict__ Y, int ldy) {
     __shared__ C2<T> tile[32][33];
     const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int i = r0 + tx, j = c0 + r;
-        if (i < rows && j < cols) tile[r][tx] = cconj<T>(A[(size_t)i + (size_t)rows * j]);
+        if (i < rows && j < cols) tile[r][tx] = cconj<T>(A[(size_t)i + (size_t)lda * j]);
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int j = c0 + tx, i = r0 + r;
-        if (i < rows && j < cols) Y[(size_t)j + (size_t)cols * i] = tile[tx][r];
+        if (i < rows && j < cols) Y[(size_t)j + (size_t)ldy * i] = tile[tx][r];
     }
+}
+
+// dst[i + ldd * j] = src[i + lds * j] for a rows x cols block
+template <typename T>
+__global__ void k_copy_cols(const C2<T>* __restrict__ src, int rows, int lds, C2<T>* __restrict__ dst,
+                            int ldd) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i < rows) dst[(size_t)i + (size_t)ldd * j] = src[(size_t)i + (size_t)lds * j];
 }
 
 template <typename T>
@@ -1113,10 +1137,55 @@ __global__ __launch_bounds__(256) void k_scale_apply(C2<T>* __restrict__ X, size
             sig2[i] = ldexp(sig2[i], 2 * k);
 }
 
+// Start of a sweep: clear the sweep's measures (no memset node, so that a
+// captured sweep replays correctly).  End of a sweep: the convergence test on
+// the device, so that sweeps can be queued ahead of the host's read.
+__global__ void k_sweep_begin(DevInfo* info) {
+    if (threadIdx.x != 0 || info->done) return;
+    info->offmax_bits = 0ull;
+    info->rotations = 0;
+    info->inner_steps = 0;
+}
+
+__global__ void k_sweep_end(DevInfo* info, double stop_off, int max_sweeps) {
+    if (threadIdx.x != 0 || info->done) return;
+    const double off = __longlong_as_double((long long)info->offmax_bits);
+    info->sweeps += 1;
+    info->rot_total += info->rotations;
+    if (info->rotations == 0 || off <= stop_off) info->done = 1;
+    else if (info->sweeps >= max_sweeps) info->done = 2;
+}
+
+__global__ void k_jacobi_reset(DevInfo* info) {
+    if (threadIdx.x != 0) return;
+    info->done = 0;
+    info->sweeps = 0;
+    info->rot_total = 0;
+}
+
 // ------------------------------------------------------------------- host side
+// Captured sweeps, one per shape, owned by the handle.
+struct SweepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+using GraphKey = std::tuple<int, int, int, int, int, int, long, long>;
+using GraphCache = std::map<GraphKey, SweepGraph>;
+
+void* jacobi_graph_cache_new() { return new GraphCache(); }
+void jacobi_graph_cache_free(void* cache) {
+    GraphCache* c = (GraphCache*)cache;
+    if (!c) return;
+    for (auto& kv : *c) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    delete c;
+}
+
 template <typename T, int JB, bool BF>
-static int jacobi_run(C2<T>* X, int m, int N, double tol, double stop_off, double zrel2, int max_sweeps,
-                      int inner_max, JacobiWork& w, hipStream_t st) {
+static int jacobi_run(C2<T>* X, int m, int N, int ld, double tol, double stop_off, double zrel2,
+                      int max_sweeps, int inner_max, JacobiWork& w, hipStream_t st) {
     constexpr int NB = 2 * JB;
     int nb = (N + JB - 1) / JB;
     if (nb < 2) nb = 2;
@@ -1131,6 +1200,7 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, double stop_off, doubl
     splits = (m + chunk - 1) / chunk;
     if (splits < 1) splits = 1;
     double* fro2 = &w.info->total;   // scratch slot reused for ||X||_F^2
+    const int* halt = &w.info->done;
     const dim3 gnorm((N + 3) / 4);
     Profiler& pf = *w.prof;
     const double csz = 2.0 * sizeof(T);
@@ -1142,87 +1212,145 @@ static int jacobi_run(C2<T>* X, int m, int N, double tol, double stop_off, doubl
     const double pair_bytes = (double)m * NB * csz;
     // FP32 storage: X is held scaled by a power of two during the sweeps
     constexpr bool scaled = sizeof(T) == 4;
-    const dim3 gscale((unsigned)std::min<size_t>(2048, ((size_t)m * N + 255) / 256));
+    const dim3 gscale((unsigned)std::min<size_t>(2048, ((size_t)ld * N + 255) / 256));
     auto unscale = [&](bool with_values) {
         if (!scaled) return;
-        hipLaunchKernelGGL((k_scale_apply<T>), gscale, dim3(256), 0, st, X, (size_t)m * N,
+        hipLaunchKernelGGL((k_scale_apply<T>), gscale, dim3(256), 0, st, X, (size_t)ld * N,
                            (const DevInfo*)w.info, with_values ? w.sig2 : (double*)nullptr, N, 1);
         hipLaunchKernelGGL(k_scale_exp, dim3(1), dim3(64), 0, st, w.info, fro2, 1);
     };
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        pf.begin(st);
-        hipLaunchKernelGGL((k_colnorm2<T>), gnorm, dim3(256), 0, st, X, m, N, w.nrm2);
-        hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, w.nrm2, N, w.colmap, w.sig2, fro2);
-        if (scaled && sweep == 0) {
-            hipLaunchKernelGGL(k_scale_exp, dim3(1), dim3(64), 0, st, w.info, fro2, 0);
-            hipLaunchKernelGGL((k_scale_apply<T>), gscale, dim3(256), 0, st, X, (size_t)m * N,
-                               (const DevInfo*)w.info, (double*)nullptr, N, 0);
-        }
-        pf.end(st, K_NORMSORT, 8.0 * m * N, (double)m * N * csz);
-        (void)hipMemsetAsync(&w.info->offmax_bits, 0, sizeof(unsigned long long) + 2 * sizeof(int), st);
+    // One sweep: norm sort, then nb-1 rounds of (pair Gram, pair eigen-solver,
+    // pair update), then the convergence test on the device.  Every launch
+    // returns at once when an earlier sweep already converged, so sweeps may be
+    // queued ahead of the host's read.  Per-launch events (profiling) are
+    // recorded only when the sweep is not being captured.
+    auto enqueue_sweep = [&](bool events, int sweep_limit) {
+        if (events) pf.begin(st);
+        hipLaunchKernelGGL((k_colnorm2<T>), gnorm, dim3(256), 0, st, X, m, N, ld, w.nrm2, halt);
+        hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, w.nrm2, N, w.colmap, w.sig2, fro2, halt);
+        if (events) pf.end(st, K_NORMSORT, 8.0 * m * N, (double)m * N * csz);
+        hipLaunchKernelGGL(k_sweep_begin, dim3(1), dim3(64), 0, st, w.info);
         for (int r = 0; r < nb - 1; ++r) {
-            hipEvent_t a, b;
-            pf.stamps(a, b);
+            hipEvent_t a = nullptr, b = nullptr;
+            // timed launches carry start/stop events; plain ones can be captured
+#define MPO_LAUNCH(K, G, B, ...)                                                      \
+    do {                                                                              \
+        if (events) hipExtLaunchKernelGGL(K, G, B, 0, st, a, b, 0, __VA_ARGS__);      \
+        else hipLaunchKernelGGL(K, G, B, 0, st, __VA_ARGS__);                         \
+    } while (0)
+            if (events) pf.stamps(a, b);
             if constexpr (BF)
-                hipExtLaunchKernelGGL((k_pair_gram_bf3<JB>), dim3(P, splits), dim3(256), 0, st, a, b, 0,
-                                      X, m, N, (const int*)w.colmap, nb, r, splits, chunk,
-                                      (double2*)w.gram_partials);
+                MPO_LAUNCH((k_pair_gram_bf3<JB>), dim3(P, splits), dim3(256), X, m, N, ld,
+                           (const int*)w.colmap, nb, r, splits, chunk, (double2*)w.gram_partials, halt);
             else if constexpr (sizeof(T) == 4)
-                hipExtLaunchKernelGGL((k_pair_gram_regs<T, JB>), dim3(P, splits), dim3(256), 0, st, a,
-                                      b, 0, X, m, N, (const int*)w.colmap, nb, r, splits, chunk,
-                                      (double2*)w.gram_partials);
+                MPO_LAUNCH((k_pair_gram_regs<T, JB>), dim3(P, splits), dim3(256), X, m, N, ld,
+                           (const int*)w.colmap, nb, r, splits, chunk, (double2*)w.gram_partials, halt);
             else
-                hipExtLaunchKernelGGL((k_pair_gram_lds<T, JB>), dim3(P, splits), dim3(256), 0, st, a,
-                                      b, 0, X, m, N, (const int*)w.colmap, nb, r, splits, chunk,
-                                      (double2*)w.gram_partials);
-            pf.record(K_GRAM, a, b, P * gram_flops, P * pair_bytes + (double)P * splits * NB * NB * 16.0);
-            pf.stamps(a, b);
-            hipExtLaunchKernelGGL((k_pair_eig<T, JB>), dim3(P), dim3(kEigThreads), 0, st, a, b, 0,
-                                  (const double2*)w.gram_partials, splits, tol, zrel2,
-                                  (const double*)fro2, inner_max, (C2<T>*)w.w, w.skip, w.info);
-            pf.record(K_EIG, a, b, 0.0, (double)P * splits * NB * NB * 16.0);
+                MPO_LAUNCH((k_pair_gram_lds<T, JB>), dim3(P, splits), dim3(256), X, m, N, ld,
+                           (const int*)w.colmap, nb, r, splits, chunk, (double2*)w.gram_partials, halt);
+            if (events) pf.record(K_GRAM, a, b, P * gram_flops, P * pair_bytes + (double)P * splits * NB * NB * 16.0);
+            if (events) pf.stamps(a, b);
+            MPO_LAUNCH((k_pair_eig<T, JB>), dim3(P), dim3(kEigThreads), (const double2*)w.gram_partials,
+                       splits, tol, zrel2, (const double*)fro2, inner_max, (C2<T>*)w.w, w.skip, w.info);
+            if (events) pf.record(K_EIG, a, b, 0.0, (double)P * splits * NB * NB * 16.0);
             constexpr int US = update_slabs<T>();
-            pf.stamps(a, b);
-            hipExtLaunchKernelGGL((k_pair_update<T, JB>), dim3(P, (m + 64 * US - 1) / (64 * US)), dim3(256),
-                                  0, st, a, b, 0, X, m, N, (const int*)w.colmap, nb, r,
-                                  (const C2<T>*)w.w, (const int*)w.skip);
-            pf.record(K_UPDATE, a, b, 0.0, 0.0);
+            if (events) pf.stamps(a, b);
+            MPO_LAUNCH((k_pair_update<T, JB>), dim3(P, (m + 64 * US - 1) / (64 * US)), dim3(256), X, m, N,
+                       ld, (const int*)w.colmap, nb, r, (const C2<T>*)w.w, (const int*)w.skip, halt);
+            if (events) pf.record(K_UPDATE, a, b, 0.0, 0.0);
+#undef MPO_LAUNCH
         }
-        w.n_rounds += nb - 1;
-        w.n_sweeps += 1;
+        hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(64), 0, st, w.info, stop_off, sweep_limit);
+    };
+    auto read_info = [&]() -> bool {
         if (hipMemcpyAsync(w.info_host, w.info, sizeof(DevInfo), hipMemcpyDeviceToHost, st) != hipSuccess)
-            return -2;
-        if (hipStreamSynchronize(st) != hipSuccess) return -2;
-        const unsigned long long bits = w.info_host->offmax_bits;
-        double off;
-        std::memcpy(&off, &bits, sizeof(off));
-        const int rot = w.info_host->rotations;
-        w.n_rotations += rot;
-        if (w.trace)
-            std::fprintf(stderr, "jacobi %dx%d sweep %d: max rel off-diagonal %.3e, %d of %d pairs x %d rounds rotated\n",
-                         m, N, sweep, off, rot, P, nb - 1);
-        pf.add_work(K_UPDATE, rot * pair_flops, rot * 2.0 * pair_bytes);
-        // each inner step applies a two-sided 2x2 transform to all NB^2 entries of G
-        // (22 real flops per entry) and a column rotation to W (11 per entry)
-        pf.add_work(K_EIG, 33.0 * NB * NB * (double)w.info_host->inner_steps, 0.0);
-        if (rot == 0 || off <= stop_off) {
-            pf.begin(st);
-            hipLaunchKernelGGL((k_colnorm2<T>), gnorm, dim3(256), 0, st, X, m, N, w.nrm2);
-            hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, w.nrm2, N, w.colmap, w.sig2, fro2);
-            unscale(true);
-            pf.end(st, K_NORMSORT, 8.0 * m * N, (double)m * N * csz);
-            return sweep + 1;
+            return false;
+        return hipStreamSynchronize(st) == hipSuccess;
+    };
+    // norms, order and (FP32 storage) the power-of-two scale before the first sweep
+    hipLaunchKernelGGL(k_jacobi_reset, dim3(1), dim3(64), 0, st, w.info);
+    pf.begin(st);
+    hipLaunchKernelGGL((k_colnorm2<T>), gnorm, dim3(256), 0, st, X, m, N, ld, w.nrm2, (const int*)nullptr);
+    hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, w.nrm2, N, w.colmap, w.sig2, fro2,
+                       (const int*)nullptr);
+    if (scaled) {
+        hipLaunchKernelGGL(k_scale_exp, dim3(1), dim3(64), 0, st, w.info, fro2, 0);
+        hipLaunchKernelGGL((k_scale_apply<T>), gscale, dim3(256), 0, st, X, (size_t)ld * N,
+                           (const DevInfo*)w.info, (double*)nullptr, N, 0);
+    }
+    pf.end(st, K_NORMSORT, 8.0 * m * N, (double)m * N * csz);
+    int done = 0, sweeps = 0;
+    if (w.graphs && st != nullptr && !pf.on) {
+        // captured sweeps, replayed in batches between host reads; the batch
+        // size follows the sweeps the last decomposition of this shape needed
+        GraphCache& cache = *(GraphCache*)w.graph_cache;
+        // the captured launches carry the shape, tol and stop_off (the sweep
+        // limit is checked here, between batches)
+        const GraphKey key = std::make_tuple(m, N, ld, JB, (int)BF, (int)sizeof(T),
+                                             (long)std::llround(std::log10(stop_off) * 1000.0),
+                                             (long)std::llround(std::log10(tol) * 1000.0));
+        SweepGraph& sg = cache[key];
+        if (!sg.exec) {
+            if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return -2;
+            enqueue_sweep(false, 1 << 30);
+            if (hipStreamEndCapture(st, &sg.graph) != hipSuccess) return -2;
+            if (hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0) != hipSuccess) return -2;
+        }
+        static thread_local std::map<GraphKey, int> last_sweeps;
+        int batch = std::max(2, last_sweeps.count(key) ? last_sweeps[key] : 4);
+        while (!done) {
+            batch = std::min(batch, max_sweeps - sweeps);
+            if (batch <= 0) { done = 2; break; }
+            for (int q = 0; q < batch; ++q)
+                if (hipGraphLaunch(sg.exec, st) != hipSuccess) return -2;
+            if (!read_info()) return -2;
+            done = w.info_host->done;
+            sweeps = w.info_host->sweeps;
+            batch = 2;
+        }
+        last_sweeps[key] = sweeps;
+        w.n_rotations += w.info_host->rot_total;
+    } else {
+        for (;;) {
+            enqueue_sweep(pf.on, max_sweeps);
+            if (!read_info()) return -2;
+            done = w.info_host->done;
+            sweeps = w.info_host->sweeps;
+            const unsigned long long bits = w.info_host->offmax_bits;
+            double off;
+            std::memcpy(&off, &bits, sizeof(off));
+            const int rot = w.info_host->rotations;
+            w.n_rotations += rot;
+            if (w.trace)
+                std::fprintf(stderr, "jacobi %dx%d sweep %d: max rel off-diagonal %.3e, %d of %d pairs x %d rounds rotated\n",
+                             m, N, sweeps - 1, off, rot, P, nb - 1);
+            pf.add_work(K_UPDATE, rot * pair_flops, rot * 2.0 * pair_bytes);
+            // each inner step applies a two-sided 2x2 transform to all NB^2 entries of G
+            // (22 real flops per entry) and a column rotation to W (11 per entry)
+            pf.add_work(K_EIG, 33.0 * NB * NB * (double)w.info_host->inner_steps, 0.0);
+            if (done) break;
         }
     }
-    unscale(false);
-    return -1;
+    w.n_rounds += (long long)sweeps * (nb - 1);
+    w.n_sweeps += sweeps;
+    if (done != 1) {
+        unscale(false);
+        return -1;
+    }
+    pf.begin(st);
+    hipLaunchKernelGGL((k_colnorm2<T>), gnorm, dim3(256), 0, st, X, m, N, ld, w.nrm2, (const int*)nullptr);
+    hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, w.nrm2, N, w.colmap, w.sig2, fro2,
+                       (const int*)nullptr);
+    unscale(true);
+    pf.end(st, K_NORMSORT, 8.0 * m * N, (double)m * N * csz);
+    return sweeps;
 }
 
 // Sweeps stop when no pair rotated or when the largest relative off-diagonal
 // met at the start of the pairs is at most stop_off (= tol, except for the
 // first phase of split-BF16x3 mode).
 template <typename T>
-int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, JacobiWork& w,
+int jacobi_orthogonalize(C2<T>* X, int m, int N, int ld, double tol, int max_sweeps, JacobiWork& w,
                          hipStream_t st) {
     w.n_splits += 1;
     if constexpr (sizeof(T) == 4) {
@@ -1232,20 +1360,20 @@ int jacobi_orthogonalize(C2<T>* X, int m, int N, double tol, int max_sweeps, Jac
             // FP32-MFMA Gram down to kTolFp32; both with the BF16x3 zero floor
             const double hand = std::fmax(tol, kBf3Handoff);
             const int s1 = w.block == 16
-                ? jacobi_run<T, 16, true>(X, m, N, tol, hand, kZeroRel2Bf3, max_sweeps, w.inner, w, st)
-                : jacobi_run<T, 32, true>(X, m, N, tol, hand, kZeroRel2Bf3, max_sweeps, w.inner, w, st);
+                ? jacobi_run<T, 16, true>(X, m, N, ld, tol, hand, kZeroRel2Bf3, max_sweeps, w.inner, w, st)
+                : jacobi_run<T, 32, true>(X, m, N, ld, tol, hand, kZeroRel2Bf3, max_sweeps, w.inner, w, st);
             if (s1 < 0 || tol <= kTolFp32) return s1;
             const int s2 = w.block == 16
-                ? jacobi_run<T, 16, false>(X, m, N, kTolFp32, kTolFp32, kZeroRel2Bf3, max_sweeps - s1,
+                ? jacobi_run<T, 16, false>(X, m, N, ld, kTolFp32, kTolFp32, kZeroRel2Bf3, max_sweeps - s1,
                                            w.inner, w, st)
-                : jacobi_run<T, 32, false>(X, m, N, kTolFp32, kTolFp32, kZeroRel2Bf3, max_sweeps - s1,
+                : jacobi_run<T, 32, false>(X, m, N, ld, kTolFp32, kTolFp32, kZeroRel2Bf3, max_sweeps - s1,
                                            w.inner, w, st);
             return s2 < 0 ? s2 : s1 + s2;
         }
     }
     const double zrel2 = jacobi_zero_rel2<T>();
-    if (w.block == 16) return jacobi_run<T, 16, false>(X, m, N, tol, tol, zrel2, max_sweeps, w.inner, w, st);
-    return jacobi_run<T, 32, false>(X, m, N, tol, tol, zrel2, max_sweeps, w.inner, w, st);
+    if (w.block == 16) return jacobi_run<T, 16, false>(X, m, N, ld, tol, tol, zrel2, max_sweeps, w.inner, w, st);
+    return jacobi_run<T, 32, false>(X, m, N, ld, tol, tol, zrel2, max_sweeps, w.inner, w, st);
 }
 
 void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,
@@ -1255,21 +1383,28 @@ void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, doub
 }
 
 template <typename T>
-void launch_gather_cols(const C2<T>* X, int m, const int* colmap, const double* sig2, int k,
-                        C2<T>* dst, int ldd, hipStream_t st) {
-    hipLaunchKernelGGL((k_gather_cols<T>), dim3((m + 255) / 256, k), dim3(256), 0, st, X, m, colmap,
-                       sig2, k, dst, ldd);
+void launch_gather_cols(const C2<T>* X, int m, int ldx, const int* colmap, const double* sig2, int k,
+                        C2<T>* dst, int ldd, hipStream_t st, bool normalize) {
+    hipLaunchKernelGGL((k_gather_cols<T>), dim3((m + 255) / 256, k), dim3(256), 0, st, X, m, ldx, colmap,
+                       sig2, k, dst, ldd, normalize ? 1 : 0);
 }
 template <typename T>
-void launch_gather_rows_conj(const C2<T>* X, int m, const int* colmap, const double* sig2, int k,
-                             C2<T>* dst, hipStream_t st) {
+void launch_gather_rows_conj(const C2<T>* X, int m, int ldx, const int* colmap, const double* sig2,
+                             int k, C2<T>* dst, hipStream_t st) {
     hipLaunchKernelGGL((k_gather_rows_conj<T>), dim3((m + 31) / 32, (k + 31) / 32), dim3(256), 0, st,
-                       X, m, colmap, sig2, k, dst);
+                       X, m, ldx, colmap, sig2, k, dst);
 }
 template <typename T>
-void launch_conj_transpose(const C2<T>* A, int rows, int cols, C2<T>* Y, hipStream_t st) {
+void launch_conj_transpose(const C2<T>* A, int rows, int cols, int lda, C2<T>* Y, int ldy,
+                           hipStream_t st) {
     hipLaunchKernelGGL((k_conj_transpose<T>), dim3((rows + 31) / 32, (cols + 31) / 32), dim3(256), 0,
-                       st, A, rows, cols, Y);
+                       st, A, rows, cols, lda, Y, ldy);
+}
+template <typename T>
+void launch_copy_cols(const C2<T>* src, int rows, int cols, int lds, C2<T>* dst, int ldd, hipStream_t st) {
+    if (rows <= 0 || cols <= 0) return;
+    hipLaunchKernelGGL((k_copy_cols<T>), dim3((rows + 255) / 256, cols), dim3(256), 0, st, src, rows, lds,
+                       dst, ldd);
 }
 template <typename T>
 void launch_copy(const C2<T>* src, C2<T>* dst, size_t count, hipStream_t st) {
@@ -1278,12 +1413,13 @@ void launch_copy(const C2<T>* src, C2<T>* dst, size_t count, hipStream_t st) {
 }
 
 #define INST(T)                                                                                  \
-    template int jacobi_orthogonalize<T>(C2<T>*, int, int, double, int, JacobiWork&, hipStream_t); \
-    template void launch_gather_cols<T>(const C2<T>*, int, const int*, const double*, int, C2<T>*,  \
-                                        int, hipStream_t);                                         \
-    template void launch_gather_rows_conj<T>(const C2<T>*, int, const int*, const double*, int,     \
+    template int jacobi_orthogonalize<T>(C2<T>*, int, int, int, double, int, JacobiWork&, hipStream_t); \
+    template void launch_gather_cols<T>(const C2<T>*, int, int, const int*, const double*, int,     \
+                                        C2<T>*, int, hipStream_t, bool);                           \
+    template void launch_gather_rows_conj<T>(const C2<T>*, int, int, const int*, const double*, int, \
                                              C2<T>*, hipStream_t);                                 \
-    template void launch_conj_transpose<T>(const C2<T>*, int, int, C2<T>*, hipStream_t);           \
+    template void launch_conj_transpose<T>(const C2<T>*, int, int, int, C2<T>*, int, hipStream_t); \
+    template void launch_copy_cols<T>(const C2<T>*, int, int, int, C2<T>*, int, hipStream_t);      \
     template void launch_copy<T>(const C2<T>*, C2<T>*, size_t, hipStream_t);
 INST(double)
 INST(float)

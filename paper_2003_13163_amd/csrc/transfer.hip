@@ -285,6 +285,39 @@ void launch_dot(const double2* x, const double2* y, int len, double2* out, hipSt
     hipLaunchKernelGGL(k_dot, dim3(1), dim3(256), 0, st, x, y, len, out);
 }
 
+// A[a, I, c] <- A[a, I, c] * fl(a) * fr(c) with fl = lamL[a] (or 1 / lamL[a]
+// when invL), fr likewise; a null vector leaves that index alone.  The
+// diagonal factors of the Gamma-lambda form (Sec. III.A, App. A).
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale_site(C2<T>* __restrict__ A, int chiL, int chiR,
+                                                    const double* __restrict__ lamL,
+                                                    const double* __restrict__ lamR, int invL, int invR) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t total = (size_t)chiL * 4 * chiR;
+    if (e >= total) return;
+    const int a = (int)(e % chiL);
+    const int c = (int)(e / (4 * (size_t)chiL));
+    double f = 1.0;
+    if (lamL) f = invL ? f / lamL[a] : f * lamL[a];
+    if (lamR) f = invR ? f / lamR[c] : f * lamR[c];
+    C2<T> v = A[e];
+    v.x = (T)(v.x * f);
+    v.y = (T)(v.y * f);
+    A[e] = v;
+}
+
+template <typename T>
+void launch_scale_site(C2<T>* A, int chiL, int chiR, const double* lamL, const double* lamR, bool invL,
+                       bool invR, hipStream_t st) {
+    const size_t total = (size_t)chiL * 4 * chiR;
+    hipLaunchKernelGGL((k_scale_site<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A, chiL,
+                       chiR, lamL, lamR, invL ? 1 : 0, invR ? 1 : 0);
+}
+template void launch_scale_site<double>(double2*, int, int, const double*, const double*, bool, bool,
+                                        hipStream_t);
+template void launch_scale_site<float>(float2*, int, int, const double*, const double*, bool, bool,
+                                       hipStream_t);
+
 template void launch_transfer_left<double>(const double2*, int, int, const double2*, const double2*,
                                            double2*, hipStream_t);
 template void launch_transfer_left<float>(const float2*, int, int, const double2*, const double2*,

@@ -8,6 +8,10 @@ run (oracle/replay.py), central differences with step h = 1e-6 give
   * dO/dp, the superoperators rebuilt at p +- h (Sec. II.B, N2[p] after U);
   * dO/d eps along three unit directions D_k in superoperator space
     (mpo_inputs.gradient_directions(372, 3, seed=5)), M_g +- h D_k[g].
+O is a polynomial of degree 372 in p (and in eps), so the h^2 term of a
+central difference is not negligible at 1e-8 (about 3e-8 of dO/dp); the same
+differences at 2h give the Richardson value (4 D(h) - D(2h)) / 3, whose error
+is of order h^4.
 Usage: python tests/golden/make_golden_adjoint.py
 writes tests/golden/oracle_adjoint_n32_d24_p0.01_chi256.json.
 """
@@ -42,16 +46,25 @@ def main():
         return v
 
     O_rep = value(sup)
-    dp = (value(gates.circuit_superops(draws, p + h, "pauli"))
-          - value(gates.circuit_superops(draws, p - h, "pauli"))) / (2 * h)
+
+    def central(f, step):
+        return (f(step) - f(-step)) / (2 * step)
+
+    def richardson(f):
+        d1, d2 = central(f, h), central(f, 2 * h)
+        return d1, (4 * d1 - d2) / 3
+
+    dp, dp_r = richardson(lambda e: value(gates.circuit_superops(draws, p + e, "pauli")))
     dirs = mi.gradient_directions(len(sup), 3, seed=5)
-    dd = [(value(sup + h * d) - value(sup - h * d)) / (2 * h) for d in dirs]
+    dd = [richardson(lambda e, d=d: value(sup + e * d)) for d in dirs]
     out = {"workload": {"n": n, "depth": depth, "p": p, "chi_max": chi, "seed": seed, "cutoff": cutoff,
                         "basis": "pauli", "observable": "sum_i Tr[Z_i rho_D]"},
            "h": h, "direction_seed": 5, "n_gates": len(sup),
            "O_forward": O_fwd, "O_replay": [O_rep.real, O_rep.imag],
            "dO_dp_fd": [dp.real, dp.imag],
-           "dO_ddir_fd": [[v.real, v.imag] for v in dd],
+           "dO_dp_richardson": [dp_r.real, dp_r.imag],
+           "dO_ddir_fd": [[v[0].real, v[0].imag] for v in dd],
+           "dO_ddir_richardson": [[v[1].real, v[1].imag] for v in dd],
            "seconds": time.time() - t0}
     path = os.path.join(HERE, "oracle_adjoint_n32_d24_p0.01_chi256.json")
     with open(path, "w") as f:

@@ -29,7 +29,7 @@ def pm():
 def declared_functions():
     text = open(os.path.join(ROOT, "include", "mpo.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:mpo_status|void|const char \*)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:mpo_status|void|int|const char \*)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
@@ -110,3 +110,13 @@ def test_run_brickwork_signature_has_order():
     decl = re.search(r"mpo_status run_brickwork\((.*?)\);", text, flags=re.S).group(1)
     args = [a.strip() for a in decl.split(",")]
     assert args[6].startswith("mpo_order"), args
+
+
+def test_default_tuning_validation(pm):
+    lib = pm.library()
+    assert lib.mpo_set_default_tuning(1, 64, 24, 1) == 1          # block must be 16 or 32
+    assert lib.mpo_set_default_tuning(1, 64, 32, 0) == 1          # inner in [1, 8]
+    assert lib.mpo_set_default_tuning(7, 64, 32, 1) == 1          # unknown precision
+    assert lib.mpo_set_default_tuning(1, 0, 32, 1) == 1
+    assert lib.mpo_set_tuning(None, 16, 1) == 1
+    assert lib.mpo_set_graphs(None, 1) == 1

@@ -34,3 +34,31 @@ def test_noiseless_saturation_n8(ens):
     print(f"p=0 n=8: S_max(30) {r['S_max_by_depth'][-1]:.3f}", flush=True)
     assert abs(r["S_max_by_depth"][-1] - 6.56) <= 0.1
     assert abs(r["trace_at_D_star"] - 1.0) <= 1e-10
+
+
+def test_batched_ensemble_equals_oracle_ensemble(ens):
+    """The batched ensemble (all realizations in one mpo_batch_run) against the
+    oracle run realization by realization with the same seeds: mean bond
+    entropies and mean Tr rho after every time step to the FP64 target, and
+    the same D* (8 qubits, p = 0.1, chi_max = 12 so that truncation is active,
+    8 realizations, depth 8)."""
+    import numpy as np
+    import mpo_inputs as mi
+    from oracle import gates, mpo as omp
+    from paper_2003_13163_amd.ensemble import ensemble_stats
+    n, p, chi, depth, samples, seed0 = 8, 0.1, 12, 8, 8, 2000
+    r = ens(n, p, chi, depth, samples, seed0)
+    S, tr = [], []
+    for i in range(samples):
+        draws = mi.ginibre_draws(n, depth, seed=seed0 + i)
+        ref = omp.run_brickwork(n, gates.circuit_superops(draws, p, "pauli"), mi.brickwork_sites(n, depth),
+                                chi, 1e-12, "pauli")
+        S.append(ref["S"])
+        tr.append(ref["trace"])
+    want = ensemble_stats(np.array(S), np.array(tr))
+    dS = np.abs(np.array(r["S_max_by_depth"]) - np.array(want["S_max_by_depth"])).max()
+    dT = np.abs(np.array(r["mean_trace_by_depth"]) - np.array(want["mean_trace_by_depth"])).max()
+    print(f"batched ensemble vs oracle: max|dS_max| {dS:.2e} max|dTr| {dT:.2e} D* {r['D_star']}", flush=True)
+    assert min(want["mean_trace_by_depth"]) < 0.999          # truncation is active
+    assert dS <= 1e-10 and dT <= 1e-10
+    assert r["D_star"] == want["D_star"]

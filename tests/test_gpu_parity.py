@@ -1,10 +1,11 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
 Tolerances: FP64 mode |dS| <= 1e-10 and |d<Z>| <= 1e-6 (the stated targets
-for entropies and expectation values); FP32-MFMA mode |dS| <= 1e-4;
-split-BF16x3 mode as derived beside its constants below.  Raw
-tensors are compared only through gauge-invariant quantities (dense states,
-singular values, entropies, expectation values).
+for entropies and expectation values); the reduced-precision modes (FP32-MFMA
+and split-BF16x3) |dS| <= 1e-4 (the stated mixed-mode target) and
+|d<Z>| <= Z_MIXED_TOL, derived below.  Raw tensors are compared only through
+gauge-invariant quantities (dense states, singular values, entropies,
+expectation values).
 """
 import json
 import os
@@ -20,14 +21,19 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# Split-BF16x3 carries about 16 significant bits: a product term is off by up
-# to about 2^-15 = 3e-5 relative, and one truncated gate applies the
-# two-site product, the channel and some 15 sweeps of Jacobi rotations, so a
-# gate moves the state by about sqrt(15) * 1.5e-5 = 6e-5.  One bulk gate is
-# held to 2e-4 (entropy, and singular values relative to the largest); the
-# 32 gates of the n = 8 circuit, adding up at worst linearly, to 2e-3.
-BF3_GATE_TOL = 2e-4
-BF3_CIRCUIT_TOL = 2e-3
+# Mixed-mode entropy target (both reduced-precision modes), per gate and per
+# circuit.
+MIXED_TOL = 1e-4
+# <Z_i> in the FP32-storage modes: every split rotates each column some
+# R = sweeps x rounds ~ 10 x 60 = 600 times, each rotation rounding it to
+# u = 2^-24 relative, so a split leaves about u sqrt(R) = 1.5e-6 of relative
+# noise in the state; an 8-qubit depth-8 circuit makes S ~ 130 splits (28 gates
+# and the re-gauging moves around them), about u sqrt(R S) = 1.7e-5 in the
+# state, and <Z_i> = Tr[Z_i rho] / Tr rho, a ratio of two linear functionals
+# of it, carries that relative error (measured 1.1e-5 FP32, 1.8e-5 BF16x3).
+# The 1e-6 target for <Z_i> is therefore an FP64 bound; the FP32-storage
+# modes are held to 5e-5, about three times the estimate.
+Z_MIXED_TOL = 5e-5
 
 
 @pytest.fixture(scope="module")
@@ -87,7 +93,7 @@ def test_n8_exact_fp64_vs_dense(pm, basis):
     st.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16x3", BF3_CIRCUIT_TOL)])
+@pytest.mark.parametrize("prec,tol", [("fp32", MIXED_TOL), ("bf16x3", MIXED_TOL)])
 def test_n8_exact_reduced_precision_vs_dense(pm, prec, tol):
     n, depth, p = 8, 8, 0.02
     say(f"case n8 exact {prec}")
@@ -101,7 +107,8 @@ def test_n8_exact_reduced_precision_vs_dense(pm, prec, tol):
     dZ = np.abs(res["Z"] - z_ref).max()
     say(f"  {prec} max|dS| {dS:.3e} max|dZ| {dZ:.3e} trace-1 {np.abs(res['trace'] - 1).max():.3e}")
     assert dS <= tol
-    assert dZ <= tol
+    assert dZ <= Z_MIXED_TOL
+    assert np.abs(res["trace"] - 1.0).max() <= Z_MIXED_TOL
     st.close()
 
 
@@ -133,8 +140,8 @@ def test_single_gate_ragged_vs_oracle(pm, site, chi_max):
     st.close()
 
 
-@pytest.mark.parametrize("chi,prec,tol", [(128, "fp64", 1e-10), (512, "fp64", 1e-10), (128, "fp32", 1e-4),
-                                          (128, "bf16x3", BF3_GATE_TOL)])
+@pytest.mark.parametrize("chi,prec,tol", [(128, "fp64", 1e-10), (512, "fp64", 1e-10), (128, "fp32", MIXED_TOL),
+                                          (128, "bf16x3", MIXED_TOL)])
 def test_bulk_gate_singular_values(pm, chi, prec, tol):
     # a saturated bulk gate: chi_L = chi_M = chi_R = chi, theta' is (4 chi) x (4 chi)
     n = 12
@@ -181,10 +188,7 @@ def test_bulk_gate_full_size_all_modes(pm):
     rinfo = ref.apply_gate(s0, sup, chi, 1e-12)
     lam_ref = ref.schmidt_sweep()[s0]
     say(f"  oracle kept {rinfo.kept} S {rinfo.entropy:.6f}")
-    # BF16x3 stops its sweeps at a relative orthogonality of 1e-4, so each of
-    # the ~2(n-1) re-gauging moves that canonicalise the imported state leaves
-    # the isometries exact to ~1e-4: a few 1e-3 in weight, 1e-3 in entropy
-    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4), ("bf16x3", 1e-3)):
+    for prec, tol in (("fp64", 1e-10), ("fp32", MIXED_TOL), ("bf16x3", MIXED_TOL)):
         st = pm.Mpo(n, chi, prec, "pauli")
         st.import_state(pm.tensors_to_snapshot(ts))
         info = st.apply(s0, sup, chi, 1e-12)
@@ -195,11 +199,43 @@ def test_bulk_gate_full_size_all_modes(pm):
         assert info.kept == rinfo.kept
         assert abs(info.entropy - rinfo.entropy) <= tol
         assert dlam <= tol
-        assert abs(info.total_weight - rinfo.total_weight) <= 10 * tol * rinfo.total_weight
-        assert abs(info.discarded_weight - rinfo.discarded_weight) <= 10 * tol * rinfo.total_weight
-        if prec != "bf16x3":
-            assert abs(info.total_weight - rinfo.total_weight) <= tol * rinfo.total_weight
+        assert abs(info.total_weight - rinfo.total_weight) <= tol * rinfo.total_weight
+        assert abs(info.discarded_weight - rinfo.discarded_weight) <= tol * rinfo.total_weight
         st.close()
+
+
+def test_bulk_trajectory_reduced_precision_vs_fp64(pm):
+    """The benchmarked gate sequence: an in-situ chi = 1024 state (16 qubits,
+    depth-10 brickwork, p = 0.01, seed 0, built in FP64), then seven bulk gates
+    of the continuing brickwork (sites 6..9 with their centre moves, fresh gates
+    from seed 1) in each mode.  FP32-MFMA and split-BF16x3 follow the FP64 run,
+    itself checked against the oracle gate by gate above, to the mixed-mode
+    target on the entropy of every gate."""
+    n, depth, p, chi = 16, 10, 0.01, 1024
+    say(f"case bulk trajectory chi={chi}: FP64 snapshot of n={n} depth={depth}")
+    draws = mi.ginibre_draws(n, depth, seed=0)
+    st = pm.Mpo(n, chi, "fp64", "pauli")
+    st.run_brickwork(depth, pm.build_superops(draws, p, "pauli"), chi, 1e-12, record=None)
+    assert max(st.bond_dims()[0]) == chi
+    snap = st.export()
+    st.close()
+    sites = [6, 8, 7, 9, 6, 8, 7]
+    sups = pm.build_superops(mi.ginibre_draws(n, 4, seed=1)[:len(sites)], p, "pauli")
+    ent, disc = {}, {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        st = pm.Mpo(n, chi, prec, "pauli")
+        st.import_state(snap)
+        infos = [st.apply(s, m, chi, 1e-12) for s, m in zip(sites, sups)]
+        st.close()
+        ent[prec] = np.array([i.entropy for i in infos])
+        disc[prec] = np.array([i.discarded_weight / i.total_weight for i in infos])
+        assert all(i.kept == chi for i in infos)
+    for prec in ("fp32", "bf16x3"):
+        dS = np.abs(ent[prec] - ent["fp64"]).max()
+        dw = np.abs(disc[prec] - disc["fp64"]).max()
+        say(f"  {prec}: max|dS| {dS:.3e}  max|d discarded fraction| {dw:.3e}")
+        assert dS <= MIXED_TOL
+        assert dw <= MIXED_TOL
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-4)])
@@ -419,7 +455,7 @@ def test_adjoint_vs_oracle_dense(pm, basis, chi):
     assert err <= 1e-10
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16x3", 2e-3)])
+@pytest.mark.parametrize("prec,tol", [("fp32", MIXED_TOL), ("bf16x3", MIXED_TOL)])
 def test_adjoint_reduced_precision(pm, prec, tol):
     # exact regime (no truncation): the forward differs from FP64 by rounding only,
     # so the gradient carries the mode's relative error
@@ -472,6 +508,49 @@ def test_adjoint_rejects_bonds_above_chi_max(pm):
     with pytest.raises(pm.MpoError, match="chi_max"):
         st.adjoint_brickwork(depth, sup, 8, 1e-12)
     st.close()
+
+
+def test_adjoint_differentiation_workload_vs_frozen_replay(pm):
+    """n = 32, depth 24, p = 0.01, chi_max = 256 (seed 0), O = sum_i Tr[Z_i rho_D],
+    checkpoints every 4 time steps: dO/dp and three directional derivatives of
+    the GPU adjoint against central differences (h = 1e-6) of the oracle's
+    frozen-projector replay (tests/golden/make_golden_adjoint.py; differences
+    at h and 2h combined by Richardson extrapolation, since O is a polynomial of
+    degree 372 in each parameter), to 1e-8 relative (dO/dp to itself, a
+    directional derivative to the gradient's norm); the Euler identity at
+    every gate."""
+    with open(os.path.join(HERE, "golden", "oracle_adjoint_n32_d24_p0.01_chi256.json")) as f:
+        w = json.load(f)
+    wl = w["workload"]
+    n, depth, p, chi = wl["n"], wl["depth"], wl["p"], wl["chi_max"]
+    say(f"case adjoint differentiation workload n={n} depth={depth} chi={chi} checkpoint_every=4")
+    draws = mi.ginibre_draws(n, depth, seed=wl["seed"])
+    sup = pm.build_superops(draws, p, "pauli")
+    st = pm.Mpo(n, chi, "fp64", "pauli")
+    O, grads, comax = st.adjoint_brickwork(depth, sup, chi, wl["cutoff"], checkpoint_every=4)
+    st.close()
+    assert abs(O - w["O_forward"]) <= 1e-10 * abs(w["O_forward"])
+    euler = np.einsum("gij,gij->g", sup, grads)
+    assert np.abs(euler - O).max() <= 1e-10 * abs(O)
+    # M_g = S_N(p) S_U in the Pauli basis, S_N = diag(1, 1 - 16p/15, ...): dM/dp
+    su = pm.build_superops(draws, 0.0, "pauli")
+    dmdp = np.concatenate([[0.0], np.full(15, -16.0 / 15.0)])[None, :, None] * su
+    dO_dp = np.sum(grads * dmdp)
+    ref = complex(*w["dO_dp_richardson"])
+    say(f"  O {O:.12e}  dO/dp {dO_dp.real:.12e} vs fd {ref.real:.12e} (plain h: {w['dO_dp_fd'][0]:.12e})"
+        f"  co-state bond {comax}")
+    assert abs(dO_dp - ref) <= 1e-8 * abs(ref)
+    # unit directions spread over all 372 x 256 entries: a directional derivative
+    # is about |grad| / sqrt(95232), and the difference quotient carries the
+    # replay's rounding (about 1e-14 of O) divided by h; both are measured
+    # against |grad| |D| = |grad|, the scale of any directional derivative
+    gnorm = float(np.sqrt(np.sum(np.abs(grads) ** 2)))
+    dirs = mi.gradient_directions(len(sup), 3, seed=w["direction_seed"])
+    for k, d in enumerate(dirs):
+        got = np.sum(grads * d)
+        ref = complex(*w["dO_ddir_richardson"][k])
+        say(f"  direction {k}: {got.real:.12e} vs fd {ref.real:.12e}  (|grad| {gnorm:.3e})")
+        assert abs(got - ref) <= 1e-8 * gnorm
 
 
 def test_adjoint_euler_identity_larger(pm):
@@ -558,3 +637,80 @@ def test_snake_equals_ascending_without_truncation(pm):
     assert np.abs(ra["S"] - rb["S"]).max() <= 1e-11
     assert np.abs(ra["Z"] - rb["Z"]).max() <= 1e-11
     a.close(); b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_captured_sweeps_bit_identical(pm, prec):
+    """Jacobi sweeps replayed from captured HIP graphs, queued ahead of the
+    convergence read, give the same state as direct launches, bit for bit."""
+    import torch
+    n, depth, p, chi = 10, 6, 0.02, 48
+    say(f"case captured sweeps {prec} n={n} depth={depth} chi={chi}")
+    sup = pm.build_superops(mi.ginibre_draws(n, depth, seed=61), p, "pauli")
+    outs = []
+    for graphs in (False, True):
+        stream = torch.cuda.Stream()
+        st = pm.Mpo(n, chi, prec, "pauli", stream=stream)
+        if graphs:
+            st.set_graphs(True)
+        outs.append(st.run_brickwork(depth, sup, chi, 1e-12, record="all"))
+        st.close()
+    for key in ("S", "Z", "trace", "discarded"):
+        assert np.array_equal(outs[0][key], outs[1][key]), key
+
+
+def test_batch_with_captured_sweeps_equals_direct(pm):
+    shapes = [(6, 4, 16), (8, 5, 32), (10, 6, 16), (12, 4, 32)]
+    circuits, sups = [], []
+    for i, (n, depth, chi) in enumerate(shapes):
+        circuits.append((n, depth, chi, 1e-12))
+        sups.append(pm.build_superops(mi.ginibre_draws(n, depth, seed=300 + i), 0.02, "pauli"))
+    say(f"case batch with captured sweeps, {len(shapes)} circuits, record all")
+    direct = pm.batch_run(circuits, sups, "fp32", "pauli", n_streams=2, record="all")
+    graphs = pm.batch_run(circuits, sups, "fp32", "pauli", n_streams=2, record="all", use_graph=True)
+    for a, b in zip(direct, graphs):
+        assert np.array_equal(a["S"], b["S"]) and np.array_equal(a["Z"], b["Z"])
+        assert np.array_equal(a["trace"], b["trace"])
+
+
+# ------------------------------------------------------ the paper's own update
+@pytest.mark.parametrize("n,depth,chi,p", [(8, 6, 12, 0.02), (10, 5, 20, 0.01)])
+def test_vidal_update_vs_oracle_appendix_a(pm, n, depth, chi, p):
+    """mpo_run_brickwork_vidal (Gamma-lambda form, global SVD sweeps, Gamma
+    recovered by dividing by lambda') against the oracle's App. A update
+    (oracle/vidal.py) with truncation active: S_b at every bond after every
+    time step and the discarded weight of every gate to the FP64 target; and
+    against the local update (run_brickwork), which truncates the same Schmidt
+    values; the final <Z_i> against the oracle."""
+    from oracle import vidal
+    say(f"case App. A update n={n} depth={depth} chi={chi}")
+    draws = mi.ginibre_draws(n, depth, seed=71)
+    sup = pm.build_superops(draws, p, "pauli")
+    st = pm.Mpo(n, chi, "fp64", "pauli")
+    res = st.run_brickwork_vidal(depth, sup, chi, 1e-12)
+    z_gpu, tr_gpu = st.expect_z_all()
+    dims = st.bond_dims()[0]
+    st.close()
+    ref = vidal.VidalMPO(n, "pauli")
+    S_ref, disc_ref, g = [], [], 0
+    for layer in mi.brickwork_sites(n, depth):
+        for s in layer:
+            disc_ref.append(ref.apply_gate(s, sup[g], chi, 1e-12).discarded_weight)
+            g += 1
+        S_ref.append(ref.bond_entropies())
+    S_ref = np.array(S_ref)
+    m = omp.MPO.from_tensors(ref.to_tensors(), "pauli")
+    z_ref = m.expect_z_all()
+    st = pm.Mpo(n, chi, "fp64", "pauli")
+    loc = st.run_brickwork(depth, sup, chi, 1e-12, record="all")
+    st.close()
+    dS = np.abs(res["S"] - S_ref).max()
+    dL = np.abs(res["S"] - loc["S"]).max()
+    dD = np.abs(res["discarded"] - np.array(disc_ref)).max()
+    dZ = np.abs(z_gpu - z_ref).max()
+    say(f"  max|dS| vs oracle {dS:.3e}, vs local update {dL:.3e}; discarded {dD:.3e}; <Z> {dZ:.3e}; "
+        f"bonds {dims}")
+    assert max(dims) == chi and np.array(disc_ref).max() > 1e-8      # truncation is active
+    assert dS <= 1e-10 and dL <= 1e-10
+    assert dD <= 1e-12
+    assert dZ <= 1e-6
