@@ -343,6 +343,26 @@ mpo_status mpo_set_graphs(mpo_handle *h, int on);
 mpo_status mpo_set_tuning(mpo_handle *h, int block, int inner);
 mpo_status mpo_set_default_tuning(mpo_precision prec, int chi_upto, int block, int inner);
 
+/* Starting basis of the truncated split (App. A: SVD of the two-site block).
+ * A split of an m x N block with N >= min_cols first computes the Gram matrix
+ * G = theta'^H theta' (FP64), its eigenvectors V (Householder
+ * tridiagonalisation, divide and conquer on the tridiagonal), and hands
+ * theta' V, whose columns are orthogonal to about the FP64 eigen-solver's
+ * accuracy relative to their own norms, to the one-sided Jacobi sweeps, which
+ * then only polish (they still decide convergence, the values and the
+ * isometries).  Every mode computes this start in FP64.  min_cols = 0 turns
+ * it off.  Default 1024 (environment override MPO_PRECOND_MIN).  Handles with
+ * 4 chi_cap < 512 have no eigen workspace: min_cols > 0 is MPO_ERR_ARG there. */
+mpo_status mpo_set_precond(mpo_handle *h, int min_cols);
+
+/* The eigen-solver of mpo_set_precond on a host matrix, for tests: G is an
+ * N x N Hermitian matrix (row-major, interleaved complex, caller-owned), w
+ * receives the N eigenvalues in ascending order and V (row-major, interleaved
+ * complex, N x N) the eigenvectors as columns.  2 <= N <= 4 chi_cap; uses the
+ * handle's arena and stream (synchronises).  MPO_ERR_ARG: no eigen
+ * workspace, N out of range, non-finite input.  The state is unchanged.     */
+mpo_status mpo_hermitian_eig(mpo_handle *h, int N, const double *G, double *w, double *V);
+
 /* Instrumentation: per-kernel-class timing with HIP events recorded on the
  * handle's stream around every launch, plus the algorithmic flop and byte
  * counts of those launches (real flops; complex MAC = 8).  Enabling resets
@@ -356,8 +376,8 @@ typedef struct {
 } mpo_kernel_stat;
 mpo_status mpo_profile_enable(mpo_handle *h, int on);
 /* Synchronises.  Writes up to cap entries; *count = number of kernel classes.
- * svd_counters (4 values or NULL): splits, Jacobi sweeps, Jacobi rounds,
- * rotated block pairs.                                                      */
+ * svd_counters (5 values or NULL): splits, Jacobi sweeps, Jacobi rounds,
+ * rotated block pairs, splits started from the Gram eigenvectors.           */
 mpo_status mpo_profile_read(mpo_handle *h, mpo_kernel_stat *out, int cap, int *count,
                             long long *svd_counters);
 

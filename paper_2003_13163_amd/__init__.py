@@ -100,6 +100,8 @@ def library() -> ctypes.CDLL:
         "mpo_set_graphs": [P, I],
         "mpo_run_brickwork_vidal": [P, I, pd, I, I, D, pd, pd],
         "mpo_set_tuning": [P, I, I],
+        "mpo_set_precond": [P, I],
+        "mpo_hermitian_eig": [P, I, pd, pd, pd],
         "mpo_set_default_tuning": [I, I, I, I],
         "mpo_batch_result_doubles": [I, I, I],
         "mpo_adjoint_workspace_bytes": [I, I, I, I, I, ctypes.POINTER(S)],
@@ -315,6 +317,21 @@ class Mpo:
         del work
         return O.value, grads.view(np.complex128).reshape(g, 16, 16), comax.value
 
+    def set_precond(self, min_cols: int):
+        """Splits with at least min_cols columns start from the Gram eigenvectors (0 = never)."""
+        _check(library().mpo_set_precond(self._h, int(min_cols)))
+
+    def hermitian_eig(self, G):
+        """Eigenvalues (ascending) and eigenvectors (columns) of a Hermitian matrix through
+        the split's eigen-solver kernels (uses this handle's workspace)."""
+        G = np.ascontiguousarray(np.asarray(G, dtype=np.complex128))
+        N = G.shape[0]
+        w = np.empty(N)
+        V = np.empty((N, N), dtype=np.complex128)
+        _check(library().mpo_hermitian_eig(self._h, N, _dptr(G.view(np.float64)), _dptr(w),
+                                           _dptr(V.view(np.float64))))
+        return w, V
+
     def set_graphs(self, on: bool = True):
         """Replay the Jacobi sweeps from captured HIP graphs (needs a non-null stream)."""
         _check(library().mpo_set_graphs(self._h, 1 if on else 0))
@@ -325,11 +342,12 @@ class Mpo:
         _check(library().mpo_profile_enable(self._h, 1 if on else 0))
 
     def profile_read(self) -> dict:
-        stats = (_KernelStat * 16)()
+        stats = (_KernelStat * 32)()
         cnt = ctypes.c_int()
-        svd = (ctypes.c_longlong * 4)()
-        _check(library().mpo_profile_read(self._h, stats, 16, ctypes.byref(cnt), svd))
-        out = {"kernels": {}, "svd": dict(zip(("splits", "sweeps", "rounds", "rotated_pairs"), list(svd)))}
+        svd = (ctypes.c_longlong * 5)()
+        _check(library().mpo_profile_read(self._h, stats, 32, ctypes.byref(cnt), svd))
+        out = {"kernels": {}, "svd": dict(zip(("splits", "sweeps", "rounds", "rotated_pairs", "eigen_starts"),
+                                              list(svd)))}
         for k in range(cnt.value):
             st = stats[k]
             out["kernels"][st.name.decode()] = {"launches": st.launches, "ms": st.ms,

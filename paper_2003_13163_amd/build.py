@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpo.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["gemm.hip", "jacobi.hip", "transfer.hip", "capi.hip", "superop.cpp", "batch.cpp"]
+SOURCES = ["gemm.hip", "jacobi.hip", "heev.hip", "transfer.hip", "capi.hip", "superop.cpp", "batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

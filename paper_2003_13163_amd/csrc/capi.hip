@@ -68,9 +68,16 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // that one MFMA operand load touches into the same L1 cache sets.
 inline int work_ld(int m) { return ((m + 1) & ~1) + 8; }
 
+// Splits of at least this many columns start from the eigenvectors of the
+// Gram matrix (heev.hip) when the handle's bond cap allows them; the eigen
+// workspace is reserved for handles whose widest split, 4 chi_cap columns,
+// reaches kHeevMinCols.
+constexpr int kHeevMinCols = 512;
+constexpr int kPrecondMinDefault = 1024;
+
 struct Layout {
     size_t slot_bytes, slots, x_bytes, r_bytes, partial_bytes, w_bytes, skip_bytes, vecN_bytes,
-        info_bytes, env_bytes, tscr_bytes, vec_bytes, dot_bytes, super_bytes, total;
+        info_bytes, env_bytes, tscr_bytes, vec_bytes, dot_bytes, super_bytes, heev_bytes, total;
     int max_pairs;
 };
 
@@ -96,11 +103,12 @@ Layout make_layout(int n, int chi_cap, mpo_precision prec) {
     L.vec_bytes = align256((size_t)(n + 2) * 4 * sizeof(double2));
     L.dot_bytes = align256((size_t)(n + 2) * sizeof(double2));
     L.super_bytes = align256((size_t)kMaxSuper * 256 * csz);
+    L.heev_bytes = 4 * chi_cap >= kHeevMinCols ? align256(heev_bytes(4 * chi_cap, 4 * chi_cap)) : 0;
     L.total = L.slot_bytes * L.slots + 2 * L.x_bytes + L.r_bytes + L.partial_bytes + L.w_bytes +
               L.skip_bytes + 3 * L.vecN_bytes + 2 * align256((size_t)chi_cap * sizeof(double)) +
               L.info_bytes + 2 * L.env_bytes + L.tscr_bytes +
               align256((size_t)chi_cap * sizeof(double2)) + L.vec_bytes + L.dot_bytes +
-              L.super_bytes;
+              L.super_bytes + L.heev_bytes;
     return L;
 }
 
@@ -124,6 +132,7 @@ struct mpo_handle {
     char *X = nullptr, *X2 = nullptr, *R = nullptr, *Mdev = nullptr;
     size_t x_bytes = 0;          // bytes of X and of X2 each
     JacobiWork jw{};
+    HeevWork hw{};
     double2 *envL = nullptr, *envR = nullptr, *tscr = nullptr, *tmp = nullptr, *vecs = nullptr,
             *dots = nullptr;
     double* sig2_all = nullptr;  // copy of the last split's sorted squared values
@@ -1133,6 +1142,8 @@ mpo_status guarded(mpo_handle* h, F&& f) {
         return fail(MPO_ERR_NOCONV, "%s", e.what);
     } catch (const ArenaError& e) {
         return fail(MPO_ERR_ARENA, "%s", e.what);
+    } catch (const HeevFailure& e) {
+        return fail(MPO_ERR_HIP, "eigen-solver: %s", e.what);
     }
 }
 
@@ -1312,6 +1323,17 @@ mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis, v
     h->vecs = (double2*)p; p += L.vec_bytes;
     h->dots = (double2*)p; p += L.dot_bytes;
     h->Mdev = p; p += L.super_bytes;
+    h->jw.heev = nullptr;
+    h->jw.precond_min = 0;
+    h->jw.n_precond = 0;
+    if (L.heev_bytes) {
+        heev_carve(p, 4 * chi_cap, 4 * chi_cap, h->hw);
+        p += L.heev_bytes;
+        h->hw.plans = heev_plans_new();
+        h->jw.heev = &h->hw;
+        h->jw.precond_min = kPrecondMinDefault;
+        if (const char* e = std::getenv("MPO_PRECOND_MIN")) h->jw.precond_min = std::max(0, std::atoi(e));
+    }
     h->dims.assign(n - 1, 1);
     h->last_S.assign(n - 1, 0.0);
     h->last_lam.assign(n - 1, std::vector<double>());
@@ -1337,6 +1359,7 @@ void mpo_destroy(mpo_handle* h) {
     if (h->small_host) (void)hipHostFree(h->small_host);
     if (h->sig_host) (void)hipHostFree(h->sig_host);
     jacobi_graph_cache_free(h->jw.graph_cache);
+    heev_plans_free(h->hw.plans);
     delete h;
 }
 
@@ -1566,6 +1589,28 @@ mpo_status mpo_set_graphs(mpo_handle* h, int on) {
     return MPO_OK;
 }
 
+mpo_status mpo_set_precond(mpo_handle* h, int min_cols) {
+    if (!h) return fail(MPO_ERR_ARG, "null handle");
+    if (min_cols < 0) return fail(MPO_ERR_ARG, "min_cols must be >= 0 (0 = off), got %d", min_cols);
+    if (min_cols > 0 && !h->jw.heev)
+        return fail(MPO_ERR_ARG, "this handle has no eigen workspace (4 chi_cap < %d)", kHeevMinCols);
+    h->jw.precond_min = min_cols;
+    return MPO_OK;
+}
+
+mpo_status mpo_hermitian_eig(mpo_handle* h, int N, const double* G, double* w, double* V) {
+    if (!h) return fail(MPO_ERR_ARG, "null handle");
+    if (!G || !w || !V) return fail(MPO_ERR_ARG, "null argument");
+    if (!h->jw.heev) return fail(MPO_ERR_ARG, "this handle has no eigen workspace (4 chi_cap < %d)", kHeevMinCols);
+    if (N < 2 || N > h->hw.cap_n) return fail(MPO_ERR_ARG, "N = %d out of [2, %d]", N, h->hw.cap_n);
+    if (!finite_all(G, (size_t)2 * N * N)) return fail(MPO_ERR_ARG, "non-finite matrix entry");
+    return guarded(h, [&] {
+        heev_host(N, G, w, V, h->hw, h->prof, h->st);
+        for (int i = 0; i < N; ++i)
+            if (!std::isfinite(w[i])) throw NumericError{"non-finite eigenvalue"};
+    });
+}
+
 mpo_status mpo_run_brickwork_vidal(mpo_handle* h, int depth, const double* superops, int n_gates, int chi_max,
                                    double cutoff, double* S_out, double* discarded_out) {
     if (!h) return fail(MPO_ERR_ARG, "null handle");
@@ -1589,7 +1634,7 @@ mpo_status mpo_profile_enable(mpo_handle* h, int on) {
     if (!h) return fail(MPO_ERR_ARG, "null handle");
     h->prof.reset();
     h->prof.on = on != 0;
-    h->jw.n_splits = h->jw.n_sweeps = h->jw.n_rounds = h->jw.n_rotations = 0;
+    h->jw.n_splits = h->jw.n_sweeps = h->jw.n_rounds = h->jw.n_rotations = h->jw.n_precond = 0;
     return MPO_OK;
 }
 
@@ -1611,6 +1656,7 @@ mpo_status mpo_profile_read(mpo_handle* h, mpo_kernel_stat* out, int cap, int* c
         svd_counters[1] = h->jw.n_sweeps;
         svd_counters[2] = h->jw.n_rounds;
         svd_counters[3] = h->jw.n_rotations;
+        svd_counters[4] = h->jw.n_precond;
     }
     return MPO_OK;
 }

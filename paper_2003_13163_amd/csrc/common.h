@@ -143,6 +143,40 @@ void launch_theta_channel(int chiL, int chiM, int chiR, const C2<T>* As, const C
                           const C2<T>* Mdev, C2<T>* X, C2<T>* X2, int ldx, hipStream_t st,
                           bool bf3 = false);
 
+// Eigen-decomposition of the split's Gram matrix (heev.hip): workspace carved
+// from the handle's arena, sized for at most cap_m rows and cap_n columns.
+constexpr int kTrdNb = 32;            // panel width of the tridiagonalisation
+struct HeevFailure { const char* what; };
+struct HeevWork {
+    double2* Xd;                      // FP64 copy of X, column stride ((cap_m + 1) & ~1) + 8
+    double2* G;                       // Gram (stride N + 8), then the reflectors below its diagonal
+    double2 *VW, *WV;                 // panel [V W] and [W V], N x 2 kTrdNb each (stride N)
+    double2 *yraw, *wt, *dots, *tau;
+    double* part;                     // partial sums of the vector kernels
+    double *d, *e;                    // tridiagonal
+    double2 *Y, *Tm, *Cpart, *P;      // back-transformation blocks, split-K partials
+    double *Z, *Z2, *U;               // eigenvectors of T and merge scratch (N x N, stride N)
+    double *dv, *ds, *dz, *ndv, *ndz, *dfv, *taus, *lam, *zh;
+    int *dcol, *ndc, *dfc, *orig, *perm;
+    int2* rot_ab;
+    double2* rot_cs;
+    int *mk, *mnrot;
+    double* mrho;
+    void* plans;                      // divide-and-conquer plans per size (host, owned by the handle)
+    int cap_m = 0, cap_n = 0;
+    long long n_runs = 0;
+};
+size_t heev_bytes(int m_max, int n_max);
+void heev_carve(char* p, int m_max, int n_max, HeevWork& w);
+void* heev_plans_new();
+void heev_plans_free(void* plans);
+// X (m x N, stride ld) <- X V with V the eigenvectors of X^H X, computed in FP64.
+template <typename T>
+void heev_precondition(C2<T>* X, int m, int N, int ld, HeevWork& w, Profiler& pf, hipStream_t st);
+// Eigenvalues (ascending) and eigenvectors of a host Hermitian matrix (row-major,
+// interleaved complex), through the same kernels.
+void heev_host(int N, const double* G, double* w, double* V, HeevWork& work, Profiler& pf, hipStream_t st);
+
 struct JacobiWork {
     void* gram_partials;   // P_max * splits * 64*64 complex (T)
     void* w;               // P_max * 64*64 complex (T)
@@ -162,6 +196,9 @@ struct JacobiWork {
     bool graphs;           // replay captured sweeps (hipGraph) speculatively, one read per batch
     void* graph_cache;     // captured sweep per shape (owned by the handle)
     long long n_splits, n_sweeps, n_rounds, n_rotations;   // running counters
+    HeevWork* heev;        // Gram eigen-decomposition start (null = plain sweeps)
+    int precond_min;       // start from it for splits with at least this many columns
+    long long n_precond;   // splits that started from it
 };
 
 // One-sided block Jacobi on the columns of X (m x N, column stride ld >= m).  On return

@@ -1,0 +1,1192 @@
+// Hermitian eigen-decomposition of a split's Gram matrix, used to hand the
+// one-sided Jacobi SVD a starting basis whose columns are already orthogonal
+// to about the eigen-solver's accuracy (App. A: the truncated SVD of the
+// two-site block; its right singular vectors are the eigenvectors of
+// theta'^H theta').  With that basis the Jacobi sweeps only polish: in FP64
+// storage one rotating sweep and a check, in FP32 storage a check.
+//
+//   G = X^H X                  FP64 MFMA
+//   G = Q_H T Q_H^H            blocked Householder tridiagonalisation (panels of
+//                              kTrdNb columns, rank-2*kTrdNb trailing updates on MFMA)
+//   T = Z diag(lambda) Z^T     divide and conquer on the real tridiagonal
+//                              (rank-one tearing, secular equation per root,
+//                              Gu-Eisenstat vectors, MFMA merge products)
+//   X <- X Q_H Z               blocked reflectors (compact WY) + real MFMA GEMM
+//
+// Everything runs in FP64 whatever the storage precision of X: X is copied to
+// FP64 first and the final product is rounded to the storage precision.  The
+// columns of the result are then orthogonal relative to their own norms, so
+// small singular values are resolved as well as the FP64 Gram allows.
+#include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <vector>
+
+#include "common.h"
+
+namespace mpo {
+
+namespace {
+
+constexpr int kPart = 64;          // row chunks of the tridiagonalisation's vector kernels
+constexpr int kGemvWaves = 16;     // waves per work-group of the trailing matrix-vector product
+constexpr int kBtNb = 64;          // reflectors per block of the back-transformation
+constexpr int kSplitK = 256;       // K chunk of the split-K products
+
+// ------------------------------------------------------------ wave reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_prod(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of one value per thread over a work-group of NT threads (fixed tree).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) s += red[q];
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ double2 zcmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ double2 zmulc(double2 a, double2 b) {
+    return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+// ------------------------------------------------------------ booked launches
+// A launch that, with profiling on, carries start/stop events stamped by the
+// dispatch itself (hipExtLaunchKernel) and is booked under class cls.
+template <typename K, typename... Args>
+void launch_booked(Profiler& pf, int cls, double fl, double by, K kernel, dim3 g, dim3 b, size_t lds,
+                   hipStream_t st, Args... args) {
+    if (pf.on) {
+        hipEvent_t a = nullptr, e = nullptr;
+        pf.stamps(a, e);
+        hipExtLaunchKernelGGL(kernel, g, b, lds, st, a, e, 0, args...);
+        pf.record(cls, a, e, fl, by);
+    } else {
+        hipLaunchKernelGGL(kernel, g, b, lds, st, args...);
+    }
+}
+
+// ------------------------------------------------------------ complex GEMM
+// C = op(A) op(B) (MODE 0) or C -= op(A) op(B) (MODE 1), FP64 complex, 64x64
+// tiles, 4 waves of 2x2 16x16 MFMA tiles.  blockIdx.z selects a batch entry:
+// the operands are offset by z times their strides and, with kchunk > 0, the
+// entry covers K range [z*kchunk, min(K, (z+1)*kchunk)) (split-K partials).
+constexpr int ZBM = 64, ZBN = 64, ZBK = 16;
+
+template <int OPA, int OPB, int MODE>
+__global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, int kchunk, const double2* __restrict__ A,
+                                               int lda, size_t sA, const double2* __restrict__ B, int ldb,
+                                               size_t sB, double2* __restrict__ C, int ldc, size_t sC) {
+    __shared__ double2 As[ZBK][ZBM + 1];
+    __shared__ double2 Bs[ZBK][ZBN + 1];
+    const int z = blockIdx.z;
+    A += sA * z;
+    B += sB * z;
+    C += sC * z;
+    if (kchunk > 0) K = min(kchunk, K - z * kchunk);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int m0 = blockIdx.x * ZBM, n0 = blockIdx.y * ZBN;
+    d4 accR[2][2], accI[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = 0.0; accI[bi][bj][r] = 0.0; }
+    for (int k0 = 0; k0 < K; k0 += ZBK) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = t + 256 * r;
+            int i, k;
+            if (OPA == 0) { i = e & 63; k = e >> 6; } else { k = e & 15; i = e >> 4; }
+            const int gi = m0 + i, gk = k0 + k;
+            double2 v = make_double2(0.0, 0.0);
+            if (gi < M && gk < K) {
+                v = OPA == 0 ? A[gi + (size_t)gk * lda] : A[gk + (size_t)gi * lda];
+                if (OPA == 1) v.y = -v.y;
+            }
+            As[k][i] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = t + 256 * r;
+            int j, k;
+            if (OPB == 0) { k = e & 15; j = e >> 4; } else { j = e & 63; k = e >> 6; }
+            const int gj = n0 + j, gk = k0 + k;
+            double2 v = make_double2(0.0, 0.0);
+            if (gj < N && gk < K) {
+                v = OPB == 0 ? B[gk + (size_t)gj * ldb] : B[gj + (size_t)gk * ldb];
+                if (OPB == 1) v.y = -v.y;
+            }
+            Bs[k][j] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < ZBK; kk += 4) {
+            double2 a[2], b[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                a[q] = As[kk + (lane >> 4)][wm * 32 + q * 16 + (lane & 15)];
+                b[q] = Bs[kk + (lane >> 4)][wn * 32 + q * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    accR[bi][bj] = mfma16(a[bi].x, b[bj].x, accR[bi][bj]);
+                    accR[bi][bj] = mfma16(-a[bi].y, b[bj].y, accR[bi][bj]);
+                    accI[bi][bj] = mfma16(a[bi].x, b[bj].y, accI[bi][bj]);
+                    accI[bi][bj] = mfma16(a[bi].y, b[bj].x, accI[bi][bj]);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = m0 + wm * 32 + bi * 16 + acc_row<double>(lane, r);
+                const int j = n0 + wn * 32 + bj * 16 + (lane & 15);
+                if (i < M && j < N) {
+                    double2* c = C + i + (size_t)j * ldc;
+                    if (MODE == 0) *c = make_double2(accR[bi][bj][r], accI[bi][bj][r]);
+                    else *c = make_double2(c->x - accR[bi][bj][r], c->y - accI[bi][bj][r]);
+                }
+            }
+}
+
+template <int OPA, int OPB, int MODE>
+void zgemm(int M, int N, int K, const double2* A, int lda, const double2* B, int ldb, double2* C, int ldc,
+           hipStream_t st, int batches = 1, int kchunk = 0, size_t sA = 0, size_t sB = 0, size_t sC = 0,
+           Profiler* pf = nullptr, int cls = 0) {
+    if (M <= 0 || N <= 0 || batches <= 0) return;
+    dim3 grid((M + ZBM - 1) / ZBM, (N + ZBN - 1) / ZBN, batches);
+    if (pf && pf->on) {
+        hipEvent_t a = nullptr, e = nullptr;
+        pf->stamps(a, e);
+        hipExtLaunchKernelGGL((k_zgemm<OPA, OPB, MODE>), grid, dim3(256), 0, st, a, e, 0, M, N, K, kchunk, A, lda,
+                              sA, B, ldb, sB, C, ldc, sC);
+        const double kk = kchunk > 0 ? (double)K : (double)K * batches;
+        pf->record(cls, a, e, 8.0 * M * N * kk, 16.0 * ((double)M * kk + (double)N * kk + (MODE + 1.0) * M * N * batches));
+    } else {
+        hipLaunchKernelGGL((k_zgemm<OPA, OPB, MODE>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, sA, B, ldb,
+                           sB, C, ldc, sC);
+    }
+}
+
+// ------------------------------------------------------------ real GEMM
+// One 64x64 tile of C = A B, FP64, A's columns optionally through a map
+// (absolute column indices), output converted to TO.
+template <typename TO>
+__device__ __forceinline__ TO to_out(double v) { return (TO)v; }
+
+template <typename TO, bool MAP>
+__device__ __forceinline__ void dgemm_tile(int M, int N, int K, const double* __restrict__ A, int lda,
+                                           const int* __restrict__ amap, const double* __restrict__ B, int ldb,
+                                           TO* __restrict__ C, int ldc, int m0, int n0) {
+    __shared__ double As[ZBK][ZBM + 1];
+    __shared__ double Bs[ZBK][ZBN + 1];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    d4 acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[bi][bj][r] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += ZBK) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = t + 256 * r;
+            const int i = e & 63, k = e >> 6;
+            const int gi = m0 + i, gk = k0 + k;
+            double v = 0.0;
+            if (gi < M && gk < K) v = A[gi + (size_t)(MAP ? amap[gk] : gk) * lda];
+            As[k][i] = v;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = t + 256 * r;
+            const int k = e & 15, j = e >> 4;
+            const int gj = n0 + j, gk = k0 + k;
+            Bs[k][j] = (gj < N && gk < K) ? B[gk + (size_t)gj * ldb] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < ZBK; kk += 4) {
+            double a[2], b[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                a[q] = As[kk + (lane >> 4)][wm * 32 + q * 16 + (lane & 15)];
+                b[q] = Bs[kk + (lane >> 4)][wn * 32 + q * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma16(a[bi], b[bj], acc[bi][bj]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = m0 + wm * 32 + bi * 16 + acc_row<double>(lane, r);
+                const int j = n0 + wn * 32 + bj * 16 + (lane & 15);
+                if (i < M && j < N) C[i + (size_t)j * ldc] = to_out<TO>(acc[bi][bj][r]);
+            }
+}
+
+template <typename TO>
+__global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, const double* __restrict__ A, int lda,
+                                               const double* __restrict__ B, int ldb, TO* __restrict__ C,
+                                               int ldc) {
+    dgemm_tile<TO, false>(M, N, K, A, lda, nullptr, B, ldb, C, ldc, blockIdx.x * ZBM, blockIdx.y * ZBN);
+}
+
+// ------------------------------------------------------------ Gram, copies
+template <typename T>
+__global__ __launch_bounds__(256) void k_to_f64(const C2<T>* __restrict__ X, int m, int ld, double2* __restrict__ Xd,
+                                                int ldd) {
+    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    if (i < m) Xd[i + (size_t)ldd * j] = to_d2(X[i + (size_t)ld * j]);
+}
+
+__global__ void k_fill_z(double2* p, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = make_double2(0.0, 0.0);
+}
+
+// ------------------------------------------- Householder tridiagonalisation
+// Lower storage of the Hermitian G (both triangles kept valid by the trailing
+// updates).  Reflector j: H_j = I - tau_j v v^H with v[0..j] = 0, v[j+1] = 1,
+// beta_j = -sign(Re alpha) ||G[j+1:, j]|| real, so that T is real symmetric
+// with diagonal d and off-diagonal e.  Within a panel (columns j0..j0+nb-1)
+// the trailing matrix is left as it was at the panel start and corrected on
+// the fly by the panel's V and W (G_eff = G - V W^H - W V^H); after the panel
+// it is updated once by a rank-2 nb product on MFMA.
+
+struct House { double2 tau, scale; double beta; };
+
+// Reflector scalars of column j from alpha = G[j+1, j] and ||G[j+2:, j]||^2.
+__device__ __forceinline__ House house_scalars(double2 alpha, double xnorm2) {
+    House h;
+    if (xnorm2 == 0.0 && alpha.y == 0.0) {
+        h.tau = make_double2(0.0, 0.0);
+        h.scale = make_double2(0.0, 0.0);
+        h.beta = alpha.x;
+        return h;
+    }
+    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xnorm2);
+    const double beta = alpha.x >= 0.0 ? -nrm : nrm;
+    h.beta = beta;
+    h.tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+    const double2 den = make_double2(alpha.x - beta, alpha.y);   // |den| >= |beta|: no cancellation
+    const double dd = den.x * den.x + den.y * den.y;
+    h.scale = make_double2(den.x / dd, -den.y / dd);
+    return h;
+}
+
+// Row chunk of kPart work-groups over [r0, N).
+__device__ __forceinline__ void part_rows(int r0, int N, int& a, int& b) {
+    const int len = N - r0;
+    const int ch = len > 0 ? (len + kPart - 1) / kPart : 0;
+    a = r0 + (int)blockIdx.x * ch;
+    b = min(N, a + ch);
+}
+
+// Panel start: partial sums of ||G[j+2:, j]||^2 (column j needs no panel update).
+__global__ __launch_bounds__(256) void k_trd_colnorm(const double2* __restrict__ G, int ldg, int N, int j,
+                                                     double* __restrict__ part) {
+    __shared__ double red[4];
+    int a, b;
+    part_rows(j + 2, N, a, b);
+    double s = 0.0;
+    for (int i = a + (int)threadIdx.x; i < b; i += 256) {
+        const double2 v = G[i + (size_t)ldg * j];
+        s += v.x * v.x + v.y * v.y;
+    }
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Column j of the panel (c = j - j0): the reflector from the updated column
+// (scalars recomputed identically in every work-group), then
+//   y_raw = G[j+1:, j+1:] v        (panel-start trailing matrix; one wave per column,
+//                                   y_i = conj(G[:, i]) . v by Hermitian symmetry)
+//   dots  = W^H v (first c), V^H v (at kTrdNb + c')
+// Work-group 0 also stores the reflector in the panel buffers and tau_j, e_j, d_j.
+__global__ __launch_bounds__(1024) void k_trd_gemv(const double2* __restrict__ G, int ldg, int N, int j, int c,
+                                                   const double* __restrict__ part, double2* __restrict__ VW,
+                                                   double2* __restrict__ WV, double2* __restrict__ yraw,
+                                                   double2* __restrict__ dots, double2* __restrict__ tau,
+                                                   double* __restrict__ d, double* __restrict__ e) {
+    extern __shared__ double2 vs[];      // v[j+1 .. N)
+    const int len = N - j - 1;
+    const int tid = threadIdx.x;
+    double xn2 = 0.0;
+    for (int q = 0; q < kPart; ++q) xn2 += part[q];
+    const double2 alpha = G[(j + 1) + (size_t)ldg * j];
+    const House h = house_scalars(alpha, xn2);
+    for (int r = tid; r < len; r += 1024)
+        vs[r] = r == 0 ? make_double2(1.0, 0.0) : zmul(G[(j + 1 + r) + (size_t)ldg * j], h.scale);
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        if (tid == 0) {
+            tau[j] = h.tau;
+            e[j] = h.beta;
+            d[j] = G[j + (size_t)ldg * j].x;
+        }
+        for (int r = tid; r < N; r += 1024) {
+            const double2 v = r <= j ? make_double2(0.0, 0.0) : vs[r - j - 1];
+            VW[r + (size_t)N * c] = v;
+            WV[r + (size_t)N * (kTrdNb + c)] = v;
+        }
+    }
+    const int wave = blockIdx.x * kGemvWaves + (tid >> 6), lane = tid & 63;
+    if (wave >= len + 2 * c) return;
+    const double2* src;
+    if (wave < len) src = G + (size_t)ldg * (j + 1 + wave) + (j + 1);
+    else if (wave - len < c) src = VW + (size_t)N * (kTrdNb + (wave - len)) + (j + 1);   // W column
+    else src = VW + (size_t)N * (wave - len - c) + (j + 1);                              // V column
+    double sr = 0.0, si = 0.0;
+    for (int r = lane; r < len; r += 64) {
+        const double2 a = src[r], b = vs[r];
+        sr += a.x * b.x + a.y * b.y;
+        si += a.x * b.y - a.y * b.x;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) {
+        const double2 out = make_double2(sr, si);
+        if (wave < len) yraw[j + 1 + wave] = out;
+        else if (wave - len < c) dots[wave - len] = out;
+        else dots[kTrdNb + (wave - len - c)] = out;
+    }
+}
+
+// y = y_raw - V (W^H v) - W (V^H v); w~ = tau_j y; partial sums of w~^H v;
+// the reflector is stored below the diagonal of G (G[j+1, j] = 1).
+__global__ __launch_bounds__(256) void k_trd_corr(double2* __restrict__ G, int ldg, int N, int j, int c,
+                                                  const double2* __restrict__ tau, const double2* __restrict__ VW,
+                                                  const double2* __restrict__ dots,
+                                                  const double2* __restrict__ yraw, double2* __restrict__ wt,
+                                                  double* __restrict__ part2) {
+    __shared__ double red[4];
+    int a, b;
+    part_rows(j + 1, N, a, b);
+    const double2 tj = tau[j];
+    double sr = 0.0, si = 0.0;
+    for (int i = a + (int)threadIdx.x; i < b; i += 256) {
+        double2 y = yraw[i];
+        for (int q = 0; q < c; ++q) {
+            const double2 t1 = zmul(VW[i + (size_t)N * q], dots[q]);
+            const double2 t2 = zmul(VW[i + (size_t)N * (kTrdNb + q)], dots[kTrdNb + q]);
+            y.x -= t1.x + t2.x;
+            y.y -= t1.y + t2.y;
+        }
+        const double2 w = zmul(tj, y);
+        wt[i] = w;
+        const double2 v = VW[i + (size_t)N * c];
+        const double2 p = zcmul(w, v);
+        sr += p.x;
+        si += p.y;
+        G[i + (size_t)ldg * j] = v;
+    }
+    sr = block_sum<256>(sr, red);
+    si = block_sum<256>(si, red);
+    if (threadIdx.x == 0) {
+        part2[2 * blockIdx.x] = sr;
+        part2[2 * blockIdx.x + 1] = si;
+    }
+}
+
+// w = w~ + alpha v with alpha = -tau_j (w~^H v) / 2 into the panel buffers
+// (zero above row j+1); if the panel continues, column j+1 is brought up to
+// date, G[j+1:, j+1] -= V conj(W[j+1, :]) + W conj(V[j+1, :]), and the partial
+// sums of ||G[j+3:, j+1]||^2 are formed for its reflector.
+__global__ __launch_bounds__(256) void k_trd_next(double2* __restrict__ G, int ldg, int N, int j, int c,
+                                                  int update_next, const double2* __restrict__ tau,
+                                                  double2* __restrict__ VW, double2* __restrict__ WV,
+                                                  const double2* __restrict__ wt,
+                                                  const double* __restrict__ part2, double* __restrict__ part) {
+    __shared__ double red[4];
+    double s_r = 0.0, s_i = 0.0;
+    for (int q = 0; q < kPart; ++q) { s_r += part2[2 * q]; s_i += part2[2 * q + 1]; }
+    const double2 tj = tau[j];
+    const double2 ts = zmul(tj, make_double2(s_r, s_i));
+    const double2 al = make_double2(-0.5 * ts.x, -0.5 * ts.y);
+    int a, b;
+    part_rows(0, N, a, b);
+    // W[j+1, c] = w~[j+1] + alpha (v[j+1] = 1), needed by every row of the column update
+    double2 wj1 = make_double2(0.0, 0.0);
+    if (j + 1 < N) { wj1 = wt[j + 1]; wj1.x += al.x; wj1.y += al.y; }
+    double nrm = 0.0;
+    for (int i = a + (int)threadIdx.x; i < b; i += 256) {
+        double2 w = make_double2(0.0, 0.0);
+        if (i > j) {
+            const double2 v = VW[i + (size_t)N * c];
+            w = wt[i];
+            const double2 av = zmul(al, v);
+            w.x += av.x;
+            w.y += av.y;
+        }
+        VW[i + (size_t)N * (kTrdNb + c)] = w;
+        WV[i + (size_t)N * c] = w;
+        if (update_next && i >= j + 1) {
+            double2 g = G[i + (size_t)ldg * (j + 1)];
+            for (int q = 0; q <= c; ++q) {
+                const double2 vi = VW[i + (size_t)N * q];
+                const double2 wi = q == c ? w : VW[i + (size_t)N * (kTrdNb + q)];
+                const double2 vr = VW[(j + 1) + (size_t)N * q];
+                const double2 wr = q == c ? wj1 : VW[(j + 1) + (size_t)N * (kTrdNb + q)];
+                const double2 t1 = zmulc(vi, wr), t2 = zmulc(wi, vr);
+                g.x -= t1.x + t2.x;
+                g.y -= t1.y + t2.y;
+            }
+            G[i + (size_t)ldg * (j + 1)] = g;
+            if (i >= j + 3) nrm += g.x * g.x + g.y * g.y;
+        }
+    }
+    if (update_next) {
+        nrm = block_sum<256>(nrm, red);
+        if (threadIdx.x == 0) part[blockIdx.x] = nrm;
+    }
+}
+
+__global__ void k_trd_last(const double2* __restrict__ G, int ldg, int N, double* __restrict__ d) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) d[N - 1] = G[(N - 1) + (size_t)ldg * (N - 1)].x;
+}
+
+// ----------------------------------------------------- divide and conquer
+// T = diag(T1', T2') + |beta| u u^T, u = [e_last; sign(beta) e_first] at every
+// internal node of a halving tree with leaves of size 1 (the diagonal entries
+// on both sides of every coupling lose |beta|).  A merge with children
+// T1' = Q1 D1 Q1^T, T2' = Q2 D2 Q2^T solves D + rho z z^T, z = [Q1^T e_last;
+// sign(beta) Q2^T e_first] / sqrt(2), rho = 2|beta|:
+//   deflation   rho |z_i| <= tol: (d_i, e_i) is an eigenpair; two close values
+//               are rotated so that one z component vanishes (tol = 8 eps
+//               max(|d|, rho));
+//   roots       one per interval (delta_j, delta_{j+1}) (the last in
+//               (delta_{k-1}, delta_{k-1} + rho |z|^2]), found by bisection in
+//               the coordinate of the nearer pole, so that delta_i - lambda_j
+//               keeps full relative accuracy;
+//   vectors     z recomputed from the roots (Gu-Eisenstat), u_j = zhat /
+//               (delta - lambda_j) normalised: orthogonal to working accuracy;
+//   product     [Q1 0; 0 Q2] (rotated, deflated columns removed) times U on MFMA.
+// Eigenvalues are kept in ascending order within every node.
+
+__global__ void k_dc_init(int N, const double* __restrict__ d, const double* __restrict__ e,
+                          double* __restrict__ dv, double* __restrict__ Z) {
+    const size_t nn = (size_t)N * N;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nn; q += stride) {
+        const size_t i = q % N, k = q / N;
+        Z[q] = i == k ? 1.0 : 0.0;
+        if (k == 0) {
+            double v = d[i];
+            if (i >= 1) v -= fabs(e[i - 1]);
+            if (i + 1 < (size_t)N) v -= fabs(e[i]);
+            dv[i] = v;
+        }
+    }
+}
+
+struct DcMerge { int lo, n1, n2, id; };
+
+// number of entries of sorted a[0..n) below x (strict) / at most x
+__device__ __forceinline__ int count_less(const double* a, int n, double x) {
+    int lo = 0, hi = n;
+    while (lo < hi) { const int mid = (lo + hi) >> 1; if (a[mid] < x) lo = mid + 1; else hi = mid; }
+    return lo;
+}
+__device__ __forceinline__ int count_le(const double* a, int n, double x) {
+    int lo = 0, hi = n;
+    while (lo < hi) { const int mid = (lo + hi) >> 1; if (a[mid] <= x) lo = mid + 1; else hi = mid; }
+    return lo;
+}
+
+struct DcBuf {
+    double *dv, *ds, *dz, *ndv, *ndz, *dfv, *taus, *lam, *zh;
+    int *dcol, *ndc, *dfc, *orig, *perm;
+    int2* rot_ab;
+    double2* rot_cs;
+    int *mk, *mnrot;
+    double* mrho;
+};
+
+// One work-group per merge: z, the merged ascending order, and the deflation
+// scan (sequential, thread 0).
+__global__ __launch_bounds__(1024) void k_dc_prep(const DcMerge* __restrict__ plan, int N,
+                                                  const double* __restrict__ e, const double* __restrict__ Z,
+                                                  DcBuf b) {
+    const DcMerge mg = plan[blockIdx.x];
+    const int lo = mg.lo, n1 = mg.n1, n2 = mg.n2, n = n1 + n2;
+    const double beta = e[lo + n1 - 1];
+    const double rho = 2.0 * fabs(beta);
+    const double sg = beta < 0.0 ? -1.0 : 1.0;
+    const double r2 = 0.70710678118654752440;
+    const double* dl = b.dv + lo;
+    const double* dr = b.dv + lo + n1;
+    for (int t = threadIdx.x; t < n; t += 1024) {
+        double val, zt;
+        int pos;
+        if (t < n1) {
+            val = dl[t];
+            pos = t + count_less(dr, n2, val);
+            zt = Z[(lo + n1 - 1) + (size_t)N * (lo + t)] * r2;
+        } else {
+            const int u = t - n1;
+            val = dr[u];
+            pos = u + count_le(dl, n1, val);
+            zt = sg * Z[(lo + n1) + (size_t)N * (lo + t)] * r2;
+        }
+        b.ds[lo + pos] = val;
+        b.dz[lo + pos] = zt;
+        b.dcol[lo + pos] = lo + t;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double dmax = fmax(fabs(b.ds[lo]), fabs(b.ds[lo + n - 1]));
+    const double tol = 8.0 * 2.220446049250313e-16 * fmax(dmax, rho);
+    int k = 0, nd = 0, nrot = 0;
+    for (int t = 0; t < n; ++t) {
+        double dt = b.ds[lo + t], zt = b.dz[lo + t];
+        const int ct = b.dcol[lo + t];
+        if (rho * fabs(zt) <= tol) {
+            b.dfv[lo + nd] = dt;
+            b.dfc[lo + nd] = ct;
+            ++nd;
+            continue;
+        }
+        if (k > 0) {
+            const double dlast = b.ndv[lo + k - 1], zlast = b.ndz[lo + k - 1];
+            const int clast = b.ndc[lo + k - 1];
+            const double tt = hypot(zlast, zt);
+            const double cc = zt / tt, ss = -zlast / tt;
+            if (fabs((dt - dlast) * cc * ss) <= tol) {
+                b.rot_ab[lo + nrot] = make_int2(clast, ct);
+                b.rot_cs[lo + nrot] = make_double2(cc, ss);
+                ++nrot;
+                const double dnl = dlast * cc * cc + dt * ss * ss;
+                const double dnt = dlast * ss * ss + dt * cc * cc;
+                --k;
+                b.dfv[lo + nd] = dnl;
+                b.dfc[lo + nd] = clast;
+                ++nd;
+                dt = dnt;
+                zt = tt;
+            }
+        }
+        b.ndv[lo + k] = dt;
+        b.ndz[lo + k] = zt;
+        b.ndc[lo + k] = ct;
+        ++k;
+    }
+    b.mk[mg.id] = k;
+    b.mnrot[mg.id] = nrot;
+    b.mrho[mg.id] = rho;
+}
+
+// The deflation rotations on the merge's block rows, in scan order.
+__global__ __launch_bounds__(256) void k_dc_rot(const DcMerge* __restrict__ plan, int N, double* __restrict__ Z,
+                                                DcBuf b) {
+    const DcMerge mg = plan[blockIdx.y];
+    const int n = mg.n1 + mg.n2, nrot = b.mnrot[mg.id];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= n || nrot == 0) return;
+    const size_t row = mg.lo + r;
+    for (int q = 0; q < nrot; ++q) {
+        const int2 ab = b.rot_ab[mg.lo + q];
+        const double2 cs = b.rot_cs[mg.lo + q];
+        double* pa = Z + row + (size_t)N * ab.x;
+        double* pb = Z + row + (size_t)N * ab.y;
+        const double za = *pa, zb = *pb;
+        *pa = cs.x * za + cs.y * zb;
+        *pb = -cs.y * za + cs.x * zb;
+    }
+}
+
+// Roots of 1 + rho sum_i z_i^2 / (delta_i - lambda): one wave per root, the
+// poles of the merge staged in LDS.
+__global__ __launch_bounds__(256) void k_dc_secular(const DcMerge* __restrict__ plan, DcBuf b) {
+    __shared__ double sd[4096];
+    __shared__ double sz[4096];
+    const DcMerge mg = plan[blockIdx.y];
+    const int k = b.mk[mg.id];
+    if ((int)blockIdx.x * 4 >= k) return;
+    const int lo = mg.lo;
+    for (int i = threadIdx.x; i < k; i += 256) {
+        sd[i] = b.ndv[lo + i];
+        const double z = b.ndz[lo + i];
+        sz[i] = z * z;
+    }
+    __syncthreads();
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= k) return;
+    const double rho = b.mrho[mg.id];
+    double zs = 0.0;
+    for (int i = lane; i < k; i += 64) zs += sz[i];
+    zs = wave_sum(zs);
+    int o;
+    double sgn, lo_s, hi_s;
+    if (j < k - 1) {
+        const double h = sd[j + 1] - sd[j];
+        double f = 0.0;
+        for (int i = lane; i < k; i += 64) f += sz[i] / ((sd[i] - sd[j]) - 0.5 * h);
+        f = 1.0 + rho * wave_sum(f);
+        const double den = 1.0 + 2.0 * rho * zs / h;
+        if (f >= 0.0) { o = j; sgn = 1.0; lo_s = rho * sz[j] / den; }
+        else { o = j + 1; sgn = -1.0; lo_s = rho * sz[j + 1] / den; }
+        hi_s = 0.5 * h;
+    } else {
+        o = j;
+        sgn = 1.0;
+        hi_s = rho * zs;
+        lo_s = 0.5 * rho * sz[j];
+    }
+    lo_s = fmin(lo_s, hi_s);
+    const double dor = sd[o];
+    for (int it = 0; it < 400; ++it) {
+        const double mid = (lo_s > 0.0 && hi_s > 64.0 * lo_s) ? sqrt(lo_s * hi_s)
+                         : (lo_s > 0.0 ? 0.5 * (lo_s + hi_s) : 0.5 * hi_s);
+        if (!(mid > lo_s && mid < hi_s)) break;
+        const double tau = sgn * mid;
+        double g = 0.0;
+        for (int i = lane; i < k; i += 64) g += sz[i] / ((sd[i] - dor) - tau);
+        g = 1.0 + rho * wave_sum(g);
+        if ((g >= 0.0) == (sgn > 0.0)) hi_s = mid;
+        else lo_s = mid;
+    }
+    if (lane == 0) {
+        const double tau = sgn * 0.5 * (lo_s + hi_s);
+        b.taus[lo + j] = tau;
+        b.orig[lo + j] = o;
+        b.lam[lo + j] = dor + tau;
+    }
+}
+
+// zhat_i^2 = (lambda_i - delta_i)/rho * prod_{j != i} (lambda_j - delta_i) / (delta_j - delta_i)
+__global__ __launch_bounds__(256) void k_dc_zhat(const DcMerge* __restrict__ plan, DcBuf b) {
+    __shared__ double sd[4096];
+    const DcMerge mg = plan[blockIdx.y];
+    const int k = b.mk[mg.id];
+    if ((int)blockIdx.x * 4 >= k) return;
+    const int lo = mg.lo;
+    for (int i = threadIdx.x; i < k; i += 256) sd[i] = b.ndv[lo + i];
+    __syncthreads();
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= k) return;
+    const double rho = b.mrho[mg.id];
+    const double di = sd[i];
+    double p = 1.0;
+    for (int q = lane; q < k; q += 64) {
+        const double lq = b.taus[lo + q] - (di - sd[b.orig[lo + q]]);   // lambda_q - delta_i
+        p *= q == i ? lq / rho : lq / (sd[q] - di);
+    }
+    p = wave_prod(p);
+    if (lane == 0) b.zh[lo + i] = copysign(sqrt(fmax(p, 0.0)), b.ndz[lo + i]);
+}
+
+// U[:, j] = zhat / (delta - lambda_j), normalised (one wave per column).
+__global__ __launch_bounds__(256) void k_dc_vec(const DcMerge* __restrict__ plan, int N, double* __restrict__ U,
+                                                DcBuf b) {
+    __shared__ double sd[4096];
+    __shared__ double sz[4096];
+    const DcMerge mg = plan[blockIdx.y];
+    const int k = b.mk[mg.id];
+    if ((int)blockIdx.x * 4 >= k) return;
+    const int lo = mg.lo;
+    for (int i = threadIdx.x; i < k; i += 256) { sd[i] = b.ndv[lo + i]; sz[i] = b.zh[lo + i]; }
+    __syncthreads();
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= k) return;
+    const double tau = b.taus[lo + j], dor = sd[b.orig[lo + j]];
+    double s = 0.0;
+    for (int i = lane; i < k; i += 64) {
+        const double u = sz[i] / ((sd[i] - dor) - tau);
+        s += u * u;
+    }
+    s = wave_sum(s);
+    const double inv = 1.0 / sqrt(s);
+    double* col = U + lo + (size_t)N * (lo + j);
+    for (int i = lane; i < k; i += 64) col[i] = sz[i] / ((sd[i] - dor) - tau) * inv;
+}
+
+// Z2[lo.., lo + j] = Z[lo.., ndc[i]] U[i, j] over the non-deflated columns.
+__global__ __launch_bounds__(256) void k_dc_gemm(const DcMerge* __restrict__ plan, int N,
+                                                 const double* __restrict__ Z, const double* __restrict__ U,
+                                                 double* __restrict__ Z2, DcBuf b) {
+    const DcMerge mg = plan[blockIdx.z];
+    const int k = b.mk[mg.id], n = mg.n1 + mg.n2, lo = mg.lo;
+    const int m0 = blockIdx.x * ZBM, n0 = blockIdx.y * ZBN;
+    if (m0 >= n || n0 >= k) return;
+    dgemm_tile<double, true>(n, k, k, Z + lo, N, b.ndc + lo, U + lo + (size_t)N * lo, N,
+                             Z2 + lo + (size_t)N * lo, N, m0, n0);
+}
+
+// Deflated columns after the roots' columns: Z2[lo.., lo + k + u] = Z[lo.., dfc[u]].
+__global__ __launch_bounds__(256) void k_dc_defl(const DcMerge* __restrict__ plan, int N,
+                                                 const double* __restrict__ Z, double* __restrict__ Z2, DcBuf b) {
+    const DcMerge mg = plan[blockIdx.y];
+    const int k = b.mk[mg.id], n = mg.n1 + mg.n2, lo = mg.lo;
+    const int u = blockIdx.x;
+    if (u >= n - k) return;
+    const double* src = Z + (size_t)N * b.dfc[lo + u] + lo;
+    double* dst = Z2 + (size_t)N * (lo + k + u) + lo;
+    for (int r = threadIdx.x; r < n; r += 256) dst[r] = src[r];
+}
+
+// All n eigenvalues of the merge (roots, then deflated values) in ascending
+// order (bitonic, ties by position); perm[r] is the Z2 column of the r-th.
+__global__ __launch_bounds__(1024) void k_dc_sort(const DcMerge* __restrict__ plan, DcBuf b) {
+    __shared__ double sv[4096];
+    __shared__ int si[4096];
+    const DcMerge mg = plan[blockIdx.x];
+    const int k = b.mk[mg.id], n = mg.n1 + mg.n2, lo = mg.lo;
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int t = threadIdx.x; t < P; t += 1024) {
+        si[t] = t;
+        sv[t] = t < k ? b.lam[lo + t] : (t < n ? b.dfv[lo + t - k] : INFINITY);
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < P; t += 1024) {
+                const int pr = t ^ stride;
+                if (pr > t) {
+                    const bool up = (t & size) == 0;
+                    const double a = sv[t], c = sv[pr];
+                    const int ia = si[t], ic = si[pr];
+                    const bool gt = a > c || (a == c && ia > ic);
+                    if (gt == up) { sv[t] = c; sv[pr] = a; si[t] = ic; si[pr] = ia; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < n; t += 1024) {
+        b.dv[lo + t] = sv[t];
+        b.perm[lo + t] = lo + si[t];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dc_perm(const DcMerge* __restrict__ plan, int N, double* __restrict__ Z,
+                                                 const double* __restrict__ Z2, DcBuf b) {
+    const DcMerge mg = plan[blockIdx.y];
+    const int n = mg.n1 + mg.n2, lo = mg.lo;
+    const int r = blockIdx.x;
+    if (r >= n) return;
+    const double* src = Z2 + (size_t)N * b.perm[lo + r] + lo;
+    double* dst = Z + (size_t)N * (lo + r) + lo;
+    for (int q = threadIdx.x; q < n; q += 256) dst[q] = src[q];
+}
+
+// --------------------------------------------------- back-transformation
+// Y = [v_j0 .. v_j0+nb-1] (N x kBtNb, zero-padded) from the reflectors below the diagonal.
+__global__ __launch_bounds__(256) void k_bt_y(const double2* __restrict__ G, int ldg, int N, int j0, int nbb,
+                                              double2* __restrict__ Y) {
+    const int i = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+    if (i >= N) return;
+    const int j = j0 + c;
+    double2 v = make_double2(0.0, 0.0);
+    if (c < nbb && i > j) v = G[i + (size_t)ldg * j];
+    Y[i + (size_t)N * c] = v;
+}
+
+// T of H_j0 .. H_j0+nb-1 = I - Y T Y^H (forward, columnwise): T[i][i] = tau_i,
+// T[0:i, i] = -tau_i T[0:i, 0:i] (Y^H Y)[0:i, i]; S = Y^H Y from split-K partials.
+__global__ __launch_bounds__(1024) void k_bt_t(const double2* __restrict__ Spart, int splits,
+                                               const double2* __restrict__ tau, int j0, int nbb,
+                                               double2* __restrict__ Tm) {
+    __shared__ double2 S[kBtNb][kBtNb + 1];
+    __shared__ double2 T[kBtNb][kBtNb + 1];   // T[r][c]
+    for (int q = threadIdx.x; q < kBtNb * kBtNb; q += 1024) {
+        const int r = q % kBtNb, c = q / kBtNb;
+        double2 s = make_double2(0.0, 0.0);
+        for (int z = 0; z < splits; ++z) {
+            const double2 v = Spart[(size_t)z * kBtNb * kBtNb + r + kBtNb * c];
+            s.x += v.x;
+            s.y += v.y;
+        }
+        S[r][c] = s;
+        T[r][c] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int i = 0; i < nbb; ++i) {
+        const double2 ti = tau[j0 + i];
+        // T[r][i] = -tau_i sum_{q=r}^{i-1} T[r][q] S[q][i]  for r < i
+        const int r = threadIdx.x;
+        double2 acc = make_double2(0.0, 0.0);
+        if (r < i) {
+            for (int q = r; q < i; ++q) {
+                const double2 p = zmul(T[r][q], S[q][i]);
+                acc.x += p.x;
+                acc.y += p.y;
+            }
+        }
+        __syncthreads();
+        if (r < i) {
+            const double2 p = zmul(ti, acc);
+            T[r][i] = make_double2(-p.x, -p.y);
+        }
+        if (r == i) T[i][i] = ti;
+        __syncthreads();
+    }
+    for (int q = threadIdx.x; q < kBtNb * kBtNb; q += 1024) {
+        const int r = q % kBtNb, c = q / kBtNb;
+        Tm[r + kBtNb * c] = T[r][c];
+    }
+}
+
+// P = (sum of split-K partials) T, rows of the m x kBtNb product.
+__global__ __launch_bounds__(256) void k_bt_pt(const double2* __restrict__ Ppart, int splits, int m,
+                                               const double2* __restrict__ Tm, double2* __restrict__ P) {
+    __shared__ double2 T[kBtNb][kBtNb];
+    for (int q = threadIdx.x; q < kBtNb * kBtNb; q += 256) T[q % kBtNb][q / kBtNb] = Tm[q];
+    __syncthreads();
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), c = threadIdx.x & 63;
+    if (i >= m) return;
+    // row i of the summed partials, one column per lane, then the row times T
+    double2 s = make_double2(0.0, 0.0);
+    for (int z = 0; z < splits; ++z) {
+        const double2 v = Ppart[(size_t)z * m * kBtNb + i + (size_t)m * c];
+        s.x += v.x;
+        s.y += v.y;
+    }
+    double2 acc = make_double2(0.0, 0.0);
+    for (int q = 0; q < kBtNb; ++q) {
+        const double2 sq = make_double2(__shfl(s.x, q, 64), __shfl(s.y, q, 64));
+        const double2 p = zmul(sq, T[q][c]);
+        acc.x += p.x;
+        acc.y += p.y;
+    }
+    P[i + (size_t)m * c] = acc;
+}
+
+// ------------------------------------------------------------ host plans
+struct DcPlan {
+    std::vector<int> level_off, level_cnt, level_nmax;
+    DcMerge* dev = nullptr;   // all merges, level by level
+};
+
+int dc_build(int lo, int n, std::vector<std::vector<DcMerge>>& by_h) {
+    if (n == 1) return 0;
+    const int n1 = n / 2, n2 = n - n1;
+    const int h = 1 + std::max(dc_build(lo, n1, by_h), dc_build(lo + n1, n2, by_h));
+    if ((int)by_h.size() <= h) by_h.resize(h + 1);
+    by_h[h].push_back({lo, n1, n2, 0});
+    return h;
+}
+
+}  // namespace
+
+struct HeevPlans {
+    std::map<int, DcPlan> plans;
+    ~HeevPlans() {
+        for (auto& kv : plans)
+            if (kv.second.dev) (void)hipFree(kv.second.dev);
+    }
+};
+
+void* heev_plans_new() { return new HeevPlans(); }
+void heev_plans_free(void* p) { delete (HeevPlans*)p; }
+
+size_t heev_bytes(int m_max, int n_max) {
+    if (n_max <= 0) return 0;
+    const size_t N = n_max, ldx = (size_t)((m_max + 1) & ~1) + 8;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t b = 0;
+    b += al(ldx * N * sizeof(double2));                         // Xd
+    b += al((N + 8) * N * sizeof(double2));                     // G
+    b += 2 * al(N * 2 * kTrdNb * sizeof(double2));              // VW, WV
+    b += 2 * al(N * sizeof(double2));                           // yraw, wt
+    b += al(2 * kTrdNb * sizeof(double2));                      // dots
+    b += al(4 * kPart * sizeof(double));                        // part, part2
+    b += al(N * sizeof(double2));                               // tau
+    b += 2 * al(N * sizeof(double));                            // d, e
+    b += al(N * kBtNb * sizeof(double2));                       // Y
+    b += al(kBtNb * kBtNb * sizeof(double2));                   // T
+    const size_t splits = (N + kSplitK - 1) / kSplitK;
+    b += al(splits * std::max<size_t>(ldx, kBtNb) * kBtNb * sizeof(double2));   // split-K partials
+    b += al(ldx * kBtNb * sizeof(double2));                     // P
+    b += 3 * al(N * N * sizeof(double));                        // Z, Z2, U
+    b += 9 * al(N * sizeof(double));                            // dv ds dz ndv ndz dfv taus lam zh
+    b += 5 * al(N * sizeof(int));                               // dcol ndc dfc orig perm
+    b += al(N * sizeof(int2)) + al(N * sizeof(double2));        // rotations
+    b += 2 * al(N * sizeof(int)) + al(N * sizeof(double));      // per-merge k, rotations, rho
+    return b;
+}
+
+void heev_carve(char* p, int m_max, int n_max, HeevWork& w) {
+    const size_t N = n_max, ldx = (size_t)((m_max + 1) & ~1) + 8;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    auto take = [&](size_t bytes) { char* q = p; p += al(bytes); return q; };
+    w.cap_m = m_max;
+    w.cap_n = n_max;
+    w.Xd = (double2*)take(ldx * N * sizeof(double2));
+    w.G = (double2*)take((N + 8) * N * sizeof(double2));
+    w.VW = (double2*)take(N * 2 * kTrdNb * sizeof(double2));
+    w.WV = (double2*)take(N * 2 * kTrdNb * sizeof(double2));
+    w.yraw = (double2*)take(N * sizeof(double2));
+    w.wt = (double2*)take(N * sizeof(double2));
+    w.dots = (double2*)take(2 * kTrdNb * sizeof(double2));
+    w.part = (double*)take(4 * kPart * sizeof(double));
+    w.tau = (double2*)take(N * sizeof(double2));
+    w.d = (double*)take(N * sizeof(double));
+    w.e = (double*)take(N * sizeof(double));
+    w.Y = (double2*)take(N * kBtNb * sizeof(double2));
+    w.Tm = (double2*)take(kBtNb * kBtNb * sizeof(double2));
+    const size_t splits = (N + kSplitK - 1) / kSplitK;
+    w.Cpart = (double2*)take(splits * std::max<size_t>(ldx, kBtNb) * kBtNb * sizeof(double2));
+    w.P = (double2*)take(ldx * kBtNb * sizeof(double2));
+    w.Z = (double*)take(N * N * sizeof(double));
+    w.Z2 = (double*)take(N * N * sizeof(double));
+    w.U = (double*)take(N * N * sizeof(double));
+    double** dbl[] = {&w.dv, &w.ds, &w.dz, &w.ndv, &w.ndz, &w.dfv, &w.taus, &w.lam, &w.zh};
+    for (double** q : dbl) *q = (double*)take(N * sizeof(double));
+    int** ints[] = {&w.dcol, &w.ndc, &w.dfc, &w.orig, &w.perm};
+    for (int** q : ints) *q = (int*)take(N * sizeof(int));
+    w.rot_ab = (int2*)take(N * sizeof(int2));
+    w.rot_cs = (double2*)take(N * sizeof(double2));
+    w.mk = (int*)take(N * sizeof(int));
+    w.mnrot = (int*)take(N * sizeof(int));
+    w.mrho = (double*)take(N * sizeof(double));
+}
+
+namespace {
+
+const DcPlan& dc_plan(HeevPlans& hp, int N) {
+    auto it = hp.plans.find(N);
+    if (it != hp.plans.end()) return it->second;
+    std::vector<std::vector<DcMerge>> by_h;
+    dc_build(0, N, by_h);
+    DcPlan pl;
+    std::vector<DcMerge> all;
+    for (size_t h = 1; h < by_h.size(); ++h) {
+        pl.level_off.push_back((int)all.size());
+        pl.level_cnt.push_back((int)by_h[h].size());
+        int nmax = 0;
+        for (DcMerge m : by_h[h]) {
+            m.id = (int)all.size();
+            nmax = std::max(nmax, m.n1 + m.n2);
+            all.push_back(m);
+        }
+        pl.level_nmax.push_back(nmax);
+    }
+    if (!all.empty()) {
+        if (hipMalloc((void**)&pl.dev, all.size() * sizeof(DcMerge)) != hipSuccess ||
+            hipMemcpy(pl.dev, all.data(), all.size() * sizeof(DcMerge), hipMemcpyHostToDevice) != hipSuccess)
+            throw HeevFailure{"divide-and-conquer plan upload"};
+    }
+    return hp.plans.emplace(N, std::move(pl)).first->second;
+}
+
+}  // namespace
+
+// Eigenvalues (ascending, w.dv) and eigenvectors (w.Z, N x N, ld N) of the
+// Hermitian G (w.G, ld w.ldg), which is overwritten by its reflectors.
+void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
+    const int ldg = N + 8;
+    // ---- tridiagonalisation: the trailing matrix-vector products are booked
+    // as K_TRIDIAG, the vector kernels and the rank-2 nb panel updates as K_TRDAUX
+    for (int j0 = 0; j0 < N - 1; j0 += kTrdNb) {
+        const int nbb = std::min(kTrdNb, N - 1 - j0);
+        const double pn = (double)N * 2 * kTrdNb;
+        launch_booked(pf, K_TRDAUX, 0.0, 32.0 * pn, k_fill_z, dim3(64), dim3(256), 0, st, w.VW, (size_t)pn);
+        launch_booked(pf, K_TRDAUX, 0.0, 32.0 * pn, k_fill_z, dim3(64), dim3(256), 0, st, w.WV, (size_t)pn);
+        launch_booked(pf, K_TRDAUX, 0.0, 16.0 * (N - j0), k_trd_colnorm, dim3(kPart), dim3(256), 0, st,
+                      (const double2*)w.G, ldg, N, j0, w.part);
+        for (int c = 0; c < nbb; ++c) {
+            const int j = j0 + c, len = N - j - 1;
+            const int waves = len + 2 * c;
+            launch_booked(pf, K_TRIDIAG, 8.0 * (double)len * waves, 16.0 * (double)len * waves,
+                          k_trd_gemv, dim3((waves + kGemvWaves - 1) / kGemvWaves), dim3(1024),
+                          (size_t)len * sizeof(double2), st, (const double2*)w.G, ldg, N, j, c,
+                          (const double*)w.part, w.VW, w.WV, w.yraw, w.dots, w.tau, w.d, w.e);
+            launch_booked(pf, K_TRDAUX, 16.0 * len * c, 16.0 * len * (2.0 * c + 5.0), k_trd_corr, dim3(kPart),
+                          dim3(256), 0, st, w.G, ldg, N, j, c, (const double2*)w.tau, (const double2*)w.VW,
+                          (const double2*)w.dots, (const double2*)w.yraw, w.wt, w.part + 2 * kPart);
+            launch_booked(pf, K_TRDAUX, 16.0 * len * (c + 1), 16.0 * len * (2.0 * c + 6.0), k_trd_next, dim3(kPart),
+                          dim3(256), 0, st, w.G, ldg, N, j, c, (int)(c + 1 < nbb), (const double2*)w.tau, w.VW,
+                          w.WV, (const double2*)w.wt, (const double*)(w.part + 2 * kPart), w.part);
+        }
+        const int k0 = j0 + nbb;
+        zgemm<0, 1, 1>(N - k0, N - k0, 2 * kTrdNb, w.VW + k0, N, w.WV + k0, N, w.G + k0 + (size_t)ldg * k0, ldg,
+                       st, 1, 0, 0, 0, 0, &pf, K_TRDAUX);
+    }
+    hipLaunchKernelGGL(k_trd_last, dim3(1), dim3(64), 0, st, (const double2*)w.G, ldg, N, w.d);
+
+    // ---- divide and conquer
+    pf.begin(st);
+    const DcPlan& pl = dc_plan(*(HeevPlans*)w.plans, N);
+    {
+        const size_t nn = (size_t)N * N;
+        hipLaunchKernelGGL(k_dc_init, dim3((unsigned)std::min<size_t>(4096, (nn + 255) / 256)), dim3(256), 0, st,
+                           N, (const double*)w.d, (const double*)w.e, w.dv, w.Z);
+    }
+    DcBuf b{w.dv, w.ds, w.dz, w.ndv, w.ndz, w.dfv, w.taus, w.lam, w.zh, w.dcol, w.ndc, w.dfc,
+            w.orig, w.perm, w.rot_ab, w.rot_cs, w.mk, w.mnrot, w.mrho};
+    for (size_t L = 0; L < pl.level_off.size(); ++L) {
+        const DcMerge* mg = pl.dev + pl.level_off[L];
+        const unsigned cnt = pl.level_cnt[L];
+        const int nmax = pl.level_nmax[L];
+        hipLaunchKernelGGL(k_dc_prep, dim3(cnt), dim3(1024), 0, st, mg, N, (const double*)w.e,
+                           (const double*)w.Z, b);
+        hipLaunchKernelGGL(k_dc_rot, dim3((nmax + 255) / 256, cnt), dim3(256), 0, st, mg, N, w.Z, b);
+        const unsigned g4 = (nmax + 3) / 4;
+        hipLaunchKernelGGL(k_dc_secular, dim3(g4, cnt), dim3(256), 0, st, mg, b);
+        hipLaunchKernelGGL(k_dc_zhat, dim3(g4, cnt), dim3(256), 0, st, mg, b);
+        hipLaunchKernelGGL(k_dc_vec, dim3(g4, cnt), dim3(256), 0, st, mg, N, w.U, b);
+        const unsigned gt = (nmax + ZBM - 1) / ZBM;
+        hipLaunchKernelGGL(k_dc_gemm, dim3(gt, gt, cnt), dim3(256), 0, st, mg, N, (const double*)w.Z,
+                           (const double*)w.U, w.Z2, b);
+        hipLaunchKernelGGL(k_dc_defl, dim3(nmax, cnt), dim3(256), 0, st, mg, N, (const double*)w.Z, w.Z2, b);
+        hipLaunchKernelGGL(k_dc_sort, dim3(cnt), dim3(1024), 0, st, mg, b);
+        hipLaunchKernelGGL(k_dc_perm, dim3(nmax, cnt), dim3(256), 0, st, mg, N, w.Z, (const double*)w.Z2, b);
+    }
+    pf.end(st, K_DC, 2.0 * (double)N * N * N, 24.0 * (double)N * N);
+}
+
+// X (m x N, storage T, stride ld) <- X Q_H Z for the Gram eigen-decomposition
+// of X, all in FP64.  Throws HeevFailure on a HIP error.
+template <typename T>
+void heev_precondition(C2<T>* X, int m, int N, int ld, HeevWork& w, Profiler& pf, hipStream_t st) {
+    if (N > w.cap_n || m > w.cap_m || N < 2) throw HeevFailure{"eigen-preconditioner capacity"};
+    const int ldx = ((w.cap_m + 1) & ~1) + 8;
+    const int ldg = N + 8;
+    // ---- X -> FP64, Gram
+    pf.begin(st);
+    hipLaunchKernelGGL((k_to_f64<T>), dim3((m + 255) / 256, N), dim3(256), 0, st, (const C2<T>*)X, m, ld, w.Xd,
+                       ldx);
+    zgemm<1, 0, 0>(N, N, m, w.Xd, ldx, w.Xd, ldx, w.G, ldg, st);
+    pf.end(st, K_HGRAM, 8.0 * (double)N * N * m, (double)m * N * (sizeof(C2<T>) + 32.0) + 16.0 * N * N);
+
+    heev_run(N, w, pf, st);
+
+    // ---- X <- X Q_H, blocks of kBtNb reflectors in forward order
+    pf.begin(st);
+    for (int j0 = 0; j0 < N - 1; j0 += kBtNb) {
+        const int nbb = std::min(kBtNb, N - 1 - j0);
+        const int K = N - j0 - 1;                  // rows j0+1 .. N-1 of Y
+        const int splits = (K + kSplitK - 1) / kSplitK;
+        hipLaunchKernelGGL(k_bt_y, dim3((N + 255) / 256, kBtNb), dim3(256), 0, st, (const double2*)w.G, ldg, N,
+                           j0, nbb, w.Y);
+        const double2* Ys = w.Y + (j0 + 1);
+        // S = Y^H Y (split-K partials), T
+        zgemm<1, 0, 0>(kBtNb, kBtNb, K, Ys, N, Ys, N, w.Cpart, kBtNb, st, splits, kSplitK, kSplitK, kSplitK,
+                       (size_t)kBtNb * kBtNb);
+        hipLaunchKernelGGL(k_bt_t, dim3(1), dim3(1024), 0, st, (const double2*)w.Cpart, splits,
+                           (const double2*)w.tau, j0, nbb, w.Tm);
+        // P = X[:, j0+1:] Y (split-K), P <- P T
+        zgemm<0, 0, 0>(m, kBtNb, K, w.Xd + (size_t)ldx * (j0 + 1), ldx, Ys, N, w.Cpart, m, st, splits, kSplitK,
+                       (size_t)kSplitK * ldx, kSplitK, (size_t)m * kBtNb);
+        hipLaunchKernelGGL(k_bt_pt, dim3((m + 3) / 4), dim3(256), 0, st, (const double2*)w.Cpart, splits, m,
+                           (const double2*)w.Tm, w.P);
+        // X[:, j0+1:] -= P Y^H
+        zgemm<0, 1, 1>(m, K, kBtNb, w.P, m, Ys, N, w.Xd + (size_t)ldx * (j0 + 1), ldx, st);
+    }
+    pf.end(st, K_BACK, 8.0 * (double)m * N * N, 32.0 * (double)m * N * (N / kBtNb + 1));
+
+    // ---- X <- Xd Z (real view: 2m x N times N x N), rounded to the storage precision
+    pf.begin(st);
+    {
+        dim3 grid((2 * m + ZBM - 1) / ZBM, (N + ZBN - 1) / ZBN);
+        hipLaunchKernelGGL((k_dgemm<T>), grid, dim3(256), 0, st, 2 * m, N, N, (const double*)w.Xd, 2 * ldx,
+                           (const double*)w.Z, N, (T*)X, 2 * ld);
+    }
+    pf.end(st, K_BACK, 4.0 * (double)m * N * N, 16.0 * (double)m * N + 8.0 * N * N + (double)m * N * sizeof(C2<T>));
+    if (hipGetLastError() != hipSuccess) throw HeevFailure{"eigen-preconditioner launch"};
+    w.n_runs += 1;
+}
+
+template void heev_precondition<double>(double2*, int, int, int, HeevWork&, Profiler&, hipStream_t);
+template void heev_precondition<float>(float2*, int, int, int, HeevWork&, Profiler&, hipStream_t);
+
+// Hermitian eigen-decomposition of a host matrix (tests): G row-major complex
+// N x N (interleaved), values ascending, vectors as columns of V (row-major).
+void heev_host(int N, const double* Gh, double* wh, double* Vh, HeevWork& w, Profiler& pf, hipStream_t st) {
+    if (N > w.cap_n || N < 2) throw HeevFailure{"eigen-solver capacity"};
+    const int ldg = N + 8;
+    std::vector<double2> g((size_t)ldg * N);
+    for (int r = 0; r < N; ++r)
+        for (int c = 0; c < N; ++c) g[r + (size_t)ldg * c] = make_double2(Gh[2 * (r * N + c)], Gh[2 * (r * N + c) + 1]);
+    if (hipMemcpyAsync(w.G, g.data(), g.size() * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess)
+        throw HeevFailure{"copy in"};
+    heev_run(N, w, pf, st);
+    // V = Q_H Z: apply the reflectors to Z (as complex) through the same right-multiplication
+    // on X = I: Xd <- I, Xd <- Xd Q_H, V = Xd Z.
+    const int ldx = ((w.cap_m + 1) & ~1) + 8;
+    std::vector<double2> eye((size_t)ldx * N, make_double2(0.0, 0.0));
+    for (int i = 0; i < N; ++i) eye[i + (size_t)ldx * i] = make_double2(1.0, 0.0);
+    if (hipMemcpyAsync(w.Xd, eye.data(), eye.size() * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess)
+        throw HeevFailure{"copy in"};
+    for (int j0 = 0; j0 < N - 1; j0 += kBtNb) {
+        const int nbb = std::min(kBtNb, N - 1 - j0);
+        const int K = N - j0 - 1;
+        const int splits = (K + kSplitK - 1) / kSplitK;
+        hipLaunchKernelGGL(k_bt_y, dim3((N + 255) / 256, kBtNb), dim3(256), 0, st, (const double2*)w.G, ldg, N,
+                           j0, nbb, w.Y);
+        const double2* Ys = w.Y + (j0 + 1);
+        zgemm<1, 0, 0>(kBtNb, kBtNb, K, Ys, N, Ys, N, w.Cpart, kBtNb, st, splits, kSplitK, kSplitK, kSplitK,
+                       (size_t)kBtNb * kBtNb);
+        hipLaunchKernelGGL(k_bt_t, dim3(1), dim3(1024), 0, st, (const double2*)w.Cpart, splits,
+                           (const double2*)w.tau, j0, nbb, w.Tm);
+        zgemm<0, 0, 0>(N, kBtNb, K, w.Xd + (size_t)ldx * (j0 + 1), ldx, Ys, N, w.Cpart, N, st, splits, kSplitK,
+                       (size_t)kSplitK * ldx, kSplitK, (size_t)N * kBtNb);
+        hipLaunchKernelGGL(k_bt_pt, dim3((N + 3) / 4), dim3(256), 0, st, (const double2*)w.Cpart, splits, N,
+                           (const double2*)w.Tm, w.P);
+        zgemm<0, 1, 1>(N, K, kBtNb, w.P, N, Ys, N, w.Xd + (size_t)ldx * (j0 + 1), ldx, st);
+    }
+    // V (complex, N x N, ld ldx) into G's storage
+    {
+        dim3 grid((2 * N + ZBM - 1) / ZBM, (N + ZBN - 1) / ZBN);
+        hipLaunchKernelGGL((k_dgemm<double>), grid, dim3(256), 0, st, 2 * N, N, N, (const double*)w.Xd, 2 * ldx,
+                           (const double*)w.Z, N, (double*)w.G, 2 * ldg);
+    }
+    if (hipGetLastError() != hipSuccess) throw HeevFailure{"launch"};
+    std::vector<double> vals(N);
+    if (hipMemcpyAsync(vals.data(), w.dv, N * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(g.data(), w.G, g.size() * sizeof(double2), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        throw HeevFailure{"copy out"};
+    for (int i = 0; i < N; ++i) wh[i] = vals[i];
+    for (int r = 0; r < N; ++r)
+        for (int c = 0; c < N; ++c) {
+            Vh[2 * (r * N + c)] = g[r + (size_t)ldg * c].x;
+            Vh[2 * (r * N + c) + 1] = g[r + (size_t)ldg * c].y;
+        }
+}
+
+}  // namespace mpo

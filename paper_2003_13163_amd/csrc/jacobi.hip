@@ -1353,8 +1353,16 @@ template <typename T>
 int jacobi_orthogonalize(C2<T>* X, int m, int N, int ld, double tol, int max_sweeps, JacobiWork& w,
                          hipStream_t st) {
     w.n_splits += 1;
+    // Start from the eigenvectors of X^H X: the columns are then orthogonal to
+    // about the FP64 eigen-solver's accuracy and the sweeps only polish.
+    bool started = false;
+    if (w.heev && w.precond_min > 0 && N >= w.precond_min && N <= w.heev->cap_n && m <= w.heev->cap_m) {
+        heev_precondition<T>(X, m, N, ld, *w.heev, *w.prof, st);
+        w.n_precond += 1;
+        started = true;
+    }
     if constexpr (sizeof(T) == 4) {
-        if (w.bf3) {
+        if (w.bf3 && !started) {
             // BF16x3 Gram until a sweep starts within kBf3Handoff of orthogonal
             // (convergence is quadratic there, so it ends near 1e-5), then the
             // FP32-MFMA Gram down to kTolFp32; both with the BF16x3 zero floor
@@ -1372,6 +1380,8 @@ int jacobi_orthogonalize(C2<T>* X, int m, int N, int ld, double tol, int max_swe
         }
     }
     const double zrel2 = jacobi_zero_rel2<T>();
+    // split-BF16x3 from the eigen-solver's start: only the FP32-Gram polish remains
+    if (sizeof(T) == 4 && w.bf3) tol = std::fmin(tol, kTolFp32);
     if (w.block == 16) return jacobi_run<T, 16, false>(X, m, N, ld, tol, tol, zrel2, max_sweeps, w.inner, w, st);
     return jacobi_run<T, 32, false>(X, m, N, ld, tol, tol, zrel2, max_sweeps, w.inner, w, st);
 }

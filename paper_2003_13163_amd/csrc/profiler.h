@@ -22,13 +22,20 @@ enum KernelId {
     K_GATHER,        // isometry gathers / transposes / copies
     K_GEMM,          // plain complex GEMMs (right factor, centre moves)
     K_TRANSFER,      // transfer contraction
+    K_HGRAM,         // Gram matrix of the eigen-solver start
+    K_TRIDIAG,       // tridiagonalisation: trailing matrix-vector products (per launch)
+    K_TRDAUX,        // tridiagonalisation: whole reduction including vector kernels and panel updates
+    K_DC,            // divide and conquer on the tridiagonal
+    K_BACK,          // back-transformation X Q_H Z
     K_COUNT
 };
 
 inline const char* kernel_name(int k) {
     static const char* names[K_COUNT] = {"theta_channel", "jacobi_gram", "jacobi_eig64",
                                          "jacobi_update", "norm_sort",    "truncate",
-                                         "gather",        "cgemm",        "transfer"};
+                                         "gather",        "cgemm",        "transfer",
+                                         "heev_gram",     "heev_trd_gemv", "heev_tridiag", "heev_dc",
+                                         "heev_back"};
     return names[k];
 }
 
