@@ -241,15 +241,19 @@ def adjoint_measurement(pm, mi, torch, n=32, depth=24, p=0.01, chi=256):
 
 def cpu_baseline(snap_bytes, pm, site, sup, chi, threads=None):
     """Oracle (numpy complex128) on one bulk gate of the same snapshot: the
-    centre is first moved to site - 1 (untimed), then the gate is timed with
-    the one QR move it needs, the contraction, the map and the gesdd split.
+    centre is first moved next to the gate from the side the GPU comes from
+    (untimed), then the gate is timed with the one QR move it needs, the
+    contraction, the map and the gesdd split.  Both sides then move the centre
+    through the same bonds, which matters for the comparison: the snapshot is
+    canonical only to the precision it was built in, so a detour across other
+    bonds would change the local split at that level.
     threads: BLAS threads (None = all)."""
     from oracle import mpo as omp
     from threadpoolctl import threadpool_info, threadpool_limits
     n, basis, centre, tensors = pm.snapshot_to_tensors(snap_bytes)
     m = omp.MPO.__new__(omp.MPO)
     m.n, m.basis, m.A, m.centre = n, "pauli", tensors, centre
-    target = max(0, site - 1)
+    target = site + 1 if centre > site else max(0, site - 1)
     t0 = time.perf_counter()
     while m.centre != target:      # untimed: bring the centre next to the gate
         m.move_centre(m.centre + (1 if m.centre < target else -1))

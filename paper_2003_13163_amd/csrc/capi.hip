@@ -74,6 +74,8 @@ inline int work_ld(int m) { return ((m + 1) & ~1) + 8; }
 // reaches kHeevMinCols.
 constexpr int kHeevMinCols = 512;
 constexpr int kPrecondMinDefault = 1024;
+// centre moves on bonds of at least this dimension use the Cholesky QR re-gauge
+constexpr int kQrMinDefault = 128;
 
 struct Layout {
     size_t slot_bytes, slots, x_bytes, r_bytes, partial_bytes, w_bytes, skip_bytes, vecN_bytes,
@@ -128,6 +130,8 @@ struct mpo_handle {
     std::vector<int> spare;      // free slot indices
     std::vector<int> dims;       // bond b in [0, n-2]
     int centre = 0;
+    int qr_min = 0;              // centre moves by Cholesky QR on bonds of at least this size (0 = SVD moves)
+    long long n_qr_fallback = 0; // QR moves that met rank deficiency and moved by the SVD instead
     bool poisoned = false;
     char *X = nullptr, *X2 = nullptr, *R = nullptr, *Mdev = nullptr;
     size_t x_bytes = 0;          // bytes of X and of X2 each
@@ -312,9 +316,79 @@ struct Engine {
         return inf;
     }
 
+    // Centre c -> c+1 by an exact QR of L(A_c) ("Note added"): A_c <- Q,
+    // A_{c+1} <- R A_{c+1}; the bond keeps its dimension (no values dropped).
+    // Returns false, with the state untouched, when L(A_c) is numerically
+    // rank-deficient (the caller then moves by the SVD, which drops the null part).
+    static bool move_right_qr(mpo_handle* h, int c) {
+        const int chiL = h->chiL(c), r = h->dims[c], chiR2 = h->chiR(c + 1);
+        const int m = 4 * chiL;
+        const int s1 = h->take_spare(), s2 = h->take_spare();
+        C* Q = (C*)h->slot[s1];
+        C* Anext = (C*)h->slot[s2];
+        if (!cholqr3<T>(site(h, c), m, r, m, Q, m, (C*)h->R, h->jw.info, h->info_host, h->hw, h->prof, h->st)) {
+            h->give_spare(s2);
+            h->give_spare(s1);
+            h->n_qr_fallback += 1;
+            return false;
+        }
+        h->prof.begin(h->st);
+        launch_cgemm<T>(0, 0, r, 4 * chiR2, r, (C*)h->R, r, site(h, c + 1), r, Anext, r, h->st, h->bf3);
+        h->prof.end(h->st, K_GEMM, 8.0 * r * 4.0 * chiR2 * r, (double)sizeof(C) * ((double)r * r + 8.0 * r * chiR2));
+        HIPCHK(hipGetLastError());
+        h->give_spare(h->site_slot[c]);
+        h->give_spare(h->site_slot[c + 1]);
+        h->site_slot[c] = s1;
+        h->site_slot[c + 1] = s2;
+        h->centre = c + 1;
+        return true;
+    }
+
+    // Centre c -> c-1: R(A_c)^H = Q R, so R(A_c) = R^H Q^H; A_c <- Q^H,
+    // A_{c-1} <- L(A_{c-1}) R^H.  False (state untouched) on rank deficiency.
+    static bool move_left_qr(mpo_handle* h, int c) {
+        const int r = h->dims[c - 1], chiR = h->chiR(c), chiLL = h->chiL(c - 1);
+        const int m = 4 * chiR;
+        h->prof.begin(h->st);
+        launch_conj_transpose<T>(site(h, c), r, m, r, (C*)h->X, work_ld(m), h->st);
+        h->prof.end(h->st, K_GATHER, 0.0, 2.0 * sizeof(C) * m * r);
+        if (!cholqr3<T>((const C*)h->X, m, r, work_ld(m), (C*)h->X, work_ld(m), (C*)h->R, h->jw.info, h->info_host,
+                        h->hw, h->prof, h->st)) {
+            h->n_qr_fallback += 1;
+            return false;
+        }
+        const int s1 = h->take_spare(), s2 = h->take_spare();
+        C* Qh = (C*)h->slot[s1];
+        C* Aprev = (C*)h->slot[s2];
+        h->prof.begin(h->st);
+        launch_conj_transpose<T>((C*)h->X, m, r, work_ld(m), Qh, r, h->st);
+        launch_cgemm<T>(0, 1, 4 * chiLL, r, r, site(h, c - 1), 4 * chiLL, (C*)h->R, r, Aprev, 4 * chiLL, h->st,
+                        h->bf3);
+        h->prof.end(h->st, K_GEMM, 8.0 * 4.0 * chiLL * r * r, (double)sizeof(C) * (2.0 * m * r + 8.0 * chiLL * r + (double)r * r));
+        HIPCHK(hipGetLastError());
+        h->give_spare(h->site_slot[c]);
+        h->give_spare(h->site_slot[c - 1]);
+        h->site_slot[c] = s1;
+        h->site_slot[c - 1] = s2;
+        h->centre = c - 1;
+        return true;
+    }
+
+    // Centre moves of the gate path: exact QR re-gauges where the handle has the
+    // FP64 workspace, the bond is at least qr_min and the matrix to factor has at
+    // least as many rows (4 x the outer bond) as columns; else the SVD moves.
+    static bool use_qr(const mpo_handle* h, int bond_dim, int outer_dim) {
+        return h->jw.heev && h->qr_min > 0 && bond_dim >= h->qr_min && 4 * outer_dim >= bond_dim;
+    }
     static void move_centre(mpo_handle* h, int target) {
-        while (h->centre < target) move_right(h, h->centre);
-        while (h->centre > target) move_left(h, h->centre, false);
+        while (h->centre < target) {
+            const int c = h->centre;
+            if (!(use_qr(h, h->dims[c], h->chiL(c)) && move_right_qr(h, c))) move_right(h, c);
+        }
+        while (h->centre > target) {
+            const int c = h->centre;
+            if (!(use_qr(h, h->dims[c - 1], h->chiR(c)) && move_left_qr(h, c))) move_left(h, c, false);
+        }
     }
 
     // Gate on (s, s+1) with superoperator already on the device at Mg.
@@ -1333,6 +1407,8 @@ mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis, v
         h->jw.heev = &h->hw;
         h->jw.precond_min = kPrecondMinDefault;
         if (const char* e = std::getenv("MPO_PRECOND_MIN")) h->jw.precond_min = std::max(0, std::atoi(e));
+        h->qr_min = kQrMinDefault;
+        if (const char* e = std::getenv("MPO_QR_MIN")) h->qr_min = std::max(0, std::atoi(e));
     }
     h->dims.assign(n - 1, 1);
     h->last_S.assign(n - 1, 0.0);

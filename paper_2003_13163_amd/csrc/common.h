@@ -124,6 +124,8 @@ struct DevInfo {
     int done;              // set on the device once the sweeps converged (1) or hit the limit (2)
     int sweeps;            // sweeps run in this decomposition
     long long rot_total;   // rotated pairs summed over its sweeps
+    int qr_fail;           // a Cholesky QR pass met a pivot below its bound (rank deficiency)
+    double qr_shift;       // shift of the first Cholesky QR pass
 };
 
 }  // namespace mpo
@@ -152,7 +154,8 @@ struct HeevWork {
     double2* G;                       // Gram (stride N + 8), then the reflectors below its diagonal
     double2 *VW, *WV;                 // panel [V W] and [W V], N x 2 kTrdNb each (stride N)
     double2 *yraw, *wt, *dots, *tau;
-    double* part;                     // partial sums of the vector kernels
+    double* part;                     // partial sums of ||column||^2 (row chunks)
+    double2 *pdot, *palpha;           // partial sums of the panel dots and of w~^H v
     double *d, *e;                    // tridiagonal
     double2 *Y, *Tm, *Cpart, *P;      // back-transformation blocks, split-K partials
     double *Z, *Z2, *U;               // eigenvectors of T and merge scratch (N x N, stride N)
@@ -173,6 +176,13 @@ void heev_plans_free(void* plans);
 // X (m x N, stride ld) <- X V with V the eigenvectors of X^H X, computed in FP64.
 template <typename T>
 void heev_precondition(C2<T>* X, int m, int N, int ld, HeevWork& w, Profiler& pf, hipStream_t st);
+// A (m x r, stride lda) = Q R: Q (stride ldq, may alias A) an isometry, R (r x r, stride r)
+// upper triangular; shifted Cholesky QR plus two Cholesky QR passes in FP64.
+// Returns false, writing neither Q nor R, when A is numerically rank-deficient
+// (a pivot below its pass's bound); reads that flag through info_host (pinned).
+template <typename T>
+bool cholqr3(const C2<T>* A, int m, int r, int lda, C2<T>* Q, int ldq, C2<T>* R, DevInfo* info,
+             DevInfo* info_host, HeevWork& w, Profiler& pf, hipStream_t st);
 // Eigenvalues (ascending) and eigenvectors of a host Hermitian matrix (row-major,
 // interleaved complex), through the same kernels.
 void heev_host(int N, const double* G, double* w, double* V, HeevWork& work, Profiler& pf, hipStream_t st);

@@ -32,7 +32,8 @@ namespace mpo {
 namespace {
 
 constexpr int kPart = 64;          // row chunks of the tridiagonalisation's vector kernels
-constexpr int kGemvWaves = 16;     // waves per work-group of the trailing matrix-vector product
+static_assert(kPart == 64, "the kernels sum the kPart partials one per lane of a wave");
+constexpr int kGemvWaves = 8;      // waves per work-group of the trailing matrix-vector product
 constexpr int kBtNb = 64;          // reflectors per block of the back-transformation
 constexpr int kSplitK = 256;       // K chunk of the split-K products
 
@@ -340,26 +341,53 @@ __global__ __launch_bounds__(256) void k_trd_colnorm(const double2* __restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// Column j of the panel (c = j - j0): the reflector from the updated column
-// (scalars recomputed identically in every work-group), then
-//   y_raw = G[j+1:, j+1:] v        (panel-start trailing matrix; one wave per column,
-//                                   y_i = conj(G[:, i]) . v by Hermitian symmetry)
-//   dots  = W^H v (first c), V^H v (at kTrdNb + c')
-// Work-group 0 also stores the reflector in the panel buffers and tau_j, e_j, d_j.
-__global__ __launch_bounds__(1024) void k_trd_gemv(const double2* __restrict__ G, int ldg, int N, int j, int c,
-                                                   const double* __restrict__ part, double2* __restrict__ VW,
-                                                   double2* __restrict__ WV, double2* __restrict__ yraw,
-                                                   double2* __restrict__ dots, double2* __restrict__ tau,
-                                                   double* __restrict__ d, double* __restrict__ e) {
+// Column j of the panel (c = j - j0), one wave per trailing column i:
+//   reflector      from the updated column (scalars recomputed identically in
+//                  every work-group from the partial sums of ||G[j+2:, j]||^2)
+//   p = W^H v, q = V^H v   from the partial sums of W^H G[j+2:, j] and
+//                  V^H G[j+2:, j] the previous kernel left (v = [1, scale x])
+//   y_i = conj(G[j+1:, i]) . v - (V p + W q)_i    (panel-start trailing matrix,
+//                  Hermitian symmetry: a column read is a row of G)
+//   w~_i = tau_j y_i, and per work-group the partial sum of w~^H v.
+// Work-group 0 stores the reflector in the panel buffers together with tau_j,
+// e_j and d_j (column j of G is still being read here).
+__global__ __launch_bounds__(64 * kGemvWaves) void k_trd_gemv(double2* __restrict__ G, int ldg, int N, int j, int c,
+                                                   const double* __restrict__ part,
+                                                   const double2* __restrict__ pdot,
+                                                   double2* __restrict__ VW, double2* __restrict__ WV,
+                                                   double2* __restrict__ wt, double2* __restrict__ palpha,
+                                                   double2* __restrict__ tau, double* __restrict__ d,
+                                                   double* __restrict__ e) {
     extern __shared__ double2 vs[];      // v[j+1 .. N)
+    __shared__ double2 pq[2 * kTrdNb];   // p, then q
+    __shared__ double2 red[kGemvWaves];
+    __shared__ double sxn2;
     const int len = N - j - 1;
     const int tid = threadIdx.x;
-    double xn2 = 0.0;
-    for (int q = 0; q < kPart; ++q) xn2 += part[q];
+    const int wave = blockIdx.x * kGemvWaves + (tid >> 6), lane = tid & 63;
+    // ||x[1:]||^2 from its kPart (= 64) partial sums: one per lane, a fixed-order
+    // butterfly, so every work-group forms the same scalars
+    if (tid < 64) {
+        const double xn = wave_sum(part[tid]);
+        if (tid == 0) sxn2 = xn;
+    }
+    __syncthreads();
     const double2 alpha = G[(j + 1) + (size_t)ldg * j];
-    const House h = house_scalars(alpha, xn2);
-    for (int r = tid; r < len; r += 1024)
+    const House h = house_scalars(alpha, sxn2);
+    for (int r = tid; r < len; r += 64 * kGemvWaves)
         vs[r] = r == 0 ? make_double2(1.0, 0.0) : zmul(G[(j + 1 + r) + (size_t)ldg * j], h.scale);
+    // p_q = conj(W[j+1, q]) + scale * sum_w (W^H x)_q, likewise q_q with V: dot d
+    // (isv = d / c, q = d % c) summed over the kPart partials by wave d % 16
+    for (int dd = tid >> 6; dd < 2 * c; dd += kGemvWaves) {
+        const int q = dd % c, isv = dd / c;
+        const double2 t = pdot[(size_t)lane * 2 * kTrdNb + isv * kTrdNb + q];
+        const double sr = wave_sum(t.x), si = wave_sum(t.y);
+        if (lane == 0) {
+            const double2 row = VW[(j + 1) + (size_t)N * ((isv ? 0 : kTrdNb) + q)];
+            const double2 sc = zmul(h.scale, make_double2(sr, si));
+            pq[isv * kTrdNb + q] = make_double2(row.x + sc.x, -row.y + sc.y);
+        }
+    }
     __syncthreads();
     if (blockIdx.x == 0) {
         if (tid == 0) {
@@ -367,120 +395,155 @@ __global__ __launch_bounds__(1024) void k_trd_gemv(const double2* __restrict__ G
             e[j] = h.beta;
             d[j] = G[j + (size_t)ldg * j].x;
         }
-        for (int r = tid; r < N; r += 1024) {
+        for (int r = tid; r < N; r += 64 * kGemvWaves) {
             const double2 v = r <= j ? make_double2(0.0, 0.0) : vs[r - j - 1];
             VW[r + (size_t)N * c] = v;
             WV[r + (size_t)N * (kTrdNb + c)] = v;
         }
     }
-    const int wave = blockIdx.x * kGemvWaves + (tid >> 6), lane = tid & 63;
-    if (wave >= len + 2 * c) return;
-    const double2* src;
-    if (wave < len) src = G + (size_t)ldg * (j + 1 + wave) + (j + 1);
-    else if (wave - len < c) src = VW + (size_t)N * (kTrdNb + (wave - len)) + (j + 1);   // W column
-    else src = VW + (size_t)N * (wave - len - c) + (j + 1);                              // V column
-    double sr = 0.0, si = 0.0;
-    for (int r = lane; r < len; r += 64) {
-        const double2 a = src[r], b = vs[r];
-        sr += a.x * b.x + a.y * b.y;
-        si += a.x * b.y - a.y * b.x;
-    }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if (lane == 0) {
-        const double2 out = make_double2(sr, si);
-        if (wave < len) yraw[j + 1 + wave] = out;
-        else if (wave - len < c) dots[wave - len] = out;
-        else dots[kTrdNb + (wave - len - c)] = out;
-    }
-}
-
-// y = y_raw - V (W^H v) - W (V^H v); w~ = tau_j y; partial sums of w~^H v;
-// the reflector is stored below the diagonal of G (G[j+1, j] = 1).
-__global__ __launch_bounds__(256) void k_trd_corr(double2* __restrict__ G, int ldg, int N, int j, int c,
-                                                  const double2* __restrict__ tau, const double2* __restrict__ VW,
-                                                  const double2* __restrict__ dots,
-                                                  const double2* __restrict__ yraw, double2* __restrict__ wt,
-                                                  double* __restrict__ part2) {
-    __shared__ double red[4];
-    int a, b;
-    part_rows(j + 1, N, a, b);
-    const double2 tj = tau[j];
-    double sr = 0.0, si = 0.0;
-    for (int i = a + (int)threadIdx.x; i < b; i += 256) {
-        double2 y = yraw[i];
-        for (int q = 0; q < c; ++q) {
-            const double2 t1 = zmul(VW[i + (size_t)N * q], dots[q]);
-            const double2 t2 = zmul(VW[i + (size_t)N * (kTrdNb + q)], dots[kTrdNb + q]);
-            y.x -= t1.x + t2.x;
-            y.y -= t1.y + t2.y;
+    double2 contrib = make_double2(0.0, 0.0);
+    if (wave < len) {
+        const int i = j + 1 + wave;
+        const double2* src = G + (size_t)ldg * i + (j + 1);
+        double sr = 0.0, si = 0.0;
+        int r = lane;
+        for (; r + 448 < len; r += 512) {   // eight 1 KiB loads per wave in flight
+            double2 a[8], b[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = src[r + 64 * u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) b[u] = vs[r + 64 * u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                sr += a[u].x * b[u].x + a[u].y * b[u].y;
+                si += a[u].x * b[u].y - a[u].y * b[u].x;
+            }
         }
-        const double2 w = zmul(tj, y);
-        wt[i] = w;
-        const double2 v = VW[i + (size_t)N * c];
-        const double2 p = zcmul(w, v);
-        sr += p.x;
-        si += p.y;
-        G[i + (size_t)ldg * j] = v;
+        for (; r < len; r += 64) {
+            const double2 a = src[r], b = vs[r];
+            sr += a.x * b.x + a.y * b.y;
+            si += a.x * b.y - a.y * b.x;
+        }
+        // (V p + W q)_i, one panel column per lane
+        if (lane < c) {
+            const double2 t1 = zmul(VW[i + (size_t)N * lane], pq[lane]);
+            const double2 t2 = zmul(VW[i + (size_t)N * (kTrdNb + lane)], pq[kTrdNb + lane]);
+            sr -= t1.x + t2.x;
+            si -= t1.y + t2.y;
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        const double2 w = zmul(h.tau, make_double2(sr, si));
+        const double2 vi = vs[wave];
+        if (lane == 0) wt[i] = w;
+        contrib = zcmul(w, vi);
     }
-    sr = block_sum<256>(sr, red);
-    si = block_sum<256>(si, red);
-    if (threadIdx.x == 0) {
-        part2[2 * blockIdx.x] = sr;
-        part2[2 * blockIdx.x + 1] = si;
+    if (lane == 0) red[tid >> 6] = contrib;
+    __syncthreads();
+    if (tid == 0) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int q = 0; q < kGemvWaves; ++q) { s.x += red[q].x; s.y += red[q].y; }
+        palpha[blockIdx.x] = s;
     }
 }
 
 // w = w~ + alpha v with alpha = -tau_j (w~^H v) / 2 into the panel buffers
-// (zero above row j+1); if the panel continues, column j+1 is brought up to
-// date, G[j+1:, j+1] -= V conj(W[j+1, :]) + W conj(V[j+1, :]), and the partial
-// sums of ||G[j+3:, j+1]||^2 are formed for its reflector.
+// (zero above row j+1), the reflector below the diagonal of G (G[j+1, j] = 1
+// for the back-transformation); if the panel continues, column j+1 is brought up to
+// date, G[j+1:, j+1] -= V conj(W[j+1, :]) + W conj(V[j+1, :]), and the
+// partial sums its reflector needs are formed: ||G[j+3:, j+1]||^2, and
+// W^H G[j+3:, j+1], V^H G[j+3:, j+1] over the panel's first c+1 columns.
 __global__ __launch_bounds__(256) void k_trd_next(double2* __restrict__ G, int ldg, int N, int j, int c,
-                                                  int update_next, const double2* __restrict__ tau,
-                                                  double2* __restrict__ VW, double2* __restrict__ WV,
-                                                  const double2* __restrict__ wt,
-                                                  const double* __restrict__ part2, double* __restrict__ part) {
+                                                  int update_next, int gemv_groups,
+                                                  const double2* __restrict__ tau, double2* __restrict__ VW,
+                                                  double2* __restrict__ WV, const double2* __restrict__ wt,
+                                                  const double2* __restrict__ palpha, double* __restrict__ part,
+                                                  double2* __restrict__ pdot) {
     __shared__ double red[4];
-    double s_r = 0.0, s_i = 0.0;
-    for (int q = 0; q < kPart; ++q) { s_r += part2[2 * q]; s_i += part2[2 * q + 1]; }
-    const double2 tj = tau[j];
-    const double2 ts = zmul(tj, make_double2(s_r, s_i));
+    __shared__ double2 sw[64];            // new W column on this chunk's rows
+    __shared__ double2 arow[64];          // updated column j+1 on this chunk's rows (>= j+3; else 0)
+    __shared__ double2 red4[4][64];
+    const int t = threadIdx.x;
+    // w~^H v from the gemv's partials (at most 512): two per thread, fixed-order block sums
+    double2 pa = t < gemv_groups ? palpha[t] : make_double2(0.0, 0.0);
+    if (t + 256 < gemv_groups) { pa.x += palpha[t + 256].x; pa.y += palpha[t + 256].y; }
+    const double2 s = make_double2(block_sum<256>(pa.x, red), block_sum<256>(pa.y, red));
+    const double2 ts = zmul(tau[j], s);
     const double2 al = make_double2(-0.5 * ts.x, -0.5 * ts.y);
     int a, b;
     part_rows(0, N, a, b);
-    // W[j+1, c] = w~[j+1] + alpha (v[j+1] = 1), needed by every row of the column update
-    double2 wj1 = make_double2(0.0, 0.0);
-    if (j + 1 < N) { wj1 = wt[j + 1]; wj1.x += al.x; wj1.y += al.y; }
-    double nrm = 0.0;
-    for (int i = a + (int)threadIdx.x; i < b; i += 256) {
+    const int nr = b - a;                 // <= 64
+    if (t < nr) {
+        const int i = a + t;
         double2 w = make_double2(0.0, 0.0);
         if (i > j) {
-            const double2 v = VW[i + (size_t)N * c];
+            const double2 vi = VW[i + (size_t)N * c];
+            const double2 av = zmul(al, vi);
             w = wt[i];
-            const double2 av = zmul(al, v);
             w.x += av.x;
             w.y += av.y;
+            G[i + (size_t)ldg * j] = vi;
         }
         VW[i + (size_t)N * (kTrdNb + c)] = w;
         WV[i + (size_t)N * c] = w;
-        if (update_next && i >= j + 1) {
-            double2 g = G[i + (size_t)ldg * (j + 1)];
-            for (int q = 0; q <= c; ++q) {
-                const double2 vi = VW[i + (size_t)N * q];
-                const double2 wi = q == c ? w : VW[i + (size_t)N * (kTrdNb + q)];
-                const double2 vr = VW[(j + 1) + (size_t)N * q];
-                const double2 wr = q == c ? wj1 : VW[(j + 1) + (size_t)N * (kTrdNb + q)];
-                const double2 t1 = zmulc(vi, wr), t2 = zmulc(wi, vr);
-                g.x -= t1.x + t2.x;
-                g.y -= t1.y + t2.y;
-            }
-            G[i + (size_t)ldg * (j + 1)] = g;
-            if (i >= j + 3) nrm += g.x * g.x + g.y * g.y;
+        sw[t] = w;
+    }
+    if (!update_next) return;
+    __syncthreads();
+    // column j+1 update: thread (row r, group g) sums the panel columns q = g, g+4, ..
+    // W[j+1, c] = w~[j+1] + alpha (v[j+1] = 1)
+    const int r = t & 63, g = t >> 6;
+    double2 wj1 = wt[j + 1];
+    wj1.x += al.x;
+    wj1.y += al.y;
+    double2 acc = make_double2(0.0, 0.0);
+    const int i = a + r;
+    if (r < nr && i >= j + 1) {
+        for (int q = g; q <= c; q += 4) {
+            const double2 vi = VW[i + (size_t)N * q];
+            const double2 wi = q == c ? sw[r] : VW[i + (size_t)N * (kTrdNb + q)];
+            const double2 vr = VW[(j + 1) + (size_t)N * q];
+            const double2 wr = q == c ? wj1 : VW[(j + 1) + (size_t)N * (kTrdNb + q)];
+            const double2 t1 = zmulc(vi, wr), t2 = zmulc(wi, vr);
+            acc.x += t1.x + t2.x;
+            acc.y += t1.y + t2.y;
         }
     }
-    if (update_next) {
-        nrm = block_sum<256>(nrm, red);
-        if (threadIdx.x == 0) part[blockIdx.x] = nrm;
+    red4[g][r] = acc;
+    __syncthreads();
+    double nrm = 0.0;
+    if (t < 64) {
+        double2 gv = make_double2(0.0, 0.0);
+        if (t < nr && i >= j + 1) {
+            gv = G[i + (size_t)ldg * (j + 1)];
+            for (int q = 0; q < 4; ++q) { gv.x -= red4[q][t].x; gv.y -= red4[q][t].y; }
+            G[i + (size_t)ldg * (j + 1)] = gv;
+            if (i >= j + 3) nrm = gv.x * gv.x + gv.y * gv.y;
+        }
+        arow[t] = (t < nr && i >= j + 3) ? gv : make_double2(0.0, 0.0);
+    }
+    nrm = block_sum<256>(nrm, red);     // also orders arow before the dots
+    if (t == 0) part[blockIdx.x] = nrm;
+    // dots over this chunk: thread (dot dq, row group g) sums conj(W[i, q]) a_i
+    // (dq < c+1) or conj(V[i, q]) a_i (dq >= c+1) over rows a + g, a + g + 4, ..
+    const int nq = c + 1;
+    double2 dacc = make_double2(0.0, 0.0);
+    if (r < 2 * nq) {
+        const int q = r % nq, isv = r / nq;
+        const double2* col = VW + (size_t)N * ((isv ? 0 : kTrdNb) + q);
+        for (int rr = g; rr < nr; rr += 4) {
+            const double2 p = zcmul(col[a + rr], arow[rr]);
+            dacc.x += p.x;
+            dacc.y += p.y;
+        }
+    }
+    red4[g][r] = dacc;
+    __syncthreads();
+    if (t < 2 * nq) {
+        const int q = t % nq, isv = t / nq;
+        double2 sum = make_double2(0.0, 0.0);
+        for (int q4 = 0; q4 < 4; ++q4) { sum.x += red4[q4][t].x; sum.y += red4[q4][t].y; }
+        pdot[(size_t)blockIdx.x * 2 * kTrdNb + isv * kTrdNb + q] = sum;
     }
 }
 
@@ -816,83 +879,219 @@ __global__ __launch_bounds__(256) void k_dc_perm(const DcMerge* __restrict__ pla
 // --------------------------------------------------- back-transformation
 // Y = [v_j0 .. v_j0+nb-1] (N x kBtNb, zero-padded) from the reflectors below the diagonal.
 __global__ __launch_bounds__(256) void k_bt_y(const double2* __restrict__ G, int ldg, int N, int j0, int nbb,
-                                              double2* __restrict__ Y) {
+                                              const double2* __restrict__ tau, double2* __restrict__ Y) {
     const int i = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
     if (i >= N) return;
     const int j = j0 + c;
     double2 v = make_double2(0.0, 0.0);
-    if (c < nbb && i > j) v = G[i + (size_t)ldg * j];
+    if (c < nbb && i > j) {
+        const double2 t = tau[j];
+        if (t.x != 0.0 || t.y != 0.0) v = G[i + (size_t)ldg * j];
+    }
     Y[i + (size_t)N * c] = v;
 }
 
-// T of H_j0 .. H_j0+nb-1 = I - Y T Y^H (forward, columnwise): T[i][i] = tau_i,
-// T[0:i, i] = -tau_i T[0:i, 0:i] (Y^H Y)[0:i, i]; S = Y^H Y from split-K partials.
-__global__ __launch_bounds__(1024) void k_bt_t(const double2* __restrict__ Spart, int splits,
-                                               const double2* __restrict__ tau, int j0, int nbb,
-                                               double2* __restrict__ Tm) {
-    __shared__ double2 S[kBtNb][kBtNb + 1];
-    __shared__ double2 T[kBtNb][kBtNb + 1];   // T[r][c]
+// S = Y^H Y from the split-K partials (one 64x64 block).
+__global__ __launch_bounds__(1024) void k_bt_sred(const double2* __restrict__ Spart, int splits,
+                                                  double2* __restrict__ S) {
     for (int q = threadIdx.x; q < kBtNb * kBtNb; q += 1024) {
-        const int r = q % kBtNb, c = q / kBtNb;
         double2 s = make_double2(0.0, 0.0);
         for (int z = 0; z < splits; ++z) {
-            const double2 v = Spart[(size_t)z * kBtNb * kBtNb + r + kBtNb * c];
+            const double2 v = Spart[(size_t)z * kBtNb * kBtNb + q];
             s.x += v.x;
             s.y += v.y;
         }
-        S[r][c] = s;
-        T[r][c] = make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    for (int i = 0; i < nbb; ++i) {
-        const double2 ti = tau[j0 + i];
-        // T[r][i] = -tau_i sum_{q=r}^{i-1} T[r][q] S[q][i]  for r < i
-        const int r = threadIdx.x;
-        double2 acc = make_double2(0.0, 0.0);
-        if (r < i) {
-            for (int q = r; q < i; ++q) {
-                const double2 p = zmul(T[r][q], S[q][i]);
-                acc.x += p.x;
-                acc.y += p.y;
-            }
-        }
-        __syncthreads();
-        if (r < i) {
-            const double2 p = zmul(ti, acc);
-            T[r][i] = make_double2(-p.x, -p.y);
-        }
-        if (r == i) T[i][i] = ti;
-        __syncthreads();
-    }
-    for (int q = threadIdx.x; q < kBtNb * kBtNb; q += 1024) {
-        const int r = q % kBtNb, c = q / kBtNb;
-        Tm[r + kBtNb * c] = T[r][c];
+        S[q] = s;
     }
 }
 
-// P = (sum of split-K partials) T, rows of the m x kBtNb product.
-__global__ __launch_bounds__(256) void k_bt_pt(const double2* __restrict__ Ppart, int splits, int m,
-                                               const double2* __restrict__ Tm, double2* __restrict__ P) {
-    __shared__ double2 T[kBtNb][kBtNb];
-    for (int q = threadIdx.x; q < kBtNb * kBtNb; q += 256) T[q % kBtNb][q / kBtNb] = Tm[q];
+// P = (X Y) T for H_j0 .. H_j0+nb-1 = I - Y T Y^H without forming T: T^{-1} is
+// the strict upper triangle of Y^H Y with 1/tau_i on its diagonal (a
+// reflector with tau = 0 has its column of Y replaced by zero), so every row
+// of P solves p T^{-1} = (X Y)_row by forward substitution,
+//   p_i = tau_i ((X Y)_i - sum_{q<i} p_q S[q][i]).
+// One wave per row of X, lane q holding p_q; the split-K partials of X Y are
+// summed on the way.
+__global__ __launch_bounds__(256) void k_bt_solve(const double2* __restrict__ Ppart, int splits, int m,
+                                                  const double2* __restrict__ S, const double2* __restrict__ tau,
+                                                  int j0, int nbb, double2* __restrict__ P) {
+    __shared__ double2 Ss[kBtNb][kBtNb + 1];
+    for (int q = threadIdx.x; q < kBtNb * kBtNb; q += 256) Ss[q % kBtNb][q / kBtNb] = S[q];
     __syncthreads();
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), c = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (i >= m) return;
-    // row i of the summed partials, one column per lane, then the row times T
-    double2 s = make_double2(0.0, 0.0);
+    double2 b = make_double2(0.0, 0.0);
     for (int z = 0; z < splits; ++z) {
-        const double2 v = Ppart[(size_t)z * m * kBtNb + i + (size_t)m * c];
-        s.x += v.x;
-        s.y += v.y;
+        const double2 v = Ppart[(size_t)z * m * kBtNb + i + (size_t)m * lane];
+        b.x += v.x;
+        b.y += v.y;
     }
-    double2 acc = make_double2(0.0, 0.0);
-    for (int q = 0; q < kBtNb; ++q) {
-        const double2 sq = make_double2(__shfl(s.x, q, 64), __shfl(s.y, q, 64));
-        const double2 p = zmul(sq, T[q][c]);
-        acc.x += p.x;
-        acc.y += p.y;
+    double2 p = make_double2(0.0, 0.0);
+    for (int c = 0; c < nbb; ++c) {
+        // sum_{q<c} p_q S[q][c] over the lanes q < c
+        double2 t = lane < c ? zmul(p, Ss[lane][c]) : make_double2(0.0, 0.0);
+        t.x = wave_sum(t.x);
+        t.y = wave_sum(t.y);
+        if (lane == c) {
+            const double2 tc = tau[j0 + c];
+            p = zmul(tc, make_double2(b.x - t.x, b.y - t.y));
+        }
     }
-    P[i + (size_t)m * c] = acc;
+    P[i + (size_t)m * lane] = lane < nbb ? p : make_double2(0.0, 0.0);
+}
+
+// ------------------------------------------------ Cholesky QR re-gauge
+// Exact re-gauge of a centre move ("Note added": the orthogonality centre is
+// moved by QR): A (m x r) = Q R with Q an isometry, by shifted Cholesky QR
+// followed by two plain Cholesky QR passes, all in FP64.  The first pass
+// factors A^H A + s I with s = 11 (m r + r (r+1)) u ||A||_F^2, which keeps the
+// Cholesky factorisation defined for condition numbers up to about 1/u and
+// leaves Q_1 with condition number below about 1/sqrt(u); the next two passes
+// make it orthonormal to working accuracy.  R = R_3 R_2 R_1 (upper).
+
+// G[i][i] += coef * trace(G) (one work-group); clears the failure flag.
+__global__ __launch_bounds__(256) void k_qr_shift(double2* __restrict__ G, int ldg, int r, double coef,
+                                                  DevInfo* __restrict__ info) {
+    __shared__ double red[4];
+    double t = 0.0;
+    for (int i = threadIdx.x; i < r; i += 256) t += G[i + (size_t)ldg * i].x;
+    t = block_sum<256>(t, red);
+    for (int i = threadIdx.x; i < r; i += 256) G[i + (size_t)ldg * i].x += coef * t;
+    if (threadIdx.x == 0) {
+        info->qr_shift = coef * t;
+        info->qr_fail = 0;
+    }
+}
+
+// Upper Cholesky factor of the kb x kb diagonal block at (k0, k0), in place (one
+// work-group, the block in LDS).  A pivot at or below its bound sets
+// info->qr_fail and is replaced by a tiny positive value, so that the pass still
+// ends with finite data.  Bounds by pass kind:
+//   kQrShifted  half the shift, which every pivot of the shifted Gram exceeds;
+//   kQrAfterShift  1e-14: Q_1 conditioned beyond 1e7, past Cholesky QR twice;
+//   kQrFinal    1/2: the Gram of a nearly orthonormal Q;
+//   kQrPlain    1e-12 of the column's own squared norm (diag0): the column is
+//               independent of the earlier ones to 1e-6 in angle, so one more
+//               pass makes Q orthonormal.
+enum { kQrShifted = 0, kQrAfterShift = 1, kQrFinal = 2, kQrPlain = 3 };
+__global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ G, int ldg, int k0, int kb, int pass,
+                                                   const double* __restrict__ diag0,
+                                                   DevInfo* __restrict__ info) {
+    __shared__ double2 B[64][65];
+    for (int q = threadIdx.x; q < kb * kb; q += 256) {
+        const int i = q % kb, j = q / kb;
+        B[i][j] = G[(k0 + i) + (size_t)ldg * (k0 + j)];
+    }
+    __syncthreads();
+    const double floor_piv = 1e-300;
+    const double bound = pass == kQrShifted ? 0.5 * info->qr_shift
+                       : pass == kQrAfterShift ? 1e-14 : pass == kQrFinal ? 0.5 : 0.0;
+    for (int i = 0; i < kb; ++i) {
+        const double piv = B[i][i].x;
+        const double bi = pass == kQrPlain ? 1e-12 * diag0[k0 + i] : bound;
+        if (threadIdx.x == 0 && !(piv > bi)) info->qr_fail = 1;
+        const double dii = sqrt(fmax(piv, floor_piv));
+        __syncthreads();
+        // row i of R: R[i][j] = B[i][j] / d for j > i
+        for (int j = i + 1 + (int)threadIdx.x; j < kb; j += 256) {
+            B[i][j].x /= dii;
+            B[i][j].y /= dii;
+        }
+        if (threadIdx.x == 0) B[i][i] = make_double2(dii, 0.0);
+        __syncthreads();
+        // trailing upper part: B[p][q] -= conj(R[i][p]) R[i][q] for i < p <= q
+        const int n2 = kb - i - 1;
+        for (int e = threadIdx.x; e < n2 * n2; e += 256) {
+            const int p = i + 1 + e % n2, q = i + 1 + e / n2;
+            if (p <= q) {
+                const double2 t = zcmul(B[i][p], B[i][q]);
+                B[p][q].x -= t.x;
+                B[p][q].y -= t.y;
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = threadIdx.x; q < kb * kb; q += 256) {
+        const int i = q % kb, j = q / kb;
+        G[(k0 + i) + (size_t)ldg * (k0 + j)] = i <= j ? B[i][j] : make_double2(0.0, 0.0);
+    }
+}
+
+// Row block of R right of the diagonal block: R[k, j] = R_kk^{-H} G[k, j] for the
+// columns j in [k0 + kb, r) (one wave per column, forward substitution).
+__global__ __launch_bounds__(256) void k_chol_row(double2* __restrict__ G, int ldg, int k0, int kb, int r) {
+    __shared__ double2 Rk[64][65];
+    for (int q = threadIdx.x; q < kb * kb; q += 256) {
+        const int i = q % kb, j = q / kb;
+        Rk[i][j] = G[(k0 + i) + (size_t)ldg * (k0 + j)];
+    }
+    __syncthreads();
+    const int j = k0 + kb + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= r) return;
+    double2* col = G + (size_t)ldg * j + k0;
+    const double2 g = lane < kb ? col[lane] : make_double2(0.0, 0.0);
+    double2 x = make_double2(0.0, 0.0);
+    for (int i = 0; i < kb; ++i) {
+        // sum_{q<i} conj(R[q][i]) x_q
+        double2 t = lane < i ? zcmul(Rk[lane][i], x) : make_double2(0.0, 0.0);
+        t.x = wave_sum(t.x);
+        t.y = wave_sum(t.y);
+        if (lane == i) {
+            const double rii = Rk[i][i].x;
+            x = make_double2((g.x - t.x) / rii, (g.y - t.y) / rii);
+        }
+    }
+    if (lane < kb) col[lane] = x;
+}
+
+// Columns k0 .. k0+kb of Q (A is the whole m x r matrix): q_row R_kk = a_row (the
+// earlier blocks already subtracted), one wave per row, forward substitution
+// along the row.
+__global__ __launch_bounds__(256) void k_qr_rowsolve(double2* __restrict__ A, int lda, int m,
+                                                     const double2* __restrict__ G, int ldg, int k0, int kb) {
+    __shared__ double2 Rk[64][65];
+    for (int q = threadIdx.x; q < kb * kb; q += 256) {
+        const int i = q % kb, j = q / kb;
+        Rk[i][j] = G[(k0 + i) + (size_t)ldg * (k0 + j)];
+    }
+    __syncthreads();
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= m) return;
+    double2* row = A + i + (size_t)lda * k0;
+    const double2 b = lane < kb ? row[(size_t)lda * lane] : make_double2(0.0, 0.0);
+    double2 p = make_double2(0.0, 0.0);
+    for (int c = 0; c < kb; ++c) {
+        double2 t = lane < c ? zmul(p, Rk[lane][c]) : make_double2(0.0, 0.0);
+        t.x = wave_sum(t.x);
+        t.y = wave_sum(t.y);
+        if (lane == c) {
+            const double rcc = Rk[c][c].x;
+            p = make_double2((b.x - t.x) / rcc, (b.y - t.y) / rcc);
+        }
+    }
+    if (lane < kb) row[(size_t)lda * lane] = p;
+}
+
+// diag0[i] = G[i][i] (the columns' squared norms, for the plain pass's bounds);
+// clears the failure flag.
+__global__ __launch_bounds__(256) void k_qr_diag0(const double2* __restrict__ G, int ldg, int r,
+                                                  double* __restrict__ diag0, DevInfo* __restrict__ info) {
+    for (int i = threadIdx.x; i < r; i += 256) diag0[i] = G[i + (size_t)ldg * i].x;
+    if (threadIdx.x == 0) info->qr_fail = 0;
+}
+
+// Rp (r x r, stride r) = the upper triangle of G.
+__global__ __launch_bounds__(256) void k_qr_triu(const double2* __restrict__ G, int ldg, int r,
+                                                 double2* __restrict__ Rp) {
+    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    if (i < r) Rp[i + (size_t)r * j] = i <= j ? G[i + (size_t)ldg * j] : make_double2(0.0, 0.0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_from_f64(const double2* __restrict__ Xd, int ldd, int m,
+                                                  C2<T>* __restrict__ X, int ld) {
+    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    if (i < m) X[i + (size_t)ld * j] = from_d2<T>(Xd[i + (size_t)ldd * j]);
 }
 
 // ------------------------------------------------------------ host plans
@@ -933,7 +1132,9 @@ size_t heev_bytes(int m_max, int n_max) {
     b += 2 * al(N * 2 * kTrdNb * sizeof(double2));              // VW, WV
     b += 2 * al(N * sizeof(double2));                           // yraw, wt
     b += al(2 * kTrdNb * sizeof(double2));                      // dots
-    b += al(4 * kPart * sizeof(double));                        // part, part2
+    b += al(kPart * sizeof(double));                            // norm partials
+    b += al((size_t)kPart * 2 * kTrdNb * sizeof(double2));      // dot partials
+    b += al((N / kGemvWaves + 1) * sizeof(double2));            // partials of w~^H v
     b += al(N * sizeof(double2));                               // tau
     b += 2 * al(N * sizeof(double));                            // d, e
     b += al(N * kBtNb * sizeof(double2));                       // Y
@@ -962,7 +1163,9 @@ void heev_carve(char* p, int m_max, int n_max, HeevWork& w) {
     w.yraw = (double2*)take(N * sizeof(double2));
     w.wt = (double2*)take(N * sizeof(double2));
     w.dots = (double2*)take(2 * kTrdNb * sizeof(double2));
-    w.part = (double*)take(4 * kPart * sizeof(double));
+    w.part = (double*)take(kPart * sizeof(double));
+    w.pdot = (double2*)take((size_t)kPart * 2 * kTrdNb * sizeof(double2));
+    w.palpha = (double2*)take((N / kGemvWaves + 1) * sizeof(double2));
     w.tau = (double2*)take(N * sizeof(double2));
     w.d = (double*)take(N * sizeof(double));
     w.e = (double*)take(N * sizeof(double));
@@ -1019,6 +1222,7 @@ const DcPlan& dc_plan(HeevPlans& hp, int N) {
 // Hermitian G (w.G, ld w.ldg), which is overwritten by its reflectors.
 void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
     const int ldg = N + 8;
+    if (N > 64 * kPart) throw HeevFailure{"tridiagonalisation row chunks"};
     // ---- tridiagonalisation: the trailing matrix-vector products are booked
     // as K_TRIDIAG, the vector kernels and the rank-2 nb panel updates as K_TRDAUX
     for (int j0 = 0; j0 < N - 1; j0 += kTrdNb) {
@@ -1030,17 +1234,14 @@ void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
                       (const double2*)w.G, ldg, N, j0, w.part);
         for (int c = 0; c < nbb; ++c) {
             const int j = j0 + c, len = N - j - 1;
-            const int waves = len + 2 * c;
-            launch_booked(pf, K_TRIDIAG, 8.0 * (double)len * waves, 16.0 * (double)len * waves,
-                          k_trd_gemv, dim3((waves + kGemvWaves - 1) / kGemvWaves), dim3(1024),
-                          (size_t)len * sizeof(double2), st, (const double2*)w.G, ldg, N, j, c,
-                          (const double*)w.part, w.VW, w.WV, w.yraw, w.dots, w.tau, w.d, w.e);
-            launch_booked(pf, K_TRDAUX, 16.0 * len * c, 16.0 * len * (2.0 * c + 5.0), k_trd_corr, dim3(kPart),
-                          dim3(256), 0, st, w.G, ldg, N, j, c, (const double2*)w.tau, (const double2*)w.VW,
-                          (const double2*)w.dots, (const double2*)w.yraw, w.wt, w.part + 2 * kPart);
+            const int groups = (len + kGemvWaves - 1) / kGemvWaves;   // <= 512: two partials per thread of k_trd_next
+            launch_booked(pf, K_TRIDIAG, 8.0 * (double)len * len, 16.0 * (double)len * len, k_trd_gemv,
+                          dim3(groups), dim3(64 * kGemvWaves), (size_t)len * sizeof(double2), st, w.G, ldg, N,
+                          j, c, (const double*)w.part, (const double2*)w.pdot, w.VW, w.WV, w.wt, w.palpha, w.tau,
+                          w.d, w.e);
             launch_booked(pf, K_TRDAUX, 16.0 * len * (c + 1), 16.0 * len * (2.0 * c + 6.0), k_trd_next, dim3(kPart),
-                          dim3(256), 0, st, w.G, ldg, N, j, c, (int)(c + 1 < nbb), (const double2*)w.tau, w.VW,
-                          w.WV, (const double2*)w.wt, (const double*)(w.part + 2 * kPart), w.part);
+                          dim3(256), 0, st, w.G, ldg, N, j, c, (int)(c + 1 < nbb), groups, (const double2*)w.tau,
+                          w.VW, w.WV, (const double2*)w.wt, (const double2*)w.palpha, w.part, w.pdot);
         }
         const int k0 = j0 + nbb;
         zgemm<0, 1, 1>(N - k0, N - k0, 2 * kTrdNb, w.VW + k0, N, w.WV + k0, N, w.G + k0 + (size_t)ldg * k0, ldg,
@@ -1079,6 +1280,35 @@ void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
     pf.end(st, K_DC, 2.0 * (double)N * N * N, 24.0 * (double)N * N);
 }
 
+// X (rows x N, FP64, stride ldx) <- X Q_H, blocks of kBtNb reflectors in forward
+// order: X[:, j0+1:] -= ((X[:, j0+1:] Y) T) Y^H with Y the block's reflectors and
+// T its triangular factor (H_j0 .. H_j0+nb-1 = I - Y T Y^H).
+static void apply_qh(double2* X, int rows, int ldx, int N, HeevWork& w, Profiler& pf, hipStream_t st) {
+    const int ldg = N + 8;
+    for (int j0 = 0; j0 < N - 1; j0 += kBtNb) {
+        const int nbb = std::min(kBtNb, N - 1 - j0);
+        const int K = N - j0 - 1;                  // rows j0+1 .. N-1 of Y
+        const int splits = (K + kSplitK - 1) / kSplitK;
+        launch_booked(pf, K_BTAUX, 0.0, 32.0 * N * kBtNb, k_bt_y, dim3((N + 255) / 256, kBtNb), dim3(256), 0, st,
+                      (const double2*)w.G, ldg, N, j0, nbb, (const double2*)w.tau, w.Y);
+        const double2* Ys = w.Y + (j0 + 1);
+        // S = Y^H Y (split-K partials, then summed)
+        zgemm<1, 0, 0>(kBtNb, kBtNb, K, Ys, N, Ys, N, w.Cpart, kBtNb, st, splits, kSplitK, kSplitK, kSplitK,
+                       (size_t)kBtNb * kBtNb, &pf, K_BTAUX);
+        launch_booked(pf, K_BTAUX, 0.0, 16.0 * kBtNb * kBtNb * (splits + 1), k_bt_sred, dim3(1), dim3(1024), 0, st,
+                      (const double2*)w.Cpart, splits, w.Tm);
+        // X Y (split-K), then P = (X Y) T by row-wise substitution
+        zgemm<0, 0, 0>(rows, kBtNb, K, X + (size_t)ldx * (j0 + 1), ldx, Ys, N, w.Cpart, rows, st, splits, kSplitK,
+                       (size_t)kSplitK * ldx, kSplitK, (size_t)rows * kBtNb, &pf, K_BACK);
+        launch_booked(pf, K_BTAUX, 8.0 * rows * kBtNb * kBtNb / 2, 16.0 * rows * kBtNb * (splits + 1), k_bt_solve,
+                      dim3((rows + 3) / 4), dim3(256), 0, st, (const double2*)w.Cpart, splits, rows,
+                      (const double2*)w.Tm, (const double2*)w.tau, j0, nbb, w.P);
+        // X[:, j0+1:] -= P Y^H
+        zgemm<0, 1, 1>(rows, K, kBtNb, w.P, rows, Ys, N, X + (size_t)ldx * (j0 + 1), ldx, st, 1, 0, 0, 0, 0, &pf,
+                       K_BACK);
+    }
+}
+
 // X (m x N, storage T, stride ld) <- X Q_H Z for the Gram eigen-decomposition
 // of X, all in FP64.  Throws HeevFailure on a HIP error.
 template <typename T>
@@ -1087,46 +1317,20 @@ void heev_precondition(C2<T>* X, int m, int N, int ld, HeevWork& w, Profiler& pf
     const int ldx = ((w.cap_m + 1) & ~1) + 8;
     const int ldg = N + 8;
     // ---- X -> FP64, Gram
-    pf.begin(st);
-    hipLaunchKernelGGL((k_to_f64<T>), dim3((m + 255) / 256, N), dim3(256), 0, st, (const C2<T>*)X, m, ld, w.Xd,
-                       ldx);
-    zgemm<1, 0, 0>(N, N, m, w.Xd, ldx, w.Xd, ldx, w.G, ldg, st);
-    pf.end(st, K_HGRAM, 8.0 * (double)N * N * m, (double)m * N * (sizeof(C2<T>) + 32.0) + 16.0 * N * N);
+    launch_booked(pf, K_BTAUX, 0.0, (double)m * N * (sizeof(C2<T>) + 16.0), k_to_f64<T>, dim3((m + 255) / 256, N),
+                  dim3(256), 0, st, (const C2<T>*)X, m, ld, w.Xd, ldx);
+    zgemm<1, 0, 0>(N, N, m, w.Xd, ldx, w.Xd, ldx, w.G, ldg, st, 1, 0, 0, 0, 0, &pf, K_HGRAM);
 
     heev_run(N, w, pf, st);
 
-    // ---- X <- X Q_H, blocks of kBtNb reflectors in forward order
-    pf.begin(st);
-    for (int j0 = 0; j0 < N - 1; j0 += kBtNb) {
-        const int nbb = std::min(kBtNb, N - 1 - j0);
-        const int K = N - j0 - 1;                  // rows j0+1 .. N-1 of Y
-        const int splits = (K + kSplitK - 1) / kSplitK;
-        hipLaunchKernelGGL(k_bt_y, dim3((N + 255) / 256, kBtNb), dim3(256), 0, st, (const double2*)w.G, ldg, N,
-                           j0, nbb, w.Y);
-        const double2* Ys = w.Y + (j0 + 1);
-        // S = Y^H Y (split-K partials), T
-        zgemm<1, 0, 0>(kBtNb, kBtNb, K, Ys, N, Ys, N, w.Cpart, kBtNb, st, splits, kSplitK, kSplitK, kSplitK,
-                       (size_t)kBtNb * kBtNb);
-        hipLaunchKernelGGL(k_bt_t, dim3(1), dim3(1024), 0, st, (const double2*)w.Cpart, splits,
-                           (const double2*)w.tau, j0, nbb, w.Tm);
-        // P = X[:, j0+1:] Y (split-K), P <- P T
-        zgemm<0, 0, 0>(m, kBtNb, K, w.Xd + (size_t)ldx * (j0 + 1), ldx, Ys, N, w.Cpart, m, st, splits, kSplitK,
-                       (size_t)kSplitK * ldx, kSplitK, (size_t)m * kBtNb);
-        hipLaunchKernelGGL(k_bt_pt, dim3((m + 3) / 4), dim3(256), 0, st, (const double2*)w.Cpart, splits, m,
-                           (const double2*)w.Tm, w.P);
-        // X[:, j0+1:] -= P Y^H
-        zgemm<0, 1, 1>(m, K, kBtNb, w.P, m, Ys, N, w.Xd + (size_t)ldx * (j0 + 1), ldx, st);
-    }
-    pf.end(st, K_BACK, 8.0 * (double)m * N * N, 32.0 * (double)m * N * (N / kBtNb + 1));
+    // ---- X <- X Q_H
+    apply_qh(w.Xd, m, ldx, N, w, pf, st);
 
     // ---- X <- Xd Z (real view: 2m x N times N x N), rounded to the storage precision
-    pf.begin(st);
-    {
-        dim3 grid((2 * m + ZBM - 1) / ZBM, (N + ZBN - 1) / ZBN);
-        hipLaunchKernelGGL((k_dgemm<T>), grid, dim3(256), 0, st, 2 * m, N, N, (const double*)w.Xd, 2 * ldx,
-                           (const double*)w.Z, N, (T*)X, 2 * ld);
-    }
-    pf.end(st, K_BACK, 4.0 * (double)m * N * N, 16.0 * (double)m * N + 8.0 * N * N + (double)m * N * sizeof(C2<T>));
+    launch_booked(pf, K_HOUT, 4.0 * (double)m * N * N,
+                  16.0 * (double)m * N + 8.0 * (double)N * N + (double)m * N * sizeof(C2<T>), k_dgemm<T>,
+                  dim3((2 * m + ZBM - 1) / ZBM, (N + ZBN - 1) / ZBN), dim3(256), 0, st, 2 * m, N, N,
+                  (const double*)w.Xd, 2 * ldx, (const double*)w.Z, N, (T*)X, 2 * ld);
     if (hipGetLastError() != hipSuccess) throw HeevFailure{"eigen-preconditioner launch"};
     w.n_runs += 1;
 }
@@ -1152,23 +1356,7 @@ void heev_host(int N, const double* Gh, double* wh, double* Vh, HeevWork& w, Pro
     for (int i = 0; i < N; ++i) eye[i + (size_t)ldx * i] = make_double2(1.0, 0.0);
     if (hipMemcpyAsync(w.Xd, eye.data(), eye.size() * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess)
         throw HeevFailure{"copy in"};
-    for (int j0 = 0; j0 < N - 1; j0 += kBtNb) {
-        const int nbb = std::min(kBtNb, N - 1 - j0);
-        const int K = N - j0 - 1;
-        const int splits = (K + kSplitK - 1) / kSplitK;
-        hipLaunchKernelGGL(k_bt_y, dim3((N + 255) / 256, kBtNb), dim3(256), 0, st, (const double2*)w.G, ldg, N,
-                           j0, nbb, w.Y);
-        const double2* Ys = w.Y + (j0 + 1);
-        zgemm<1, 0, 0>(kBtNb, kBtNb, K, Ys, N, Ys, N, w.Cpart, kBtNb, st, splits, kSplitK, kSplitK, kSplitK,
-                       (size_t)kBtNb * kBtNb);
-        hipLaunchKernelGGL(k_bt_t, dim3(1), dim3(1024), 0, st, (const double2*)w.Cpart, splits,
-                           (const double2*)w.tau, j0, nbb, w.Tm);
-        zgemm<0, 0, 0>(N, kBtNb, K, w.Xd + (size_t)ldx * (j0 + 1), ldx, Ys, N, w.Cpart, N, st, splits, kSplitK,
-                       (size_t)kSplitK * ldx, kSplitK, (size_t)N * kBtNb);
-        hipLaunchKernelGGL(k_bt_pt, dim3((N + 3) / 4), dim3(256), 0, st, (const double2*)w.Cpart, splits, N,
-                           (const double2*)w.Tm, w.P);
-        zgemm<0, 1, 1>(N, K, kBtNb, w.P, N, Ys, N, w.Xd + (size_t)ldx * (j0 + 1), ldx, st);
-    }
+    apply_qh(w.Xd, N, ldx, N, w, pf, st);
     // V (complex, N x N, ld ldx) into G's storage
     {
         dim3 grid((2 * N + ZBM - 1) / ZBM, (N + ZBN - 1) / ZBN);
@@ -1188,5 +1376,99 @@ void heev_host(int N, const double* Gh, double* wh, double* Vh, HeevWork& w, Pro
             Vh[2 * (r * N + c) + 1] = g[r + (size_t)ldg * c].y;
         }
 }
+
+// Q (m x r, storage T, stride ldq) and R (r x r, storage T, stride r) with A = Q R,
+// A (m x r, storage T, stride lda); Q may overwrite A (it is written last).  All
+// arithmetic in FP64.  First Cholesky QR twice; if a pivot of it falls below its
+// bound (A too ill-conditioned), shifted Cholesky QR and two more passes from A
+// again.  Returns false, with Q and R unwritten, if that too meets a pivot below
+// its bound (A numerically rank-deficient).  Reads the flag back through the
+// pinned info_host (synchronises the stream once or twice).
+template <typename T>
+bool cholqr3(const C2<T>* A, int m, int r, int lda, C2<T>* Q, int ldq, C2<T>* R, DevInfo* info,
+             DevInfo* info_host, HeevWork& w, Profiler& pf, hipStream_t st) {
+    if (r > w.cap_n || m > w.cap_m || r < 1 || 2 * (size_t)r * r > (size_t)w.cap_n * w.cap_n)
+        throw HeevFailure{"Cholesky QR capacity"};
+    const int ldx = ((w.cap_m + 1) & ~1) + 8;
+    const int ldg = r + 8;
+    double2* Ad = w.Xd;
+    double2* Rt = nullptr;            // accumulated R (one of Z, U)
+    double2* Rp = (double2*)w.Z2;     // this pass's R
+    const double u = 1.1102230246251565e-16;
+    auto pass_run = [&](int kind) {
+        zgemm<1, 0, 0>(r, r, m, Ad, ldx, Ad, ldx, w.G, ldg, st, 1, 0, 0, 0, 0, &pf, K_QR);
+        if (kind == kQrShifted)
+            launch_booked(pf, K_QR, 0.0, 16.0 * r, k_qr_shift, dim3(1), dim3(256), 0, st, w.G, ldg, r,
+                          11.0 * ((double)m * r + (double)r * (r + 1)) * u, info);
+        if (kind == kQrPlain)
+            launch_booked(pf, K_QR, 0.0, 24.0 * r, k_qr_diag0, dim3(1), dim3(256), 0, st, (const double2*)w.G, ldg, r,
+                          w.dv, info);
+        for (int k0 = 0; k0 < r; k0 += 64) {
+            const int kb = std::min(64, r - k0), rest = r - k0 - kb;
+            launch_booked(pf, K_QR, 0.0, 32.0 * kb * kb, k_chol_diag, dim3(1), dim3(256), 0, st, w.G, ldg, k0, kb,
+                          kind, (const double*)w.dv, info);
+            if (rest > 0) {
+                launch_booked(pf, K_QR, 4.0 * kb * kb * rest, 32.0 * kb * rest, k_chol_row, dim3((rest + 3) / 4),
+                              dim3(256), 0, st, w.G, ldg, k0, kb, r);
+                double2* Rrow = w.G + k0 + (size_t)ldg * (k0 + kb);
+                zgemm<1, 0, 1>(rest, rest, kb, Rrow, ldg, Rrow, ldg, w.G + (k0 + kb) + (size_t)ldg * (k0 + kb), ldg,
+                               st, 1, 0, 0, 0, 0, &pf, K_QR);
+            }
+        }
+        // Ad <- Ad R^{-1}, column blocks in order
+        for (int k0 = 0; k0 < r; k0 += 64) {
+            const int kb = std::min(64, r - k0);
+            if (k0 > 0)
+                zgemm<0, 0, 1>(m, kb, k0, Ad, ldx, w.G + (size_t)ldg * k0, ldg, Ad + (size_t)ldx * k0, ldx, st, 1, 0,
+                               0, 0, 0, &pf, K_QR);
+            launch_booked(pf, K_QR, 4.0 * (double)m * kb * kb, 32.0 * (double)m * kb, k_qr_rowsolve,
+                          dim3((m + 3) / 4), dim3(256), 0, st, Ad, ldx, m, (const double2*)w.G, ldg, k0, kb);
+        }
+        // R accumulation: Rt = R_pass Rt
+        if (!Rt) {
+            Rt = (double2*)w.Z;
+            launch_booked(pf, K_QR, 0.0, 32.0 * r * r, k_qr_triu, dim3((r + 255) / 256, r), dim3(256), 0, st,
+                          (const double2*)w.G, ldg, r, Rt);
+        } else {
+            launch_booked(pf, K_QR, 0.0, 32.0 * r * r, k_qr_triu, dim3((r + 255) / 256, r), dim3(256), 0, st,
+                          (const double2*)w.G, ldg, r, Rp);
+            double2* Rn = Rt == (double2*)w.Z ? (double2*)w.U : (double2*)w.Z;
+            zgemm<0, 0, 0>(r, r, r, Rp, r, Rt, r, Rn, r, st, 1, 0, 0, 0, 0, &pf, K_QR);
+            Rt = Rn;
+        }
+    };
+    auto failed = [&]() {
+        if (hipMemcpyAsync(info_host, info, sizeof(DevInfo), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            throw HeevFailure{"Cholesky QR flag read"};
+        return info_host->qr_fail != 0;
+    };
+    auto load = [&]() {
+        launch_booked(pf, K_QR, 0.0, (double)m * r * (sizeof(C2<T>) + 16.0), k_to_f64<T>, dim3((m + 255) / 256, r),
+                      dim3(256), 0, st, A, m, lda, Ad, ldx);
+        Rt = nullptr;
+    };
+    load();
+    pass_run(kQrPlain);
+    pass_run(kQrFinal);
+    if (failed()) {
+        load();
+        pass_run(kQrShifted);
+        pass_run(kQrAfterShift);
+        pass_run(kQrFinal);
+        if (failed()) return false;
+    }
+    launch_booked(pf, K_QR, 0.0, (double)m * r * (16.0 + sizeof(C2<T>)), k_from_f64<T>, dim3((m + 255) / 256, r),
+                  dim3(256), 0, st, (const double2*)Ad, ldx, m, Q, ldq);
+    launch_booked(pf, K_QR, 0.0, (double)r * r * (16.0 + sizeof(C2<T>)), k_from_f64<T>, dim3((r + 255) / 256, r),
+                  dim3(256), 0, st, (const double2*)Rt, r, r, R, r);
+    if (hipGetLastError() != hipSuccess) throw HeevFailure{"Cholesky QR launch"};
+    return true;
+}
+
+template bool cholqr3<double>(const double2*, int, int, int, double2*, int, double2*, DevInfo*, DevInfo*,
+                              HeevWork&, Profiler&, hipStream_t);
+template bool cholqr3<float>(const float2*, int, int, int, float2*, int, float2*, DevInfo*, DevInfo*, HeevWork&,
+                             Profiler&, hipStream_t);
 
 }  // namespace mpo

@@ -26,7 +26,10 @@ enum KernelId {
     K_TRIDIAG,       // tridiagonalisation: trailing matrix-vector products (per launch)
     K_TRDAUX,        // tridiagonalisation: whole reduction including vector kernels and panel updates
     K_DC,            // divide and conquer on the tridiagonal
-    K_BACK,          // back-transformation X Q_H Z
+    K_BACK,          // back-transformation: reflector block products X Y, X -= P Y^H
+    K_BTAUX,         // back-transformation: Y, S = Y^H Y, T, P T, FP64 copy of X
+    K_HOUT,          // X Q_H times the tridiagonal's eigenvectors (real GEMM)
+    K_QR,            // Cholesky QR centre moves
     K_COUNT
 };
 
@@ -35,7 +38,7 @@ inline const char* kernel_name(int k) {
                                          "jacobi_update", "norm_sort",    "truncate",
                                          "gather",        "cgemm",        "transfer",
                                          "heev_gram",     "heev_trd_gemv", "heev_tridiag", "heev_dc",
-                                         "heev_back"};
+                                         "heev_back",     "heev_bt_aux",   "heev_out",      "qr_move"};
     return names[k];
 }
 

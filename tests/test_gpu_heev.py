@@ -10,6 +10,7 @@ at most 1e-12 ||G|| (max-abs entries).  Sizes cover single and several
 divide-and-conquer tree, exact degeneracy (clusters the deflation must
 rotate), rank deficiency (a zero cluster), a diagonal and the zero matrix.
 """
+import os
 import sys
 
 import numpy as np
@@ -151,3 +152,58 @@ def test_eigen_start_gate_against_oracle(pm):
     assert abs(info.discarded_weight - ref.discarded_weight) <= 1e-12 * ref.total_weight
     k = min(len(lam), len(lam_ref))
     assert np.abs(lam[:k] - lam_ref[:k]).max() <= 1e-11 * lam_ref[0]
+
+
+def graded_mps(n, dims, seed, decay):
+    """Random MPS whose bond indices carry weights decaying geometrically by
+    `decay` overall (a wide spread of Schmidt values, as truncated states have)."""
+    rng = np.random.default_rng(seed)
+    ts = []
+    for s in range(n):
+        cl = 1 if s == 0 else dims[s - 1]
+        cr = 1 if s == n - 1 else dims[s]
+        t = rng.standard_normal((cl, 4, cr)) + 1j * rng.standard_normal((cl, 4, cr))
+        if cr > 1:
+            t = t * np.logspace(0, np.log10(decay), cr)[None, None, :]
+        ts.append(t / np.linalg.norm(t))
+    return ts
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_qr_moves_preserve_state(pm, prec, tol):
+    """Centre moves across bonds of dimension 200 (>= the Cholesky QR threshold)
+    on a state whose bond weights span 12 orders of magnitude: Pauli
+    expectations, the trace and the Schmidt values at the bonds must match the
+    oracle's (QR moves of the same tensors), and the QR moves must agree with
+    the SVD moves.  FP64 to 1e-12 relative, FP32 to its storage rounding."""
+    n, dims = 8, [4, 16, 64, 200, 64, 16, 4]
+    ts = graded_mps(n, dims, seed=21, decay=1e-6)
+    ref = omp.MPO.from_tensors([t.copy() for t in ts], "pauli")
+    strings = ["ZIIIIIII", "IIIZZIII", "XYIIIZIX", "IIIIIIIZ"]
+    exp_ref = [complex(ref.contract_product([gates.dual_vector(gates.PAULI["IXYZ".index(ch)], "pauli")
+                                             for ch in sgl])) for sgl in strings]
+    tr_ref = ref.trace()
+    lam_ref = ref.schmidt_sweep()[3]
+    out = {}
+    for label, qr_min in (("qr", 128), ("svd", 0)):
+        os.environ["MPO_QR_MIN"] = str(qr_min)
+        try:
+            st = pm.Mpo(n, 256, prec, "pauli")
+        finally:
+            del os.environ["MPO_QR_MIN"]
+        st.import_state(pm.tensors_to_snapshot(ts))
+        for c in (7, 0, 5, 2, 4):
+            st.canonicalize(c)
+        tr = st.trace()
+        ex = [st.expect(sgl) * tr for sgl in strings]
+        lam = st.singular_values(3)
+        st.close()
+        out[label] = (tr, ex, lam)
+        say(f"{prec} {label}: trace {tr} ({abs(tr - tr_ref) / abs(tr_ref):.2e})")
+    for label in ("qr", "svd"):
+        tr, ex, lam = out[label]
+        scale = max(abs(e) for e in exp_ref)
+        assert abs(tr - tr_ref) <= tol * abs(tr_ref)
+        assert max(abs(a - b) for a, b in zip(ex, exp_ref)) <= tol * scale
+        k = min(len(lam), len(lam_ref))
+        assert np.abs(lam[:k] - lam_ref[:k]).max() <= tol * lam_ref[0]
