@@ -376,8 +376,9 @@ typedef struct {
 } mpo_kernel_stat;
 mpo_status mpo_profile_enable(mpo_handle *h, int on);
 /* Synchronises.  Writes up to cap entries; *count = number of kernel classes.
- * svd_counters (5 values or NULL): splits, Jacobi sweeps, Jacobi rounds,
- * rotated block pairs, splits started from the Gram eigenvectors.           */
+ * svd_counters (6 values or NULL): splits, Jacobi sweeps, Jacobi rounds,
+ * rotated block pairs, splits started from the Gram eigenvectors, and of
+ * those the splits their Gram certificate finished without a sweep.         */
 mpo_status mpo_profile_read(mpo_handle *h, mpo_kernel_stat *out, int cap, int *count,
                             long long *svd_counters);
 

@@ -344,10 +344,10 @@ class Mpo:
     def profile_read(self) -> dict:
         stats = (_KernelStat * 32)()
         cnt = ctypes.c_int()
-        svd = (ctypes.c_longlong * 5)()
+        svd = (ctypes.c_longlong * 6)()
         _check(library().mpo_profile_read(self._h, stats, 32, ctypes.byref(cnt), svd))
-        out = {"kernels": {}, "svd": dict(zip(("splits", "sweeps", "rounds", "rotated_pairs", "eigen_starts"),
-                                              list(svd)))}
+        out = {"kernels": {}, "svd": dict(zip(("splits", "sweeps", "rounds", "rotated_pairs", "eigen_starts",
+                                               "gram_certified"), list(svd)))}
         for k in range(cnt.value):
             st = stats[k]
             out["kernels"][st.name.decode()] = {"launches": st.launches, "ms": st.ms,

@@ -227,14 +227,17 @@ struct Engine {
     // Orthogonalise the columns of X (m x N); truncation with (chi_max, cutoff).
     static DevInfo split(mpo_handle* h, int m, int N, int chi_max, double cutoff) {
         const int sw = jacobi_orthogonalize<T>((C*)h->X, m, N, work_ld(m), jacobi_tol(h, m), kMaxSweeps,
-                                               h->jw, h->st);
+                                               h->jw, h->st, chi_max);
         if (sw == -2) HIPCHK(hipGetLastError());
         if (sw == -3) throw HipError{hipErrorInvalidValue, "jacobi pair capacity"};
         if (sw < 0) throw NoConvError{"one-sided Jacobi SVD did not converge"};
+        // the decomposition may have kept only the leading columns (their
+        // complement's weight is in the device info)
+        const int n_out = h->jw.n_cols;
         h->prof.begin(h->st);
-        launch_truncate(h->jw.sig2, N, chi_max, cutoff,
-                        h->bf3 ? kZeroRel2Bf3 : jacobi_zero_rel2<T>(), h->jw.info, h->st);
-        h->prof.end(h->st, K_TRUNC, 0.0, 8.0 * N);
+        launch_truncate(h->jw.sig2, n_out, chi_max, cutoff,
+                        h->bf3 ? kZeroRel2Bf3 : jacobi_zero_rel2<T>(), h->jw.info, h->st, h->jw.rest_on);
+        h->prof.end(h->st, K_TRUNC, 0.0, 8.0 * n_out);
         HIPCHK(hipGetLastError());
         DevInfo inf = read_info(h);
         if (inf.numeric_error) throw NumericError{"non-finite singular values"};
@@ -1400,6 +1403,7 @@ mpo_status mpo_create(int n, int chi_cap, mpo_precision prec, mpo_basis basis, v
     h->jw.heev = nullptr;
     h->jw.precond_min = 0;
     h->jw.n_precond = 0;
+    h->jw.n_checks = 0;
     if (L.heev_bytes) {
         heev_carve(p, 4 * chi_cap, 4 * chi_cap, h->hw);
         p += L.heev_bytes;
@@ -1710,7 +1714,7 @@ mpo_status mpo_profile_enable(mpo_handle* h, int on) {
     if (!h) return fail(MPO_ERR_ARG, "null handle");
     h->prof.reset();
     h->prof.on = on != 0;
-    h->jw.n_splits = h->jw.n_sweeps = h->jw.n_rounds = h->jw.n_rotations = h->jw.n_precond = 0;
+    h->jw.n_splits = h->jw.n_sweeps = h->jw.n_rounds = h->jw.n_rotations = h->jw.n_precond = h->jw.n_checks = 0;
     return MPO_OK;
 }
 
@@ -1733,6 +1737,7 @@ mpo_status mpo_profile_read(mpo_handle* h, mpo_kernel_stat* out, int cap, int* c
         svd_counters[2] = h->jw.n_rounds;
         svd_counters[3] = h->jw.n_rotations;
         svd_counters[4] = h->jw.n_precond;
+        svd_counters[5] = h->jw.n_checks;
     }
     return MPO_OK;
 }

@@ -126,6 +126,8 @@ struct DevInfo {
     long long rot_total;   // rotated pairs summed over its sweeps
     int qr_fail;           // a Cholesky QR pass met a pivot below its bound (rank deficiency)
     double qr_shift;       // shift of the first Cholesky QR pass
+    double gram_trace;     // trace of the Gram matrix of the eigen start's check
+    double rest_weight;    // weight of the columns a subset eigen start left out
 };
 
 }  // namespace mpo
@@ -153,7 +155,8 @@ struct HeevWork {
     double2* Xd;                      // FP64 copy of X, column stride ((cap_m + 1) & ~1) + 8
     double2* G;                       // Gram (stride N + 8), then the reflectors below its diagonal
     double2 *VW, *WV;                 // panel [V W] and [W V], N x 2 kTrdNb each (stride N)
-    double2 *yraw, *wt, *dots, *tau;
+    double2* ypart;                   // slots of the trailing product, (N / 64 + 2) x N (stride N)
+    double2 *wt, *tau;
     double* part;                     // partial sums of ||column||^2 (row chunks)
     double2 *pdot, *palpha;           // partial sums of the panel dots and of w~^H v
     double *d, *e;                    // tridiagonal
@@ -173,9 +176,13 @@ size_t heev_bytes(int m_max, int n_max);
 void heev_carve(char* p, int m_max, int n_max, HeevWork& w);
 void* heev_plans_new();
 void heev_plans_free(void* plans);
-// X (m x N, stride ld) <- X V with V the eigenvectors of X^H X, computed in FP64.
+// X (m x N, stride ld) <- X V with V the eigenvectors of X^H X, computed in FP64;
+// with keep < N (and rest non-null) only the keep of the largest eigenvalues,
+// X (m x keep), and *rest (device) <- the sum of the other eigenvalues.  Returns
+// the number of columns written.
 template <typename T>
-void heev_precondition(C2<T>* X, int m, int N, int ld, HeevWork& w, Profiler& pf, hipStream_t st);
+int heev_precondition(C2<T>* X, int m, int N, int ld, int keep, double* rest, HeevWork& w, Profiler& pf,
+                      hipStream_t st);
 // A (m x r, stride lda) = Q R: Q (stride ldq, may alias A) an isometry, R (r x r, stride r)
 // upper triangular; shifted Cholesky QR plus two Cholesky QR passes in FP64.
 // Returns false, writing neither Q nor R, when A is numerically rank-deficient
@@ -183,6 +190,11 @@ void heev_precondition(C2<T>* X, int m, int N, int ld, HeevWork& w, Profiler& pf
 template <typename T>
 bool cholqr3(const C2<T>* A, int m, int r, int lda, C2<T>* Q, int ldq, C2<T>* R, DevInfo* info,
              DevInfo* info_host, HeevWork& w, Profiler& pf, hipStream_t st);
+// Certificate of the eigen start: true when the largest relative off-diagonal of
+// X^H X (FP64, over columns above the floor zrel2) is at most tol.  Synchronises.
+template <typename T>
+bool heev_check(C2<T>* X, int m, int N, int ld, double tol, double zrel2, DevInfo* info, DevInfo* info_host,
+                HeevWork& w, Profiler& pf, hipStream_t st);
 // Eigenvalues (ascending) and eigenvectors of a host Hermitian matrix (row-major,
 // interleaved complex), through the same kernels.
 void heev_host(int N, const double* G, double* w, double* V, HeevWork& work, Profiler& pf, hipStream_t st);
@@ -209,15 +221,21 @@ struct JacobiWork {
     HeevWork* heev;        // Gram eigen-decomposition start (null = plain sweeps)
     int precond_min;       // start from it for splits with at least this many columns
     long long n_precond;   // splits that started from it
+    long long n_checks;    // of those, splits the Gram certificate finished (no sweep)
+    int n_cols;            // columns the last decomposition orthogonalised (<= N)
+    bool rest_on;          // it left columns out: their weight is info->rest_weight
 };
 
 // One-sided block Jacobi on the columns of X (m x N, column stride ld >= m).  On return
-// work.colmap[0..N) lists columns by decreasing norm and work.sig2 holds the
-// sorted squared norms.  Returns the number of sweeps, or -1 if the sweep
-// limit was reached, -2 on a HIP error.
+// work.colmap[0..n) lists columns by decreasing norm and work.sig2 holds the
+// sorted squared norms, n = work.n_cols.  n < N only with keep_max > 0 (the
+// caller keeps at most keep_max columns) in FP32 storage with the eigen start:
+// then X holds the n columns of the largest eigenvalues of X^H X and the
+// weight of the others is info->rest_weight (work.rest_on).  Returns the
+// number of sweeps, or -1 if the sweep limit was reached, -2 on a HIP error.
 template <typename T>
 int jacobi_orthogonalize(C2<T>* X, int m, int N, int ld, double tol, int max_sweeps,
-                         JacobiWork& w, hipStream_t st);
+                         JacobiWork& w, hipStream_t st, int keep_max = 0);
 // Cache of captured sweeps (JacobiWork::graph_cache), created and freed by the handle.
 void* jacobi_graph_cache_new();
 void jacobi_graph_cache_free(void* cache);
@@ -239,9 +257,10 @@ constexpr double kZeroRel2Bf3 = jacobi_zero_rel2<float>();   // split-BF16x3 use
 constexpr double kTolFp32 = 2e-6;
 constexpr double kBf3Handoff = 3e-3;
 
-// Truncation + entropy from the sorted squared norms (single work-group).
+// Truncation + entropy from the sorted squared norms (single work-group); with
+// with_rest, info->rest_weight is the weight of further (discarded) values.
 void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,
-                     DevInfo* info, hipStream_t st);
+                     DevInfo* info, hipStream_t st, bool with_rest = false);
 
 // dst[i + ldd*b] = X[i + ldx*colmap[b]] / sqrt(sig2[b]) for b < k, i < m  (left factor;
 // without normalize the columns are copied as they are: U Sigma)

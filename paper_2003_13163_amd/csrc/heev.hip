@@ -22,6 +22,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <functional>
 #include <map>
 #include <vector>
 
@@ -33,14 +35,18 @@ namespace {
 
 constexpr int kPart = 64;          // row chunks of the tridiagonalisation's vector kernels
 static_assert(kPart == 64, "the kernels sum the kPart partials one per lane of a wave");
-constexpr int kGemvWaves = 8;      // waves per work-group of the trailing matrix-vector product
 constexpr int kBtNb = 64;          // reflectors per block of the back-transformation
-constexpr int kSplitK = 256;       // K chunk of the split-K products
+constexpr int kSplitK = 512;       // K chunk of the split-K products
 
 // ------------------------------------------------------------ wave reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
 __device__ __forceinline__ double wave_prod(double v) {
@@ -92,7 +98,9 @@ void launch_booked(Profiler& pf, int cls, double fl, double by, K kernel, dim3 g
 }
 
 // ------------------------------------------------------------ complex GEMM
-// C = op(A) op(B) (MODE 0) or C -= op(A) op(B) (MODE 1), FP64 complex, 64x64
+// C = op(A) op(B) (MODE 0) or C -= op(A) op(B) (MODE 1); MODE 2 and 3 are the
+// same on the 64x64 tiles on or below the diagonal only (Hermitian results of
+// which only the lower triangle is used), FP64 complex, 64x64
 // tiles, 4 waves of 2x2 16x16 MFMA tiles.  blockIdx.z selects a batch entry:
 // the operands are offset by z times their strides and, with kchunk > 0, the
 // entry covers K range [z*kchunk, min(K, (z+1)*kchunk)) (split-K partials).
@@ -112,6 +120,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, int kchunk, 
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int m0 = blockIdx.x * ZBM, n0 = blockIdx.y * ZBN;
+    if ((MODE & 2) && m0 < n0) return;   // Hermitian result: lower tiles only
     d4 accR[2][2], accI[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -177,7 +186,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, int kchunk, 
                 const int j = n0 + wn * 32 + bj * 16 + (lane & 15);
                 if (i < M && j < N) {
                     double2* c = C + i + (size_t)j * ldc;
-                    if (MODE == 0) *c = make_double2(accR[bi][bj][r], accI[bi][bj][r]);
+                    if (!(MODE & 1)) *c = make_double2(accR[bi][bj][r], accI[bi][bj][r]);
                     else *c = make_double2(c->x - accR[bi][bj][r], c->y - accI[bi][bj][r]);
                 }
             }
@@ -195,7 +204,9 @@ void zgemm(int M, int N, int K, const double2* A, int lda, const double2* B, int
         hipExtLaunchKernelGGL((k_zgemm<OPA, OPB, MODE>), grid, dim3(256), 0, st, a, e, 0, M, N, K, kchunk, A, lda,
                               sA, B, ldb, sB, C, ldc, sC);
         const double kk = kchunk > 0 ? (double)K : (double)K * batches;
-        pf->record(cls, a, e, 8.0 * M * N * kk, 16.0 * ((double)M * kk + (double)N * kk + (MODE + 1.0) * M * N * batches));
+        const double part = (MODE & 2) ? 0.5 : 1.0;   // lower tiles only
+        pf->record(cls, a, e, part * 8.0 * M * N * kk,
+                   16.0 * ((double)M * kk + (double)N * kk + part * ((MODE & 1) + 1.0) * M * N * batches));
     } else {
         hipLaunchKernelGGL((k_zgemm<OPA, OPB, MODE>), grid, dim3(256), 0, st, M, N, K, kchunk, A, lda, sA, B, ldb,
                            sB, C, ldc, sC);
@@ -341,32 +352,58 @@ __global__ __launch_bounds__(256) void k_trd_colnorm(const double2* __restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// Column j of the panel (c = j - j0), one wave per trailing column i:
+// Column j of the panel (c = j - j0): y = G_eff v over the trailing matrix
+// G[j+1:, j+1:] of which only the lower triangle is read, in 64x64 tiles, one
+// work-group per tile (I, J), I >= J (tile coordinates from the trailing
+// origin j+1):
 //   reflector      from the updated column (scalars recomputed identically in
 //                  every work-group from the partial sums of ||G[j+2:, j]||^2)
-//   p = W^H v, q = V^H v   from the partial sums of W^H G[j+2:, j] and
-//                  V^H G[j+2:, j] the previous kernel left (v = [1, scale x])
-//   y_i = conj(G[j+1:, i]) . v - (V p + W q)_i    (panel-start trailing matrix,
-//                  Hermitian symmetry: a column read is a row of G)
-//   w~_i = tau_j y_i, and per work-group the partial sum of w~^H v.
+//   tile I > J     row partials G_IJ v_J (rows of block I) and column partials
+//                  G_IJ^H v_I (rows of block J), each into its own slot of
+//                  ypart: block K's rows collect slot J from tile (K, J), slot
+//                  I from tile (I, K), and slots K and nt from the diagonal
+//                  tile (its strict lower part both ways, the real diagonal
+//                  once), nt + 1 slots in all, summed by k_trd_fin.
 // Work-group 0 stores the reflector in the panel buffers together with tau_j,
-// e_j and d_j (column j of G is still being read here).
-__global__ __launch_bounds__(64 * kGemvWaves) void k_trd_gemv(double2* __restrict__ G, int ldg, int N, int j, int c,
-                                                   const double* __restrict__ part,
-                                                   const double2* __restrict__ pdot,
-                                                   double2* __restrict__ VW, double2* __restrict__ WV,
-                                                   double2* __restrict__ wt, double2* __restrict__ palpha,
-                                                   double2* __restrict__ tau, double* __restrict__ d,
-                                                   double* __restrict__ e) {
-    extern __shared__ double2 vs[];      // v[j+1 .. N)
-    __shared__ double2 pq[2 * kTrdNb];   // p, then q
-    __shared__ double2 red[kGemvWaves];
+// e_j and d_j (column j of G is still being read).
+constexpr int kHt = 64;   // tile edge of the trailing product
+
+__device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
+    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+}
+
+__global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G, int ldg, int N, int j, int c,
+                                                  const double* __restrict__ part, double2* __restrict__ VW,
+                                                  double2* __restrict__ WV, double2* __restrict__ ypart,
+                                                  double2* __restrict__ tau, double* __restrict__ d,
+                                                  double* __restrict__ e) {
+    __shared__ double2 vI[kHt], vJ[kHt];
+    __shared__ double2 red[4][kHt];
     __shared__ double sxn2;
     const int len = N - j - 1;
-    const int tid = threadIdx.x;
-    const int wave = blockIdx.x * kGemvWaves + (tid >> 6), lane = tid & 63;
-    // ||x[1:]||^2 from its kPart (= 64) partial sums: one per lane, a fixed-order
-    // butterfly, so every work-group forms the same scalars
+    const int nt = (len + kHt - 1) / kHt;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int I, J;
+    lower_tile((int)blockIdx.x, I, J);
+    // the tile first (it depends on nothing else): lane (p, q) = (lane % 8,
+    // lane / 8) takes rows 8 s + p and columns 16 wave + 8 cc + q, so each load
+    // instruction reads eight 128-byte row runs
+    const int p = lane & 7, q = lane >> 3;
+    const int rows = min(kHt, len - kHt * I), cols = min(kHt, len - kHt * J);
+    const double2* T0 = G + (size_t)(j + 1 + kHt * I) + (size_t)ldg * (j + 1 + kHt * J);
+    double2 a[8][2];
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const int r = 8 * s8 + p, b = 16 * wave + 8 * cc + q;
+            const bool ok = r < rows && b < cols && (I != J || r >= b);
+            a[s8][cc] = ok ? T0[r + (size_t)ldg * b] : make_double2(0.0, 0.0);
+        }
     if (tid < 64) {
         const double xn = wave_sum(part[tid]);
         if (tid == 0) sxn2 = xn;
@@ -374,174 +411,294 @@ __global__ __launch_bounds__(64 * kGemvWaves) void k_trd_gemv(double2* __restric
     __syncthreads();
     const double2 alpha = G[(j + 1) + (size_t)ldg * j];
     const House h = house_scalars(alpha, sxn2);
-    for (int r = tid; r < len; r += 64 * kGemvWaves)
-        vs[r] = r == 0 ? make_double2(1.0, 0.0) : zmul(G[(j + 1 + r) + (size_t)ldg * j], h.scale);
-    // p_q = conj(W[j+1, q]) + scale * sum_w (W^H x)_q, likewise q_q with V: dot d
-    // (isv = d / c, q = d % c) summed over the kPart partials by wave d % 16
-    for (int dd = tid >> 6; dd < 2 * c; dd += kGemvWaves) {
-        const int q = dd % c, isv = dd / c;
-        const double2 t = pdot[(size_t)lane * 2 * kTrdNb + isv * kTrdNb + q];
-        const double sr = wave_sum(t.x), si = wave_sum(t.y);
-        if (lane == 0) {
-            const double2 row = VW[(j + 1) + (size_t)N * ((isv ? 0 : kTrdNb) + q)];
-            const double2 sc = zmul(h.scale, make_double2(sr, si));
-            pq[isv * kTrdNb + q] = make_double2(row.x + sc.x, -row.y + sc.y);
-        }
-    }
-    __syncthreads();
+    const double2* colj = G + (size_t)ldg * j + (j + 1);
+    auto vval = [&](int r) -> double2 {
+        if (r >= len) return make_double2(0.0, 0.0);
+        return r == 0 ? make_double2(1.0, 0.0) : zmul(colj[r], h.scale);
+    };
+    if (tid < 64) vI[tid] = vval(kHt * I + tid);
+    else if (tid < 128) vJ[tid - 64] = vval(kHt * J + tid - 64);
     if (blockIdx.x == 0) {
         if (tid == 0) {
             tau[j] = h.tau;
             e[j] = h.beta;
             d[j] = G[j + (size_t)ldg * j].x;
         }
-        for (int r = tid; r < N; r += 64 * kGemvWaves) {
-            const double2 v = r <= j ? make_double2(0.0, 0.0) : vs[r - j - 1];
+        for (int r = tid; r < N; r += 256) {
+            const double2 v = r <= j ? make_double2(0.0, 0.0) : vval(r - j - 1);
             VW[r + (size_t)N * c] = v;
             WV[r + (size_t)N * (kTrdNb + c)] = v;
         }
     }
-    double2 contrib = make_double2(0.0, 0.0);
-    if (wave < len) {
-        const int i = j + 1 + wave;
-        const double2* src = G + (size_t)ldg * i + (j + 1);
-        double sr = 0.0, si = 0.0;
-        int r = lane;
-        for (; r + 448 < len; r += 512) {   // eight 1 KiB loads per wave in flight
-            double2 a[8], b[8];
+    __syncthreads();
+    double2 racc[8], cacc[2];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a[u] = src[r + 64 * u];
+    for (int cc = 0; cc < 2; ++cc) cacc[cc] = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) b[u] = vs[r + 64 * u];
+    for (int s8 = 0; s8 < 8; ++s8) {
+        racc[s8] = make_double2(0.0, 0.0);
+        const int r = 8 * s8 + p;
+        const double2 vi = vI[r];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                sr += a[u].x * b[u].x + a[u].y * b[u].y;
-                si += a[u].x * b[u].y - a[u].y * b[u].x;
+        for (int cc = 0; cc < 2; ++cc) {
+            const int b = 16 * wave + 8 * cc + q;
+            double2 g = a[s8][cc];
+            const bool diag = I == J && r == b;
+            if (diag) g.y = 0.0;                   // Hermitian: real diagonal, counted once
+            const double2 vb = vJ[b];
+            racc[s8].x += g.x * vb.x - g.y * vb.y;
+            racc[s8].y += g.x * vb.y + g.y * vb.x;
+            if (!diag) {                            // conj(g) v_r into y_b
+                cacc[cc].x += g.x * vi.x + g.y * vi.y;
+                cacc[cc].y += g.x * vi.y - g.y * vi.x;
             }
         }
-        for (; r < len; r += 64) {
-            const double2 a = src[r], b = vs[r];
-            sr += a.x * b.x + a.y * b.y;
-            si += a.x * b.y - a.y * b.x;
-        }
-        // (V p + W q)_i, one panel column per lane
-        if (lane < c) {
-            const double2 t1 = zmul(VW[i + (size_t)N * lane], pq[lane]);
-            const double2 t2 = zmul(VW[i + (size_t)N * (kTrdNb + lane)], pq[kTrdNb + lane]);
-            sr -= t1.x + t2.x;
-            si -= t1.y + t2.y;
-        }
-        sr = wave_sum(sr);
-        si = wave_sum(si);
-        const double2 w = zmul(h.tau, make_double2(sr, si));
-        const double2 vi = vs[wave];
-        if (lane == 0) wt[i] = w;
-        contrib = zcmul(w, vi);
     }
-    if (lane == 0) red[tid >> 6] = contrib;
+    // rows: sum over q (lane bits 3..5); columns: sum over p (lane bits 0..2)
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8)
+#pragma unroll
+        for (int o = 8; o < 64; o <<= 1) {
+            racc[s8].x += __shfl_xor(racc[s8].x, o, 64);
+            racc[s8].y += __shfl_xor(racc[s8].y, o, 64);
+        }
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+            cacc[cc].x += __shfl_xor(cacc[cc].x, o, 64);
+            cacc[cc].y += __shfl_xor(cacc[cc].y, o, 64);
+        }
+    const size_t ldy = (size_t)N;
+    if (q == 0) {
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) red[wave][8 * s8 + p] = racc[s8];
+    }
+    if (p == 0) {
+        const int slot = I == J ? nt : I;
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const int b = 16 * wave + 8 * cc + q;
+            if (b < cols) ypart[(size_t)slot * ldy + kHt * J + b] = cacc[cc];
+        }
+    }
     __syncthreads();
-    if (tid == 0) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int q = 0; q < kGemvWaves; ++q) { s.x += red[q].x; s.y += red[q].y; }
-        palpha[blockIdx.x] = s;
+    if (tid < rows) {
+        double2 sr = red[0][tid];
+#pragma unroll
+        for (int w4 = 1; w4 < 4; ++w4) { sr.x += red[w4][tid].x; sr.y += red[w4][tid].y; }
+        ypart[(size_t)J * ldy + kHt * I + tid] = sr;
     }
 }
 
-// w = w~ + alpha v with alpha = -tau_j (w~^H v) / 2 into the panel buffers
-// (zero above row j+1), the reflector below the diagonal of G (G[j+1, j] = 1
-// for the back-transformation); if the panel continues, column j+1 is brought up to
-// date, G[j+1:, j+1] -= V conj(W[j+1, :]) + W conj(V[j+1, :]), and the
-// partial sums its reflector needs are formed: ||G[j+3:, j+1]||^2, and
-// W^H G[j+3:, j+1], V^H G[j+3:, j+1] over the panel's first c+1 columns.
+// Finish of the trailing product, one work-group per 64-row block K: y = the
+// block's nt + 1 slots summed in fixed order, minus the panel's correction
+// (V p + W q) with p = W^H v and q = V^H v from the partial sums the previous
+// column's kernel left; w~_i = tau_j y_i, and the block's partial sum of w~^H v.
+__global__ __launch_bounds__(256) void k_trd_fin(const double2* __restrict__ G, int ldg, int N, int j, int c,
+                                                 const double* __restrict__ part,
+                                                 const double2* __restrict__ pdot,
+                                                 const double2* __restrict__ VW,
+                                                 const double2* __restrict__ ypart, double2* __restrict__ wt,
+                                                 double2* __restrict__ palpha) {
+    __shared__ double2 red[4][kHt];
+    __shared__ double2 pq[2 * kTrdNb];
+    __shared__ double sxn2;
+    const int len = N - j - 1;
+    const int nt = (len + kHt - 1) / kHt;
+    const int K = blockIdx.x;
+    const int nr = min(kHt, len - kHt * K);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const size_t ldy = (size_t)N;
+    {
+        const int r = tid & 63, g = tid >> 6;
+        double2 acc = make_double2(0.0, 0.0);
+        if (r < nr)
+            for (int sl = g; sl <= nt; sl += 4) {
+                const double2 v = ypart[(size_t)sl * ldy + kHt * K + r];
+                acc.x += v.x;
+                acc.y += v.y;
+            }
+        red[g][r] = acc;
+    }
+    if (tid < 64) {
+        const double xn = wave_sum(part[tid]);
+        if (tid == 0) sxn2 = xn;
+    }
+    __syncthreads();
+    const double2 alpha = G[(j + 1) + (size_t)ldg * j];
+    const House h = house_scalars(alpha, sxn2);
+    // p = W^H v, q = V^H v over the panel's first c columns
+    for (int dd = wave; dd < 2 * c; dd += 4) {
+        const int qq = dd % c, isv = dd / c;
+        const double2 t = pdot[(size_t)lane * 2 * kTrdNb + isv * kTrdNb + qq];
+        const double sr = wave_sum(t.x), si = wave_sum(t.y);
+        if (lane == 0) {
+            const double2 row = VW[(j + 1) + (size_t)N * ((isv ? 0 : kTrdNb) + qq)];
+            const double2 sc = zmul(h.scale, make_double2(sr, si));
+            pq[isv * kTrdNb + qq] = make_double2(row.x + sc.x, -row.y + sc.y);
+        }
+    }
+    __syncthreads();
+    if (tid < 64) {
+        double2 contrib = make_double2(0.0, 0.0);
+        if (tid < nr) {
+            double sr = red[0][tid].x, si = red[0][tid].y;
+#pragma unroll
+            for (int w4 = 1; w4 < 4; ++w4) { sr += red[w4][tid].x; si += red[w4][tid].y; }
+            const int r = kHt * K + tid;
+            const int i = j + 1 + r;
+            for (int qq = 0; qq < c; ++qq) {   // (V p + W q)_i
+                const double2 t1 = zmul(VW[i + (size_t)N * qq], pq[qq]);
+                const double2 t2 = zmul(VW[i + (size_t)N * (kTrdNb + qq)], pq[kTrdNb + qq]);
+                sr -= t1.x + t2.x;
+                si -= t1.y + t2.y;
+            }
+            const double2 w = zmul(h.tau, make_double2(sr, si));
+            wt[i] = w;
+            const double2 vi = r == 0 ? make_double2(1.0, 0.0) : zmul(G[i + (size_t)ldg * j], h.scale);
+            contrib = zcmul(w, vi);
+        }
+        contrib.x = wave_sum(contrib.x);
+        contrib.y = wave_sum(contrib.y);
+        if (tid == 0) palpha[K] = contrib;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_trd_next(double2* __restrict__ G, int ldg, int N, int j, int c,
                                                   int update_next, int gemv_groups,
                                                   const double2* __restrict__ tau, double2* __restrict__ VW,
                                                   double2* __restrict__ WV, const double2* __restrict__ wt,
                                                   const double2* __restrict__ palpha, double* __restrict__ part,
                                                   double2* __restrict__ pdot) {
-    __shared__ double red[4];
     __shared__ double2 sw[64];            // new W column on this chunk's rows
     __shared__ double2 arow[64];          // updated column j+1 on this chunk's rows (>= j+3; else 0)
     __shared__ double2 red4[4][64];
-    const int t = threadIdx.x;
-    // w~^H v from the gemv's partials (at most 512): two per thread, fixed-order block sums
-    double2 pa = t < gemv_groups ? palpha[t] : make_double2(0.0, 0.0);
-    if (t + 256 < gemv_groups) { pa.x += palpha[t + 256].x; pa.y += palpha[t + 256].y; }
-    const double2 s = make_double2(block_sum<256>(pa.x, red), block_sum<256>(pa.y, red));
-    const double2 ts = zmul(tau[j], s);
-    const double2 al = make_double2(-0.5 * ts.x, -0.5 * ts.y);
+    __shared__ double2 row1[2 * kTrdNb];  // V[j+1, q], W[j+1, q] for q < c
+    const double2 zero = make_double2(0.0, 0.0);
+    const int t = threadIdx.x, lane = t & 63;
     int a, b;
     part_rows(0, N, a, b);
     const int nr = b - a;                 // <= 64
-    if (t < nr) {
-        const int i = a + t;
-        double2 w = make_double2(0.0, 0.0);
-        if (i > j) {
-            const double2 vi = VW[i + (size_t)N * c];
-            const double2 av = zmul(al, vi);
-            w = wt[i];
-            w.x += av.x;
-            w.y += av.y;
-            G[i + (size_t)ldg * j] = vi;
+    const int r = t & 63, g = t >> 6;     // (row, group) of the update and the dots
+    const int i = a + r;
+    // Loads that depend on nothing computed here go first.
+    double2 v_own = zero, wt_own = zero;
+    if (t < nr && a + t > j) {
+        v_own = VW[(a + t) + (size_t)N * c];
+        wt_own = wt[a + t];
+    }
+    const bool urow = update_next && r < nr && i >= j + 1;
+    double2 gcol = zero, vic = zero, wj1 = zero;
+    double2 uv[8], uw[8];                 // panel columns q = g + 4 k < c of the update
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { uv[k] = zero; uw[k] = zero; }
+    if (update_next) {
+        wj1 = wt[j + 1];
+        if (t < 2 * kTrdNb && (t % kTrdNb) < c) row1[t] = VW[(j + 1) + (size_t)N * t];
+        if (urow) {
+            if (g == 0) gcol = G[i + (size_t)ldg * (j + 1)];
+            vic = VW[i + (size_t)N * c];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int q = g + 4 * k;
+                if (q < c) {
+                    uv[k] = VW[i + (size_t)N * q];
+                    uw[k] = VW[i + (size_t)N * (kTrdNb + q)];
+                }
+            }
         }
-        VW[i + (size_t)N * (kTrdNb + c)] = w;
-        WV[i + (size_t)N * c] = w;
+    }
+    // w~^H v from the trailing product's partials (at most 64): every wave sums
+    // them with the same butterfly
+    double2 pa = zero;
+    if (lane < gemv_groups) pa = palpha[lane];
+    pa.x = wave_sum(pa.x);
+    pa.y = wave_sum(pa.y);
+    const double2 ts = zmul(tau[j], pa);
+    const double2 al = make_double2(-0.5 * ts.x, -0.5 * ts.y);
+    if (t < nr) {
+        double2 w = zero;
+        if (a + t > j) {
+            const double2 av = zmul(al, v_own);
+            w = make_double2(wt_own.x + av.x, wt_own.y + av.y);
+            G[(a + t) + (size_t)ldg * j] = v_own;
+        }
+        VW[(a + t) + (size_t)N * (kTrdNb + c)] = w;
+        WV[(a + t) + (size_t)N * c] = w;
         sw[t] = w;
     }
     if (!update_next) return;
     __syncthreads();
-    // column j+1 update: thread (row r, group g) sums the panel columns q = g, g+4, ..
+    // dot operands: V columns 0..c and W columns 0..c (column c written above)
+    const int nq = c + 1;
+    double2 dcol[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int rr = g + 4 * k;
+        dcol[k] = zero;
+        if (r < 2 * nq && rr < nr) {
+            const int q = r % nq, isv = r / nq;
+            dcol[k] = VW[(a + rr) + (size_t)N * ((isv ? 0 : kTrdNb) + q)];
+        }
+    }
+    // column j+1 update: thread (row r, group g) sums the panel columns q = g, g+4, ..;
     // W[j+1, c] = w~[j+1] + alpha (v[j+1] = 1)
-    const int r = t & 63, g = t >> 6;
-    double2 wj1 = wt[j + 1];
     wj1.x += al.x;
     wj1.y += al.y;
-    double2 acc = make_double2(0.0, 0.0);
-    const int i = a + r;
-    if (r < nr && i >= j + 1) {
-        for (int q = g; q <= c; q += 4) {
-            const double2 vi = VW[i + (size_t)N * q];
-            const double2 wi = q == c ? sw[r] : VW[i + (size_t)N * (kTrdNb + q)];
-            const double2 vr = VW[(j + 1) + (size_t)N * q];
-            const double2 wr = q == c ? wj1 : VW[(j + 1) + (size_t)N * (kTrdNb + q)];
-            const double2 t1 = zmulc(vi, wr), t2 = zmulc(wi, vr);
-            acc.x += t1.x + t2.x;
-            acc.y += t1.y + t2.y;
+    double2 acc = zero;
+    if (urow) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int q = g + 4 * k;
+            if (q < c) {
+                const double2 t1 = zmulc(uv[k], row1[kTrdNb + q]), t2 = zmulc(uw[k], row1[q]);
+                acc.x += t1.x + t2.x;
+                acc.y += t1.y + t2.y;
+            } else if (q == c) {
+                const double2 t1 = zmulc(vic, wj1), t2 = zmulc(sw[r], make_double2(1.0, 0.0));
+                acc.x += t1.x + t2.x;
+                acc.y += t1.y + t2.y;
+            }
         }
     }
     red4[g][r] = acc;
     __syncthreads();
-    double nrm = 0.0;
     if (t < 64) {
-        double2 gv = make_double2(0.0, 0.0);
-        if (t < nr && i >= j + 1) {
-            gv = G[i + (size_t)ldg * (j + 1)];
-            for (int q = 0; q < 4; ++q) { gv.x -= red4[q][t].x; gv.y -= red4[q][t].y; }
+        double nrm = 0.0;
+        double2 gv = zero;
+        if (urow) {
+            gv = gcol;
+            for (int q4 = 0; q4 < 4; ++q4) { gv.x -= red4[q4][t].x; gv.y -= red4[q4][t].y; }
             G[i + (size_t)ldg * (j + 1)] = gv;
             if (i >= j + 3) nrm = gv.x * gv.x + gv.y * gv.y;
         }
-        arow[t] = (t < nr && i >= j + 3) ? gv : make_double2(0.0, 0.0);
+        double2 av = zero;
+        if (urow && i >= j + 3) av = gv;
+        arow[t] = av;
+        nrm = wave_sum(nrm);
+        if (t == 0) part[blockIdx.x] = nrm;
     }
-    nrm = block_sum<256>(nrm, red);     // also orders arow before the dots
-    if (t == 0) part[blockIdx.x] = nrm;
-    // dots over this chunk: thread (dot dq, row group g) sums conj(W[i, q]) a_i
-    // (dq < c+1) or conj(V[i, q]) a_i (dq >= c+1) over rows a + g, a + g + 4, ..
-    const int nq = c + 1;
-    double2 dacc = make_double2(0.0, 0.0);
+    __syncthreads();
+    // dots over this chunk: thread (dot r, row group g) sums conj(W[i, q]) a_i
+    // (r < c+1) or conj(V[i, q]) a_i (r >= c+1) over rows a + g, a + g + 4, ..
+    double2 dacc = zero;
     if (r < 2 * nq) {
-        const int q = r % nq, isv = r / nq;
-        const double2* col = VW + (size_t)N * ((isv ? 0 : kTrdNb) + q);
-        for (int rr = g; rr < nr; rr += 4) {
-            const double2 p = zcmul(col[a + rr], arow[rr]);
-            dacc.x += p.x;
-            dacc.y += p.y;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int rr = g + 4 * k;
+            if (rr < nr) {
+                const double2 p = zcmul(dcol[k], arow[rr]);
+                dacc.x += p.x;
+                dacc.y += p.y;
+            }
         }
     }
     red4[g][r] = dacc;
     __syncthreads();
     if (t < 2 * nq) {
         const int q = t % nq, isv = t / nq;
-        double2 sum = make_double2(0.0, 0.0);
+        double2 sum = zero;
         for (int q4 = 0; q4 < 4; ++q4) { sum.x += red4[q4][t].x; sum.y += red4[q4][t].y; }
         pdot[(size_t)blockIdx.x * 2 * kTrdNb + isv * kTrdNb + q] = sum;
     }
@@ -906,12 +1063,17 @@ __global__ __launch_bounds__(1024) void k_bt_sred(const double2* __restrict__ Sp
 }
 
 // P = (X Y) T for H_j0 .. H_j0+nb-1 = I - Y T Y^H without forming T: T^{-1} is
-// the strict upper triangle of Y^H Y with 1/tau_i on its diagonal (a
+// the strict upper triangle of S = Y^H Y with 1/tau_i on its diagonal (a
 // reflector with tau = 0 has its column of Y replaced by zero), so every row
 // of P solves p T^{-1} = (X Y)_row by forward substitution,
 //   p_i = tau_i ((X Y)_i - sum_{q<i} p_q S[q][i]).
+// ADJ: P = (X Y) T^H for the block's adjoint I - Y T^H Y^H; (T^H)^{-1} is the
+// strict lower triangle of S (S is Hermitian) with 1/conj(tau_i) on its
+// diagonal, so by backward substitution
+//   p_i = conj(tau_i) ((X Y)_i - sum_{q>i} p_q S[q][i]).
 // One wave per row of X, lane q holding p_q; the split-K partials of X Y are
 // summed on the way.
+template <bool ADJ>
 __global__ __launch_bounds__(256) void k_bt_solve(const double2* __restrict__ Ppart, int splits, int m,
                                                   const double2* __restrict__ S, const double2* __restrict__ tau,
                                                   int j0, int nbb, double2* __restrict__ P) {
@@ -927,17 +1089,60 @@ __global__ __launch_bounds__(256) void k_bt_solve(const double2* __restrict__ Pp
         b.y += v.y;
     }
     double2 p = make_double2(0.0, 0.0);
-    for (int c = 0; c < nbb; ++c) {
-        // sum_{q<c} p_q S[q][c] over the lanes q < c
-        double2 t = lane < c ? zmul(p, Ss[lane][c]) : make_double2(0.0, 0.0);
+    for (int k = 0; k < nbb; ++k) {
+        const int c = ADJ ? nbb - 1 - k : k;
+        // sum over the lanes already solved (q < c, or q > c for the adjoint) of p_q S[q][c]
+        const bool done = ADJ ? (lane > c && lane < nbb) : lane < c;
+        double2 t = done ? zmul(p, Ss[lane][c]) : make_double2(0.0, 0.0);
         t.x = wave_sum(t.x);
         t.y = wave_sum(t.y);
         if (lane == c) {
-            const double2 tc = tau[j0 + c];
+            double2 tc = tau[j0 + c];
+            if (ADJ) tc.y = -tc.y;
             p = zmul(tc, make_double2(b.x - t.x, b.y - t.y));
         }
     }
     P[i + (size_t)m * lane] = lane < nbb ? p : make_double2(0.0, 0.0);
+}
+
+// ------------------------------------------------ Gram check of the start
+// d[i] = G[i][i] (real), info->gram_trace = sum of them; clears the measure.
+__global__ __launch_bounds__(256) void k_gram_diag(const double2* __restrict__ G, int ld, int N,
+                                                   double* __restrict__ d, DevInfo* __restrict__ info) {
+    __shared__ double red[4];
+    double t = 0.0;
+    for (int i = threadIdx.x; i < N; i += 256) {
+        const double v = G[i + (size_t)ld * i].x;
+        d[i] = v;
+        t += v;
+    }
+    t = block_sum<256>(t, red);
+    if (threadIdx.x == 0) {
+        info->gram_trace = t;
+        info->offmax_bits = 0ull;
+    }
+}
+
+// Largest |g_ij| / sqrt(g_ii g_jj) over the pairs of columns above the rounding
+// floor (g_ii > zrel2 * trace G; lower triangle), as the Jacobi sweeps measure it, folded into
+// info->offmax_bits (non-negative doubles order like their bit patterns).
+__global__ __launch_bounds__(256) void k_gram_offmax(const double2* __restrict__ G, int ld, int N, double zrel2,
+                                                     const double* __restrict__ d, DevInfo* __restrict__ info) {
+    const double floor2 = zrel2 * info->gram_trace;
+    const int j = blockIdx.y;
+    const double gjj = d[j];
+    double mx = 0.0;
+    if (gjj > floor2)
+        for (int i = j + 1 + blockIdx.x * 256 + threadIdx.x; i < N; i += gridDim.x * 256) {
+            const double gii = d[i];
+            if (gii > floor2) {
+                const double2 g = G[i + (size_t)ld * j];
+                mx = fmax(mx, sqrt(g.x * g.x + g.y * g.y) / sqrt(gii * gjj));
+            }
+        }
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0 && mx > 0.0)
+        atomicMax(&info->offmax_bits, (unsigned long long)__double_as_longlong(mx));
 }
 
 // ------------------------------------------------ Cholesky QR re-gauge
@@ -1130,11 +1335,11 @@ size_t heev_bytes(int m_max, int n_max) {
     b += al(ldx * N * sizeof(double2));                         // Xd
     b += al((N + 8) * N * sizeof(double2));                     // G
     b += 2 * al(N * 2 * kTrdNb * sizeof(double2));              // VW, WV
-    b += 2 * al(N * sizeof(double2));                           // yraw, wt
-    b += al(2 * kTrdNb * sizeof(double2));                      // dots
+    b += al((N / kHt + 2) * N * sizeof(double2));               // slots of the trailing product
+    b += al(N * sizeof(double2));                               // wt
     b += al(kPart * sizeof(double));                            // norm partials
     b += al((size_t)kPart * 2 * kTrdNb * sizeof(double2));      // dot partials
-    b += al((N / kGemvWaves + 1) * sizeof(double2));            // partials of w~^H v
+    b += al((N / kHt + 2) * sizeof(double2));                   // partials of w~^H v
     b += al(N * sizeof(double2));                               // tau
     b += 2 * al(N * sizeof(double));                            // d, e
     b += al(N * kBtNb * sizeof(double2));                       // Y
@@ -1160,12 +1365,11 @@ void heev_carve(char* p, int m_max, int n_max, HeevWork& w) {
     w.G = (double2*)take((N + 8) * N * sizeof(double2));
     w.VW = (double2*)take(N * 2 * kTrdNb * sizeof(double2));
     w.WV = (double2*)take(N * 2 * kTrdNb * sizeof(double2));
-    w.yraw = (double2*)take(N * sizeof(double2));
+    w.ypart = (double2*)take((N / kHt + 2) * N * sizeof(double2));
     w.wt = (double2*)take(N * sizeof(double2));
-    w.dots = (double2*)take(2 * kTrdNb * sizeof(double2));
     w.part = (double*)take(kPart * sizeof(double));
     w.pdot = (double2*)take((size_t)kPart * 2 * kTrdNb * sizeof(double2));
-    w.palpha = (double2*)take((N / kGemvWaves + 1) * sizeof(double2));
+    w.palpha = (double2*)take((N / kHt + 2) * sizeof(double2));
     w.tau = (double2*)take(N * sizeof(double2));
     w.d = (double*)take(N * sizeof(double));
     w.e = (double*)take(N * sizeof(double));
@@ -1223,8 +1427,9 @@ const DcPlan& dc_plan(HeevPlans& hp, int N) {
 void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
     const int ldg = N + 8;
     if (N > 64 * kPart) throw HeevFailure{"tridiagonalisation row chunks"};
-    // ---- tridiagonalisation: the trailing matrix-vector products are booked
-    // as K_TRIDIAG, the vector kernels and the rank-2 nb panel updates as K_TRDAUX
+    // ---- tridiagonalisation (lower triangle of G only): the trailing
+    // matrix-vector products are booked as K_TRIDIAG, the vector kernels and
+    // the rank-2 nb panel updates as K_TRDAUX
     for (int j0 = 0; j0 < N - 1; j0 += kTrdNb) {
         const int nbb = std::min(kTrdNb, N - 1 - j0);
         const double pn = (double)N * 2 * kTrdNb;
@@ -1234,17 +1439,19 @@ void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
                       (const double2*)w.G, ldg, N, j0, w.part);
         for (int c = 0; c < nbb; ++c) {
             const int j = j0 + c, len = N - j - 1;
-            const int groups = (len + kGemvWaves - 1) / kGemvWaves;   // <= 512: two partials per thread of k_trd_next
-            launch_booked(pf, K_TRIDIAG, 8.0 * (double)len * len, 16.0 * (double)len * len, k_trd_gemv,
-                          dim3(groups), dim3(64 * kGemvWaves), (size_t)len * sizeof(double2), st, w.G, ldg, N,
-                          j, c, (const double*)w.part, (const double2*)w.pdot, w.VW, w.WV, w.wt, w.palpha, w.tau,
-                          w.d, w.e);
+            const int groups = (len + kHt - 1) / kHt;   // blocks of the trailing product: its partials of w~^H v
+            launch_booked(pf, K_TRIDIAG, 8.0 * (double)len * len, 8.0 * (double)len * (len + 1), k_trd_hemv,
+                          dim3(groups * (groups + 1) / 2), dim3(256), 0, st, (const double2*)w.G, ldg, N, j, c,
+                          (const double*)w.part, w.VW, w.WV, w.ypart, w.tau, w.d, w.e);
+            launch_booked(pf, K_TRDAUX, 16.0 * len * 2 * c, 16.0 * len * (groups + 2.0 * c + 3.0), k_trd_fin,
+                          dim3(groups), dim3(256), 0, st, (const double2*)w.G, ldg, N, j, c, (const double*)w.part,
+                          (const double2*)w.pdot, (const double2*)w.VW, (const double2*)w.ypart, w.wt, w.palpha);
             launch_booked(pf, K_TRDAUX, 16.0 * len * (c + 1), 16.0 * len * (2.0 * c + 6.0), k_trd_next, dim3(kPart),
                           dim3(256), 0, st, w.G, ldg, N, j, c, (int)(c + 1 < nbb), groups, (const double2*)w.tau,
                           w.VW, w.WV, (const double2*)w.wt, (const double2*)w.palpha, w.part, w.pdot);
         }
         const int k0 = j0 + nbb;
-        zgemm<0, 1, 1>(N - k0, N - k0, 2 * kTrdNb, w.VW + k0, N, w.WV + k0, N, w.G + k0 + (size_t)ldg * k0, ldg,
+        zgemm<0, 1, 3>(N - k0, N - k0, 2 * kTrdNb, w.VW + k0, N, w.WV + k0, N, w.G + k0 + (size_t)ldg * k0, ldg,
                        st, 1, 0, 0, 0, 0, &pf, K_TRDAUX);
     }
     hipLaunchKernelGGL(k_trd_last, dim3(1), dim3(64), 0, st, (const double2*)w.G, ldg, N, w.d);
@@ -1282,10 +1489,14 @@ void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
 
 // X (rows x N, FP64, stride ldx) <- X Q_H, blocks of kBtNb reflectors in forward
 // order: X[:, j0+1:] -= ((X[:, j0+1:] Y) T) Y^H with Y the block's reflectors and
-// T its triangular factor (H_j0 .. H_j0+nb-1 = I - Y T Y^H).
+// T its triangular factor (H_j0 .. H_j0+nb-1 = I - Y T Y^H).  ADJ: X <- X Q_H^H,
+// the blocks' adjoints I - Y T^H Y^H in backward order.
+template <bool ADJ>
 static void apply_qh(double2* X, int rows, int ldx, int N, HeevWork& w, Profiler& pf, hipStream_t st) {
     const int ldg = N + 8;
-    for (int j0 = 0; j0 < N - 1; j0 += kBtNb) {
+    const int nblk = (N - 1 + kBtNb - 1) / kBtNb;
+    for (int bk = 0; bk < nblk; ++bk) {
+        const int j0 = (ADJ ? nblk - 1 - bk : bk) * kBtNb;
         const int nbb = std::min(kBtNb, N - 1 - j0);
         const int K = N - j0 - 1;                  // rows j0+1 .. N-1 of Y
         const int splits = (K + kSplitK - 1) / kSplitK;
@@ -1297,11 +1508,11 @@ static void apply_qh(double2* X, int rows, int ldx, int N, HeevWork& w, Profiler
                        (size_t)kBtNb * kBtNb, &pf, K_BTAUX);
         launch_booked(pf, K_BTAUX, 0.0, 16.0 * kBtNb * kBtNb * (splits + 1), k_bt_sred, dim3(1), dim3(1024), 0, st,
                       (const double2*)w.Cpart, splits, w.Tm);
-        // X Y (split-K), then P = (X Y) T by row-wise substitution
+        // X Y (split-K), then P = (X Y) T (or T^H) by row-wise substitution
         zgemm<0, 0, 0>(rows, kBtNb, K, X + (size_t)ldx * (j0 + 1), ldx, Ys, N, w.Cpart, rows, st, splits, kSplitK,
                        (size_t)kSplitK * ldx, kSplitK, (size_t)rows * kBtNb, &pf, K_BACK);
-        launch_booked(pf, K_BTAUX, 8.0 * rows * kBtNb * kBtNb / 2, 16.0 * rows * kBtNb * (splits + 1), k_bt_solve,
-                      dim3((rows + 3) / 4), dim3(256), 0, st, (const double2*)w.Cpart, splits, rows,
+        launch_booked(pf, K_BTAUX, 8.0 * rows * kBtNb * kBtNb / 2, 16.0 * rows * kBtNb * (splits + 1),
+                      k_bt_solve<ADJ>, dim3((rows + 3) / 4), dim3(256), 0, st, (const double2*)w.Cpart, splits, rows,
                       (const double2*)w.Tm, (const double2*)w.tau, j0, nbb, w.P);
         // X[:, j0+1:] -= P Y^H
         zgemm<0, 1, 1>(rows, K, kBtNb, w.P, rows, Ys, N, X + (size_t)ldx * (j0 + 1), ldx, st, 1, 0, 0, 0, 0, &pf,
@@ -1309,34 +1520,79 @@ static void apply_qh(double2* X, int rows, int ldx, int N, HeevWork& w, Profiler
     }
 }
 
+// M[r, i] = Z[i, N-1-r] (as complex): the last `keep` eigenvectors (largest
+// eigenvalues first) as the rows of M (stride ldm).
+__global__ __launch_bounds__(256) void k_top_rows(const double* __restrict__ Z, int N, int keep,
+                                                  double2* __restrict__ M, int ldm) {
+    const int r = blockIdx.x * 256 + threadIdx.x, i = blockIdx.y;
+    if (r < keep) M[r + (size_t)ldm * i] = make_double2(Z[i + (size_t)N * (N - 1 - r)], 0.0);
+}
+
+// *rest = sum of the n smallest eigenvalues (ascending dv), negatives (rounding) as 0.
+__global__ __launch_bounds__(256) void k_rest_weight(const double* __restrict__ dv, int n, double* rest) {
+    __shared__ double red[4];
+    double t = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) t += fmax(dv[i], 0.0);
+    t = block_sum<256>(t, red);
+    if (threadIdx.x == 0) *rest = t;
+}
+
 // X (m x N, storage T, stride ld) <- X Q_H Z for the Gram eigen-decomposition
-// of X, all in FP64.  Throws HeevFailure on a HIP error.
+// of X, all in FP64.  With keep < N only the eigenvectors of the keep largest
+// eigenvalues are applied, X (m x keep) <- X (Q_H Z_keep): Q_H Z_keep =
+// (Z_keep^T Q_H^H)^H is formed on the keep x N matrix M (the reflectors' cost
+// falls with keep / m), and *rest (device) receives the sum of the other
+// eigenvalues, the weight of the columns left out.  Returns the number of
+// columns written (keep, or N when the subset does not fit the scratch).
+// Throws HeevFailure on a HIP error.
 template <typename T>
-void heev_precondition(C2<T>* X, int m, int N, int ld, HeevWork& w, Profiler& pf, hipStream_t st) {
+int heev_precondition(C2<T>* X, int m, int N, int ld, int keep, double* rest, HeevWork& w, Profiler& pf,
+                      hipStream_t st) {
     if (N > w.cap_n || m > w.cap_m || N < 2) throw HeevFailure{"eigen-preconditioner capacity"};
     const int ldx = ((w.cap_m + 1) & ~1) + 8;
     const int ldg = N + 8;
-    // ---- X -> FP64, Gram
+    const int ldm = ((keep + 1) & ~1) + 8;
+    // M lives in the divide-and-conquer scratch U, the FP64 product in Z2 (both
+    // N x N doubles, free once the eigenvectors are in Z)
+    const bool subset = keep < N && rest != nullptr && 2 * (size_t)ldm * N <= (size_t)N * N &&
+                        2 * (size_t)m * keep <= (size_t)N * N;
+    // ---- X -> FP64, Gram (lower triangle)
     launch_booked(pf, K_BTAUX, 0.0, (double)m * N * (sizeof(C2<T>) + 16.0), k_to_f64<T>, dim3((m + 255) / 256, N),
                   dim3(256), 0, st, (const C2<T>*)X, m, ld, w.Xd, ldx);
-    zgemm<1, 0, 0>(N, N, m, w.Xd, ldx, w.Xd, ldx, w.G, ldg, st, 1, 0, 0, 0, 0, &pf, K_HGRAM);
+    zgemm<1, 0, 2>(N, N, m, w.Xd, ldx, w.Xd, ldx, w.G, ldg, st, 1, 0, 0, 0, 0, &pf, K_HGRAM);
 
     heev_run(N, w, pf, st);
 
-    // ---- X <- X Q_H
-    apply_qh(w.Xd, m, ldx, N, w, pf, st);
-
-    // ---- X <- Xd Z (real view: 2m x N times N x N), rounded to the storage precision
-    launch_booked(pf, K_HOUT, 4.0 * (double)m * N * N,
-                  16.0 * (double)m * N + 8.0 * (double)N * N + (double)m * N * sizeof(C2<T>), k_dgemm<T>,
-                  dim3((2 * m + ZBM - 1) / ZBM, (N + ZBN - 1) / ZBN), dim3(256), 0, st, 2 * m, N, N,
-                  (const double*)w.Xd, 2 * ldx, (const double*)w.Z, N, (T*)X, 2 * ld);
+    if (!subset) {
+        // ---- X <- X Q_H
+        apply_qh<false>(w.Xd, m, ldx, N, w, pf, st);
+        // ---- X <- Xd Z (real view: 2m x N times N x N), rounded to the storage precision
+        launch_booked(pf, K_HOUT, 4.0 * (double)m * N * N,
+                      16.0 * (double)m * N + 8.0 * (double)N * N + (double)m * N * sizeof(C2<T>), k_dgemm<T>,
+                      dim3((2 * m + ZBM - 1) / ZBM, (N + ZBN - 1) / ZBN), dim3(256), 0, st, 2 * m, N, N,
+                      (const double*)w.Xd, 2 * ldx, (const double*)w.Z, N, (T*)X, 2 * ld);
+        if (hipGetLastError() != hipSuccess) throw HeevFailure{"eigen-preconditioner launch"};
+        w.n_runs += 1;
+        return N;
+    }
+    double2* M = (double2*)w.U;
+    double2* Xo = (double2*)w.Z2;
+    launch_booked(pf, K_HOUT, 0.0, 24.0 * (double)keep * N, k_top_rows, dim3((keep + 255) / 256, N), dim3(256), 0, st,
+                  (const double*)w.Z, N, keep, M, ldm);
+    apply_qh<true>(M, keep, ldm, N, w, pf, st);
+    // ---- X (m x keep) <- Xd M^H, rounded to the storage precision
+    zgemm<0, 1, 0>(m, keep, N, w.Xd, ldx, M, ldm, Xo, m, st, 1, 0, 0, 0, 0, &pf, K_HOUT);
+    launch_booked(pf, K_HOUT, 0.0, (double)m * keep * (16.0 + sizeof(C2<T>)), k_from_f64<T>,
+                  dim3((m + 255) / 256, keep), dim3(256), 0, st, (const double2*)Xo, m, m, X, ld);
+    launch_booked(pf, K_HOUT, 0.0, 8.0 * (N - keep), k_rest_weight, dim3(1), dim3(256), 0, st, (const double*)w.dv,
+                  N - keep, rest);
     if (hipGetLastError() != hipSuccess) throw HeevFailure{"eigen-preconditioner launch"};
     w.n_runs += 1;
+    return keep;
 }
 
-template void heev_precondition<double>(double2*, int, int, int, HeevWork&, Profiler&, hipStream_t);
-template void heev_precondition<float>(float2*, int, int, int, HeevWork&, Profiler&, hipStream_t);
+template int heev_precondition<double>(double2*, int, int, int, int, double*, HeevWork&, Profiler&, hipStream_t);
+template int heev_precondition<float>(float2*, int, int, int, int, double*, HeevWork&, Profiler&, hipStream_t);
 
 // Hermitian eigen-decomposition of a host matrix (tests): G row-major complex
 // N x N (interleaved), values ascending, vectors as columns of V (row-major).
@@ -1356,7 +1612,7 @@ void heev_host(int N, const double* Gh, double* wh, double* Vh, HeevWork& w, Pro
     for (int i = 0; i < N; ++i) eye[i + (size_t)ldx * i] = make_double2(1.0, 0.0);
     if (hipMemcpyAsync(w.Xd, eye.data(), eye.size() * sizeof(double2), hipMemcpyHostToDevice, st) != hipSuccess)
         throw HeevFailure{"copy in"};
-    apply_qh(w.Xd, N, ldx, N, w, pf, st);
+    apply_qh<false>(w.Xd, N, ldx, N, w, pf, st);
     // V (complex, N x N, ld ldx) into G's storage
     {
         dim3 grid((2 * N + ZBM - 1) / ZBM, (N + ZBN - 1) / ZBN);
@@ -1395,6 +1651,18 @@ bool cholqr3(const C2<T>* A, int m, int r, int lda, C2<T>* Q, int ldq, C2<T>* R,
     double2* Rt = nullptr;            // accumulated R (one of Z, U)
     double2* Rp = (double2*)w.Z2;     // this pass's R
     const double u = 1.1102230246251565e-16;
+    std::function<void(int, int)> trsm = [&](int c0, int nc) {
+        if (nc <= 64) {
+            launch_booked(pf, K_QR, 4.0 * (double)m * nc * nc, 32.0 * (double)m * nc, k_qr_rowsolve,
+                          dim3((m + 3) / 4), dim3(256), 0, st, Ad, ldx, m, (const double2*)w.G, ldg, c0, nc);
+            return;
+        }
+        const int h = ((nc / 2 + 63) / 64) * 64;
+        trsm(c0, h);
+        zgemm<0, 0, 1>(m, nc - h, h, Ad + (size_t)ldx * c0, ldx, w.G + c0 + (size_t)ldg * (c0 + h), ldg,
+                       Ad + (size_t)ldx * (c0 + h), ldx, st, 1, 0, 0, 0, 0, &pf, K_QR);
+        trsm(c0 + h, nc - h);
+    };
     auto pass_run = [&](int kind) {
         zgemm<1, 0, 0>(r, r, m, Ad, ldx, Ad, ldx, w.G, ldg, st, 1, 0, 0, 0, 0, &pf, K_QR);
         if (kind == kQrShifted)
@@ -1415,15 +1683,10 @@ bool cholqr3(const C2<T>* A, int m, int r, int lda, C2<T>* Q, int ldq, C2<T>* R,
                                st, 1, 0, 0, 0, 0, &pf, K_QR);
             }
         }
-        // Ad <- Ad R^{-1}, column blocks in order
-        for (int k0 = 0; k0 < r; k0 += 64) {
-            const int kb = std::min(64, r - k0);
-            if (k0 > 0)
-                zgemm<0, 0, 1>(m, kb, k0, Ad, ldx, w.G + (size_t)ldg * k0, ldg, Ad + (size_t)ldx * k0, ldx, st, 1, 0,
-                               0, 0, 0, &pf, K_QR);
-            launch_booked(pf, K_QR, 4.0 * (double)m * kb * kb, 32.0 * (double)m * kb, k_qr_rowsolve,
-                          dim3((m + 3) / 4), dim3(256), 0, st, Ad, ldx, m, (const double2*)w.G, ldg, k0, kb);
-        }
+        // Ad <- Ad R^{-1} by recursive halving: Q_1 = A_1 R_11^{-1}, then
+        // A_2 -= Q_1 R_12 on MFMA and Q_2 = A_2 R_22^{-1}; 64-column leaves by
+        // row-wise substitution (backward stable, like the column-block order)
+        trsm(0, r);
         // R accumulation: Rt = R_pass Rt
         if (!Rt) {
             Rt = (double2*)w.Z;
@@ -1470,5 +1733,35 @@ template bool cholqr3<double>(const double2*, int, int, int, double2*, int, doub
                               HeevWork&, Profiler&, hipStream_t);
 template bool cholqr3<float>(const float2*, int, int, int, float2*, int, float2*, DevInfo*, DevInfo*, HeevWork&,
                              Profiler&, hipStream_t);
+
+// Certificate of the eigen start: the largest relative off-diagonal of X^H X,
+// measured in FP64 as the sweeps measure it, against tol.  Returns true when X
+// is orthogonal to tol (then the sweeps can be skipped); reads the measure back
+// through info_host (synchronises).
+template <typename T>
+bool heev_check(C2<T>* X, int m, int N, int ld, double tol, double zrel2, DevInfo* info, DevInfo* info_host,
+                HeevWork& w, Profiler& pf, hipStream_t st) {
+    const int ldx = ((w.cap_m + 1) & ~1) + 8;
+    const int ldg = N + 8;
+    launch_booked(pf, K_HGRAM, 0.0, (double)m * N * (sizeof(C2<T>) + 16.0), k_to_f64<T>, dim3((m + 255) / 256, N),
+                  dim3(256), 0, st, (const C2<T>*)X, m, ld, w.Xd, ldx);
+    zgemm<1, 0, 2>(N, N, m, w.Xd, ldx, w.Xd, ldx, w.G, ldg, st, 1, 0, 0, 0, 0, &pf, K_HGRAM);
+    launch_booked(pf, K_HGRAM, 0.0, 24.0 * N, k_gram_diag, dim3(1), dim3(256), 0, st, (const double2*)w.G, ldg, N,
+                  w.dv, info);
+    launch_booked(pf, K_HGRAM, 0.0, 8.0 * (double)N * N, k_gram_offmax, dim3(4, N), dim3(256), 0, st,
+                  (const double2*)w.G, ldg, N, zrel2, (const double*)w.dv, info);
+    if (hipMemcpyAsync(info_host, info, sizeof(DevInfo), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        throw HeevFailure{"Gram check read"};
+    double off;
+    const unsigned long long bits = info_host->offmax_bits;
+    std::memcpy(&off, &bits, sizeof(off));
+    return off <= tol;
+}
+
+template bool heev_check<double>(double2*, int, int, int, double, double, DevInfo*, DevInfo*, HeevWork&,
+                                 Profiler&, hipStream_t);
+template bool heev_check<float>(float2*, int, int, int, double, double, DevInfo*, DevInfo*, HeevWork&,
+                                Profiler&, hipStream_t);
 
 }  // namespace mpo

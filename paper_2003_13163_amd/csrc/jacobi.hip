@@ -936,7 +936,7 @@ __global__ __launch_bounds__(256) void k_pair_update(C2<T>* __restrict__ X, int 
 // values.  Single work-group, FP64.
 __global__ __launch_bounds__(256) void k_truncate(const double* __restrict__ sig2, int N,
                                                   int chi_max, double cutoff, double floor_rel2,
-                                                  DevInfo* info) {
+                                                  DevInfo* info, int with_rest) {
     __shared__ double red[256];
     __shared__ int cnt[256];
     __shared__ double s_total, s_kept;
@@ -950,7 +950,9 @@ __global__ __launch_bounds__(256) void k_truncate(const double* __restrict__ sig
         if (t < o) red[t] += red[t + o];
         __syncthreads();
     }
-    if (t == 0) s_total = red[0];
+    // values left out of sig2 (all below the last of it) count as discarded
+    const double rest = with_rest ? info->rest_weight : 0.0;
+    if (t == 0) s_total = red[0] + rest;
     __syncthreads();
     const double total = s_total;
     // values the sweep treated as zero are never kept
@@ -992,7 +994,7 @@ __global__ __launch_bounds__(256) void k_truncate(const double* __restrict__ sig
         if (t < o) red[t] += red[t + o];
         __syncthreads();
     }
-    const double disc = red[0];
+    const double disc = red[0] + rest;
     __syncthreads();
     double ent = 0.0;
     if (kept > 0.0) {
@@ -1351,15 +1353,50 @@ static int jacobi_run(C2<T>* X, int m, int N, int ld, double tol, double stop_of
 // first phase of split-BF16x3 mode).
 template <typename T>
 int jacobi_orthogonalize(C2<T>* X, int m, int N, int ld, double tol, int max_sweeps, JacobiWork& w,
-                         hipStream_t st) {
+                         hipStream_t st, int keep_max) {
     w.n_splits += 1;
+    w.n_cols = N;
+    w.rest_on = false;
     // Start from the eigenvectors of X^H X: the columns are then orthogonal to
     // about the FP64 eigen-solver's accuracy and the sweeps only polish.
     bool started = false;
     if (w.heev && w.precond_min > 0 && N >= w.precond_min && N <= w.heev->cap_n && m <= w.heev->cap_m) {
-        heev_precondition<T>(X, m, N, ld, *w.heev, *w.prof, st);
+        // FP32 storage keeping at most keep_max columns: only the eigenvectors of
+        // the largest keep_max + 64 eigenvalues (rounded up to 64) are applied.
+        // Their span is the leading singular subspace to FP64 accuracy, far
+        // below the storage rounding, and the margin covers ties at the cut.
+        int keep = N;
+        if (sizeof(T) == 4 && keep_max > 0) {
+            const int k2 = (keep_max + 64 + 63) / 64 * 64;
+            if (2 * k2 <= N) keep = k2;
+        }
+        const int ncols = heev_precondition<T>(X, m, N, ld, keep, &w.info->rest_weight, *w.heev, *w.prof, st);
+        if (ncols < N) {
+            N = ncols;
+            w.n_cols = N;
+            w.rest_on = true;
+        }
         w.n_precond += 1;
         started = true;
+        // FP32 storage: the start is orthogonal to well below the sweeps' FP32
+        // tolerance, so one FP64 Gram product certifies it in place of a sweep
+        // that would find nothing to rotate; only norms and order remain.  (In
+        // FP64 storage the start is left to the sweeps: its small columns are
+        // only as orthogonal as the Gram's absolute accuracy allows.)
+        if (sizeof(T) == 4 &&
+            heev_check<T>(X, m, N, ld, std::fmin(tol, kTolFp32), jacobi_zero_rel2<T>(), w.info, w.info_host,
+                          *w.heev, *w.prof, st)) {
+            hipLaunchKernelGGL(k_jacobi_reset, dim3(1), dim3(64), 0, st, w.info);
+            double* fro2 = &w.info->total;
+            w.prof->begin(st);
+            hipLaunchKernelGGL((k_colnorm2<T>), dim3((N + 3) / 4), dim3(256), 0, st, X, m, N, ld, w.nrm2,
+                               (const int*)nullptr);
+            hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, w.nrm2, N, w.colmap, w.sig2, fro2,
+                               (const int*)nullptr);
+            w.prof->end(st, K_NORMSORT, 8.0 * m * N, (double)m * N * 2.0 * sizeof(T));
+            w.n_checks += 1;
+            return 0;
+        }
     }
     if constexpr (sizeof(T) == 4) {
         if (w.bf3 && !started) {
@@ -1387,9 +1424,9 @@ int jacobi_orthogonalize(C2<T>* X, int m, int N, int ld, double tol, int max_swe
 }
 
 void launch_truncate(const double* sig2, int N, int chi_max, double cutoff, double floor_rel2,
-                     DevInfo* info, hipStream_t st) {
+                     DevInfo* info, hipStream_t st, bool with_rest) {
     hipLaunchKernelGGL(k_truncate, dim3(1), dim3(256), 0, st, sig2, N, chi_max, cutoff, floor_rel2,
-                       info);
+                       info, (int)with_rest);
 }
 
 template <typename T>
@@ -1423,7 +1460,7 @@ void launch_copy(const C2<T>* src, C2<T>* dst, size_t count, hipStream_t st) {
 }
 
 #define INST(T)                                                                                  \
-    template int jacobi_orthogonalize<T>(C2<T>*, int, int, int, double, int, JacobiWork&, hipStream_t); \
+    template int jacobi_orthogonalize<T>(C2<T>*, int, int, int, double, int, JacobiWork&, hipStream_t, int); \
     template void launch_gather_cols<T>(const C2<T>*, int, int, const int*, const double*, int,     \
                                         C2<T>*, int, hipStream_t, bool);                           \
     template void launch_gather_rows_conj<T>(const C2<T>*, int, int, const int*, const double*, int, \
