@@ -160,7 +160,7 @@ struct HeevWork {
     double* part;                     // partial sums of ||column||^2 (row chunks)
     double2 *pdot, *palpha;           // partial sums of the panel dots and of w~^H v
     double *d, *e;                    // tridiagonal
-    double2 *Y, *Tm, *Cpart, *P;      // back-transformation blocks, split-K partials
+    double2 *Sall, *Cpart, *P;        // back-transformation: Y^H Y per block, split-K partials, (X Y) T
     double *Z, *Z2, *U;               // eigenvectors of T and merge scratch (N x N, stride N)
     double *dv, *ds, *dz, *ndv, *ndz, *dfv, *taus, *lam, *zh;
     int *dcol, *ndc, *dfc, *orig, *perm;

@@ -352,20 +352,20 @@ __global__ __launch_bounds__(256) void k_trd_colnorm(const double2* __restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// Column j of the panel (c = j - j0): y = G_eff v over the trailing matrix
-// G[j+1:, j+1:] of which only the lower triangle is read, in 64x64 tiles, one
-// work-group per tile (I, J), I >= J (tile coordinates from the trailing
-// origin j+1):
-//   reflector      from the updated column (scalars recomputed identically in
-//                  every work-group from the partial sums of ||G[j+2:, j]||^2)
-//   tile I > J     row partials G_IJ v_J (rows of block I) and column partials
-//                  G_IJ^H v_I (rows of block J), each into its own slot of
+// Column j of the panel (c = j - j0).  With G0 the panel-start trailing matrix
+// G[j+1:, j+1:] (as stored: the panel's updates are deferred) and the
+// reflector v = e_0 + scale u, u = [0, x], x = G[j+2:, j] as stored,
+//   G_eff v = G0 e_0 + scale G0 u - V (W^H v) - W (V^H v):
+// G0 e_0 is the stored column G[j+1:, j+1], and the tile product G0 u needs
+// neither the reflector's scalars nor the panel.  k_trd_hemv forms G0 u from
+// the lower triangle only, in 64x64 tiles, one work-group per tile (I, J),
+// I >= J (tile coordinates from the trailing origin j+1):
+//   tile I > J     row partials G_IJ u_J (rows of block I) and column partials
+//                  G_IJ^H u_I (rows of block J), each into its own slot of
 //                  ypart: block K's rows collect slot J from tile (K, J), slot
 //                  I from tile (I, K), and slots K and nt from the diagonal
 //                  tile (its strict lower part both ways, the real diagonal
 //                  once), nt + 1 slots in all, summed by k_trd_fin.
-// Work-group 0 stores the reflector in the panel buffers together with tau_j,
-// e_j and d_j (column j of G is still being read).
 constexpr int kHt = 64;   // tile edge of the trailing product
 
 __device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
@@ -376,22 +376,17 @@ __device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
     J = t - i * (i + 1) / 2;
 }
 
-__global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G, int ldg, int N, int j, int c,
-                                                  const double* __restrict__ part, double2* __restrict__ VW,
-                                                  double2* __restrict__ WV, double2* __restrict__ ypart,
-                                                  double2* __restrict__ tau, double* __restrict__ d,
-                                                  double* __restrict__ e) {
-    __shared__ double2 vI[kHt], vJ[kHt];
+__global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G, int ldg, int N, int j,
+                                                  double2* __restrict__ ypart) {
+    __shared__ double2 uI[kHt], uJ[kHt];
     __shared__ double2 red[4][kHt];
-    __shared__ double sxn2;
     const int len = N - j - 1;
     const int nt = (len + kHt - 1) / kHt;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int I, J;
     lower_tile((int)blockIdx.x, I, J);
-    // the tile first (it depends on nothing else): lane (p, q) = (lane % 8,
-    // lane / 8) takes rows 8 s + p and columns 16 wave + 8 cc + q, so each load
-    // instruction reads eight 128-byte row runs
+    // lane (p, q) = (lane % 8, lane / 8) takes rows 8 s + p and columns
+    // 16 wave + 8 cc + q, so each load instruction reads eight 128-byte row runs
     const int p = lane & 7, q = lane >> 3;
     const int rows = min(kHt, len - kHt * I), cols = min(kHt, len - kHt * J);
     const double2* T0 = G + (size_t)(j + 1 + kHt * I) + (size_t)ldg * (j + 1 + kHt * J);
@@ -404,31 +399,14 @@ __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G,
             const bool ok = r < rows && b < cols && (I != J || r >= b);
             a[s8][cc] = ok ? T0[r + (size_t)ldg * b] : make_double2(0.0, 0.0);
         }
-    if (tid < 64) {
-        const double xn = wave_sum(part[tid]);
-        if (tid == 0) sxn2 = xn;
-    }
-    __syncthreads();
-    const double2 alpha = G[(j + 1) + (size_t)ldg * j];
-    const House h = house_scalars(alpha, sxn2);
+    // u = [0, G[j+2:, j]] on the tile's row and column blocks
     const double2* colj = G + (size_t)ldg * j + (j + 1);
-    auto vval = [&](int r) -> double2 {
-        if (r >= len) return make_double2(0.0, 0.0);
-        return r == 0 ? make_double2(1.0, 0.0) : zmul(colj[r], h.scale);
-    };
-    if (tid < 64) vI[tid] = vval(kHt * I + tid);
-    else if (tid < 128) vJ[tid - 64] = vval(kHt * J + tid - 64);
-    if (blockIdx.x == 0) {
-        if (tid == 0) {
-            tau[j] = h.tau;
-            e[j] = h.beta;
-            d[j] = G[j + (size_t)ldg * j].x;
-        }
-        for (int r = tid; r < N; r += 256) {
-            const double2 v = r <= j ? make_double2(0.0, 0.0) : vval(r - j - 1);
-            VW[r + (size_t)N * c] = v;
-            WV[r + (size_t)N * (kTrdNb + c)] = v;
-        }
+    if (tid < 128) {
+        const int r = kHt * (tid < 64 ? I : J) + (tid & 63);
+        double2 u = make_double2(0.0, 0.0);
+        if (r > 0 && r < len) u = colj[r];
+        if (tid < 64) uI[tid] = u;
+        else uJ[tid - 64] = u;
     }
     __syncthreads();
     double2 racc[8], cacc[2];
@@ -438,19 +416,19 @@ __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G,
     for (int s8 = 0; s8 < 8; ++s8) {
         racc[s8] = make_double2(0.0, 0.0);
         const int r = 8 * s8 + p;
-        const double2 vi = vI[r];
+        const double2 ui = uI[r];
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc) {
             const int b = 16 * wave + 8 * cc + q;
             double2 g = a[s8][cc];
             const bool diag = I == J && r == b;
             if (diag) g.y = 0.0;                   // Hermitian: real diagonal, counted once
-            const double2 vb = vJ[b];
-            racc[s8].x += g.x * vb.x - g.y * vb.y;
-            racc[s8].y += g.x * vb.y + g.y * vb.x;
-            if (!diag) {                            // conj(g) v_r into y_b
-                cacc[cc].x += g.x * vi.x + g.y * vi.y;
-                cacc[cc].y += g.x * vi.y - g.y * vi.x;
+            const double2 ub = uJ[b];
+            racc[s8].x += g.x * ub.x - g.y * ub.y;
+            racc[s8].y += g.x * ub.y + g.y * ub.x;
+            if (!diag) {                            // conj(g) u_r into y_b
+                cacc[cc].x += g.x * ui.x + g.y * ui.y;
+                cacc[cc].y += g.x * ui.y - g.y * ui.x;
             }
         }
     }
@@ -491,80 +469,134 @@ __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G,
     }
 }
 
-// Finish of the trailing product, one work-group per 64-row block K: y = the
-// block's nt + 1 slots summed in fixed order, minus the panel's correction
-// (V p + W q) with p = W^H v and q = V^H v from the partial sums the previous
-// column's kernel left; w~_i = tau_j y_i, and the block's partial sum of w~^H v.
+// Finish of column j, one work-group per 64-row block K of the trailing rows:
+//   reflector      scalars from alpha = G[j+1, j] and the partial sums of
+//                  ||G[j+2:, j]||^2 (the same butterfly in every wave);
+//   y              = G[j+1:, j+1] + scale (the block's nt + 1 slots, summed in
+//                  fixed order) - (V p + W q), p = W^H v and q = V^H v from the
+//                  partial sums the previous kernel left;
+//   out            w~_i = tau_j y_i, the block's partial sum of w~^H v, and v
+//                  into the panel buffers (work-group 0 also the rows above the
+//                  trailing part, tau_j, e_j and d_j).
+// Every load that depends on nothing computed here is issued first.
+constexpr int kFinSlots = (64 * kPart / kHt + 1 + 3) / 4;   // slots per thread (nt + 1 <= 65)
+
 __global__ __launch_bounds__(256) void k_trd_fin(const double2* __restrict__ G, int ldg, int N, int j, int c,
                                                  const double* __restrict__ part,
-                                                 const double2* __restrict__ pdot,
-                                                 const double2* __restrict__ VW,
-                                                 const double2* __restrict__ ypart, double2* __restrict__ wt,
-                                                 double2* __restrict__ palpha) {
+                                                 const double2* __restrict__ pdot, double2* __restrict__ VW,
+                                                 double2* __restrict__ WV, const double2* __restrict__ ypart,
+                                                 double2* __restrict__ wt, double2* __restrict__ palpha,
+                                                 double2* __restrict__ tau, double* __restrict__ d,
+                                                 double* __restrict__ e) {
     __shared__ double2 red[4][kHt];
     __shared__ double2 pq[2 * kTrdNb];
-    __shared__ double sxn2;
+    const double2 zero = make_double2(0.0, 0.0);
     const int len = N - j - 1;
     const int nt = (len + kHt - 1) / kHt;
     const int K = blockIdx.x;
     const int nr = min(kHt, len - kHt * K);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = tid & 63, g = tid >> 6;     // row of the block, slot / panel-column group
+    const int row = kHt * K + r;              // trailing row (G row j + 1 + row)
+    const int i = j + 1 + row;
+    const bool live = r < nr;
     const size_t ldy = (size_t)N;
-    {
-        const int r = tid & 63, g = tid >> 6;
-        double2 acc = make_double2(0.0, 0.0);
-        if (r < nr)
-            for (int sl = g; sl <= nt; sl += 4) {
-                const double2 v = ypart[(size_t)sl * ldy + kHt * K + r];
-                acc.x += v.x;
-                acc.y += v.y;
-            }
-        red[g][r] = acc;
+    // ---- independent loads
+    double2 sl[kFinSlots];
+#pragma unroll
+    for (int k = 0; k < kFinSlots; ++k) {
+        const int s = g + 4 * k;
+        sl[k] = zero;
+        if (live && s <= nt) sl[k] = ypart[(size_t)s * ldy + row];
     }
-    if (tid < 64) {
-        const double xn = wave_sum(part[tid]);
-        if (tid == 0) sxn2 = xn;
+    double2 cv[kTrdNb / 4], cw[kTrdNb / 4];   // V[i, q], W[i, q] for q = g + 4 k < c
+#pragma unroll
+    for (int k = 0; k < kTrdNb / 4; ++k) {
+        const int qq = g + 4 * k;
+        cv[k] = zero;
+        cw[k] = zero;
+        if (live && qq < c) {
+            cv[k] = VW[i + (size_t)N * qq];
+            cw[k] = VW[i + (size_t)N * (kTrdNb + qq)];
+        }
     }
-    __syncthreads();
+    double2 g0 = zero, xi = zero;
+    if (live && g == 0) {
+        g0 = G[i + (size_t)ldg * (j + 1)];
+        if (row == 0) g0.y = 0.0;             // the diagonal is real
+        xi = G[i + (size_t)ldg * j];
+    }
+    const double pt = part[lane];
     const double2 alpha = G[(j + 1) + (size_t)ldg * j];
-    const House h = house_scalars(alpha, sxn2);
-    // p = W^H v, q = V^H v over the panel's first c columns
+    // ---- reflector scalars
+    const House h = house_scalars(alpha, wave_sum(pt));
+    // p_q = conj(W[j+1, q]) + scale (W^H x)_q from the kPart partial sums of
+    // W^H x (likewise q with V): one dot per wave at a time
     for (int dd = wave; dd < 2 * c; dd += 4) {
         const int qq = dd % c, isv = dd / c;
         const double2 t = pdot[(size_t)lane * 2 * kTrdNb + isv * kTrdNb + qq];
         const double sr = wave_sum(t.x), si = wave_sum(t.y);
         if (lane == 0) {
-            const double2 row = VW[(j + 1) + (size_t)N * ((isv ? 0 : kTrdNb) + qq)];
+            const double2 rw = VW[(j + 1) + (size_t)N * ((isv ? 0 : kTrdNb) + qq)];
             const double2 sc = zmul(h.scale, make_double2(sr, si));
-            pq[isv * kTrdNb + qq] = make_double2(row.x + sc.x, -row.y + sc.y);
+            pq[isv * kTrdNb + qq] = make_double2(rw.x + sc.x, -rw.y + sc.y);
         }
     }
     __syncthreads();
-    if (tid < 64) {
-        double2 contrib = make_double2(0.0, 0.0);
-        if (tid < nr) {
-            double sr = red[0][tid].x, si = red[0][tid].y;
+    // ---- this thread's share: scale (its slots) - (its panel columns of V p + W q)
+    double2 acc = zero;
 #pragma unroll
-            for (int w4 = 1; w4 < 4; ++w4) { sr += red[w4][tid].x; si += red[w4][tid].y; }
-            const int r = kHt * K + tid;
-            const int i = j + 1 + r;
-            for (int qq = 0; qq < c; ++qq) {   // (V p + W q)_i
-                const double2 t1 = zmul(VW[i + (size_t)N * qq], pq[qq]);
-                const double2 t2 = zmul(VW[i + (size_t)N * (kTrdNb + qq)], pq[kTrdNb + qq]);
-                sr -= t1.x + t2.x;
-                si -= t1.y + t2.y;
-            }
+    for (int k = 0; k < kFinSlots; ++k) { acc.x += sl[k].x; acc.y += sl[k].y; }
+    acc = zmul(h.scale, acc);
+#pragma unroll
+    for (int k = 0; k < kTrdNb / 4; ++k) {
+        const int qq = g + 4 * k;
+        if (qq < c) {
+            const double2 t1 = zmul(cv[k], pq[qq]);
+            const double2 t2 = zmul(cw[k], pq[kTrdNb + qq]);
+            acc.x -= t1.x + t2.x;
+            acc.y -= t1.y + t2.y;
+        }
+    }
+    red[g][r] = acc;
+    __syncthreads();
+    if (tid < 64) {
+        double2 contrib = zero;
+        if (live) {
+            double sr = g0.x, si = g0.y;
+#pragma unroll
+            for (int w4 = 0; w4 < 4; ++w4) { sr += red[w4][tid].x; si += red[w4][tid].y; }
             const double2 w = zmul(h.tau, make_double2(sr, si));
+            const double2 vi = row == 0 ? make_double2(1.0, 0.0) : zmul(xi, h.scale);
             wt[i] = w;
-            const double2 vi = r == 0 ? make_double2(1.0, 0.0) : zmul(G[i + (size_t)ldg * j], h.scale);
+            VW[i + (size_t)N * c] = vi;
+            WV[i + (size_t)N * (kTrdNb + c)] = vi;
             contrib = zcmul(w, vi);
         }
         contrib.x = wave_sum(contrib.x);
         contrib.y = wave_sum(contrib.y);
         if (tid == 0) palpha[K] = contrib;
     }
+    if (K == 0) {
+        // rows 0 .. j of the panel's column c are zero; the reflector's scalars
+        for (int rr = tid; rr <= j; rr += 256) {
+            VW[rr + (size_t)N * c] = zero;
+            WV[rr + (size_t)N * (kTrdNb + c)] = zero;
+        }
+        if (tid == 0) {
+            tau[j] = h.tau;
+            e[j] = h.beta;
+            d[j] = G[j + (size_t)ldg * j].x;
+        }
+    }
 }
 
+// w = w~ + alpha v with alpha = -tau_j (w~^H v) / 2 into the panel buffers
+// (zero above row j+1), the reflector below the diagonal of G (G[j+1, j] = 1
+// for the back-transformation); if the panel continues, column j+1 is brought up to
+// date, G[j+1:, j+1] -= V conj(W[j+1, :]) + W conj(V[j+1, :]), and the
+// partial sums its reflector needs are formed: ||G[j+3:, j+1]||^2, and
+// W^H G[j+3:, j+1], V^H G[j+3:, j+1] over the panel's first c+1 columns.
 __global__ __launch_bounds__(256) void k_trd_next(double2* __restrict__ G, int ldg, int N, int j, int c,
                                                   int update_next, int gemv_groups,
                                                   const double2* __restrict__ tau, double2* __restrict__ VW,
@@ -1035,31 +1067,15 @@ __global__ __launch_bounds__(256) void k_dc_perm(const DcMerge* __restrict__ pla
 
 // --------------------------------------------------- back-transformation
 // Y = [v_j0 .. v_j0+nb-1] (N x kBtNb, zero-padded) from the reflectors below the diagonal.
-__global__ __launch_bounds__(256) void k_bt_y(const double2* __restrict__ G, int ldg, int N, int j0, int nbb,
-                                              const double2* __restrict__ tau, double2* __restrict__ Y) {
-    const int i = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+// The reflectors in place: G[i, j] <- 0 for i <= j, and column j <- 0 where
+// tau_j = 0 (no reflection), so that G's columns j0 .. j0+63 are the block's Y
+// (v_j[j+1] = 1 is stored already).
+__global__ __launch_bounds__(256) void k_bt_mask(double2* __restrict__ G, int ldg, int N,
+                                                 const double2* __restrict__ tau) {
+    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
     if (i >= N) return;
-    const int j = j0 + c;
-    double2 v = make_double2(0.0, 0.0);
-    if (c < nbb && i > j) {
-        const double2 t = tau[j];
-        if (t.x != 0.0 || t.y != 0.0) v = G[i + (size_t)ldg * j];
-    }
-    Y[i + (size_t)N * c] = v;
-}
-
-// S = Y^H Y from the split-K partials (one 64x64 block).
-__global__ __launch_bounds__(1024) void k_bt_sred(const double2* __restrict__ Spart, int splits,
-                                                  double2* __restrict__ S) {
-    for (int q = threadIdx.x; q < kBtNb * kBtNb; q += 1024) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int z = 0; z < splits; ++z) {
-            const double2 v = Spart[(size_t)z * kBtNb * kBtNb + q];
-            s.x += v.x;
-            s.y += v.y;
-        }
-        S[q] = s;
-    }
+    const double2 t = j < N - 1 ? tau[j] : make_double2(0.0, 0.0);
+    if (i <= j || (t.x == 0.0 && t.y == 0.0)) G[i + (size_t)ldg * j] = make_double2(0.0, 0.0);
 }
 
 // P = (X Y) T for H_j0 .. H_j0+nb-1 = I - Y T Y^H without forming T: T^{-1} is
@@ -1342,8 +1358,7 @@ size_t heev_bytes(int m_max, int n_max) {
     b += al((N / kHt + 2) * sizeof(double2));                   // partials of w~^H v
     b += al(N * sizeof(double2));                               // tau
     b += 2 * al(N * sizeof(double));                            // d, e
-    b += al(N * kBtNb * sizeof(double2));                       // Y
-    b += al(kBtNb * kBtNb * sizeof(double2));                   // T
+    b += al((N / kBtNb + 1) * kBtNb * kBtNb * sizeof(double2)); // S = Y^H Y of every block
     const size_t splits = (N + kSplitK - 1) / kSplitK;
     b += al(splits * std::max<size_t>(ldx, kBtNb) * kBtNb * sizeof(double2));   // split-K partials
     b += al(ldx * kBtNb * sizeof(double2));                     // P
@@ -1373,8 +1388,7 @@ void heev_carve(char* p, int m_max, int n_max, HeevWork& w) {
     w.tau = (double2*)take(N * sizeof(double2));
     w.d = (double*)take(N * sizeof(double));
     w.e = (double*)take(N * sizeof(double));
-    w.Y = (double2*)take(N * kBtNb * sizeof(double2));
-    w.Tm = (double2*)take(kBtNb * kBtNb * sizeof(double2));
+    w.Sall = (double2*)take((N / kBtNb + 1) * kBtNb * kBtNb * sizeof(double2));
     const size_t splits = (N + kSplitK - 1) / kSplitK;
     w.Cpart = (double2*)take(splits * std::max<size_t>(ldx, kBtNb) * kBtNb * sizeof(double2));
     w.P = (double2*)take(ldx * kBtNb * sizeof(double2));
@@ -1441,11 +1455,12 @@ void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
             const int j = j0 + c, len = N - j - 1;
             const int groups = (len + kHt - 1) / kHt;   // blocks of the trailing product: its partials of w~^H v
             launch_booked(pf, K_TRIDIAG, 8.0 * (double)len * len, 8.0 * (double)len * (len + 1), k_trd_hemv,
-                          dim3(groups * (groups + 1) / 2), dim3(256), 0, st, (const double2*)w.G, ldg, N, j, c,
-                          (const double*)w.part, w.VW, w.WV, w.ypart, w.tau, w.d, w.e);
-            launch_booked(pf, K_TRDAUX, 16.0 * len * 2 * c, 16.0 * len * (groups + 2.0 * c + 3.0), k_trd_fin,
+                          dim3(groups * (groups + 1) / 2), dim3(256), 0, st, (const double2*)w.G, ldg, N, j,
+                          w.ypart);
+            launch_booked(pf, K_TRDAUX, 16.0 * len * 2 * c, 16.0 * len * (groups + 2.0 * c + 5.0), k_trd_fin,
                           dim3(groups), dim3(256), 0, st, (const double2*)w.G, ldg, N, j, c, (const double*)w.part,
-                          (const double2*)w.pdot, (const double2*)w.VW, (const double2*)w.ypart, w.wt, w.palpha);
+                          (const double2*)w.pdot, w.VW, w.WV, (const double2*)w.ypart, w.wt, w.palpha, w.tau, w.d,
+                          w.e);
             launch_booked(pf, K_TRDAUX, 16.0 * len * (c + 1), 16.0 * len * (2.0 * c + 6.0), k_trd_next, dim3(kPart),
                           dim3(256), 0, st, w.G, ldg, N, j, c, (int)(c + 1 < nbb), groups, (const double2*)w.tau,
                           w.VW, w.WV, (const double2*)w.wt, (const double2*)w.palpha, w.part, w.pdot);
@@ -1495,27 +1510,35 @@ template <bool ADJ>
 static void apply_qh(double2* X, int rows, int ldx, int N, HeevWork& w, Profiler& pf, hipStream_t st) {
     const int ldg = N + 8;
     const int nblk = (N - 1 + kBtNb - 1) / kBtNb;
+    // Y of every block in G itself, and S_b = Y_b^H Y_b of all blocks at once
+    // (the blocks whose 64 columns lie inside G batched, a last partial one alone;
+    // rows above a block are zero, so every product runs over all N rows)
+    launch_booked(pf, K_BTAUX, 0.0, 8.0 * (double)N * N, k_bt_mask, dim3((N + 255) / 256, N), dim3(256), 0, st, w.G,
+                  ldg, N, (const double2*)w.tau);
+    const int nfull = std::min(nblk, N / kBtNb);
+    const size_t sS = (size_t)kBtNb * kBtNb;
+    zgemm<1, 0, 0>(kBtNb, kBtNb, N, w.G, ldg, w.G, ldg, w.Sall, kBtNb, st, nfull, 0, (size_t)ldg * kBtNb,
+                   (size_t)ldg * kBtNb, sS, &pf, K_BTAUX);
+    if (nfull < nblk) {
+        const int j0 = nfull * kBtNb, nc = N - j0;
+        zgemm<1, 0, 0>(nc, nc, N, w.G + (size_t)ldg * j0, ldg, w.G + (size_t)ldg * j0, ldg, w.Sall + sS * nfull,
+                       kBtNb, st, 1, 0, 0, 0, 0, &pf, K_BTAUX);
+    }
     for (int bk = 0; bk < nblk; ++bk) {
-        const int j0 = (ADJ ? nblk - 1 - bk : bk) * kBtNb;
+        const int b = ADJ ? nblk - 1 - bk : bk;
+        const int j0 = b * kBtNb;
         const int nbb = std::min(kBtNb, N - 1 - j0);
         const int K = N - j0 - 1;                  // rows j0+1 .. N-1 of Y
         const int splits = (K + kSplitK - 1) / kSplitK;
-        launch_booked(pf, K_BTAUX, 0.0, 32.0 * N * kBtNb, k_bt_y, dim3((N + 255) / 256, kBtNb), dim3(256), 0, st,
-                      (const double2*)w.G, ldg, N, j0, nbb, (const double2*)w.tau, w.Y);
-        const double2* Ys = w.Y + (j0 + 1);
-        // S = Y^H Y (split-K partials, then summed)
-        zgemm<1, 0, 0>(kBtNb, kBtNb, K, Ys, N, Ys, N, w.Cpart, kBtNb, st, splits, kSplitK, kSplitK, kSplitK,
-                       (size_t)kBtNb * kBtNb, &pf, K_BTAUX);
-        launch_booked(pf, K_BTAUX, 0.0, 16.0 * kBtNb * kBtNb * (splits + 1), k_bt_sred, dim3(1), dim3(1024), 0, st,
-                      (const double2*)w.Cpart, splits, w.Tm);
+        const double2* Ys = w.G + (j0 + 1) + (size_t)ldg * j0;
         // X Y (split-K), then P = (X Y) T (or T^H) by row-wise substitution
-        zgemm<0, 0, 0>(rows, kBtNb, K, X + (size_t)ldx * (j0 + 1), ldx, Ys, N, w.Cpart, rows, st, splits, kSplitK,
+        zgemm<0, 0, 0>(rows, nbb, K, X + (size_t)ldx * (j0 + 1), ldx, Ys, ldg, w.Cpart, rows, st, splits, kSplitK,
                        (size_t)kSplitK * ldx, kSplitK, (size_t)rows * kBtNb, &pf, K_BACK);
         launch_booked(pf, K_BTAUX, 8.0 * rows * kBtNb * kBtNb / 2, 16.0 * rows * kBtNb * (splits + 1),
                       k_bt_solve<ADJ>, dim3((rows + 3) / 4), dim3(256), 0, st, (const double2*)w.Cpart, splits, rows,
-                      (const double2*)w.Tm, (const double2*)w.tau, j0, nbb, w.P);
+                      (const double2*)(w.Sall + sS * b), (const double2*)w.tau, j0, nbb, w.P);
         // X[:, j0+1:] -= P Y^H
-        zgemm<0, 1, 1>(rows, K, kBtNb, w.P, rows, Ys, N, X + (size_t)ldx * (j0 + 1), ldx, st, 1, 0, 0, 0, 0, &pf,
+        zgemm<0, 1, 1>(rows, K, nbb, w.P, rows, Ys, ldg, X + (size_t)ldx * (j0 + 1), ldx, st, 1, 0, 0, 0, 0, &pf,
                        K_BACK);
     }
 }
