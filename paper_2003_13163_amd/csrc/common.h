@@ -156,9 +156,9 @@ struct HeevWork {
     double2* G;                       // Gram (stride N + 8), then the reflectors below its diagonal
     double2 *VW, *WV;                 // panel [V W] and [W V], N x 2 kTrdNb each (stride N)
     double2* ypart;                   // slots of the trailing product, (N / 64 + 2) x N (stride N)
-    double2 *wt, *tau;
+    double2 *upart, *tau;             // tiles' parts of u^H G u; reflector scalars
     double* part;                     // partial sums of ||column||^2 (row chunks)
-    double2 *pdot, *palpha;           // partial sums of the panel dots and of w~^H v
+    double2* pdot;                    // partial sums of the panel dots
     double *d, *e;                    // tridiagonal
     double2 *Sall, *Cpart, *P;        // back-transformation: Y^H Y per block, split-K partials, (X Y) T
     double *Z, *Z2, *U;               // eigenvectors of T and merge scratch (N x N, stride N)

@@ -99,8 +99,9 @@ void launch_booked(Profiler& pf, int cls, double fl, double by, K kernel, dim3 g
 
 // ------------------------------------------------------------ complex GEMM
 // C = op(A) op(B) (MODE 0) or C -= op(A) op(B) (MODE 1); MODE 2 and 3 are the
-// same on the 64x64 tiles on or below the diagonal only (Hermitian results of
-// which only the lower triangle is used), FP64 complex, 64x64
+// same on the 64x64 tiles on or below the diagonal only, MODE 4 and 5 on those
+// on or above it (Hermitian results of which one triangle is used), FP64
+// complex, 64x64
 // tiles, 4 waves of 2x2 16x16 MFMA tiles.  blockIdx.z selects a batch entry:
 // the operands are offset by z times their strides and, with kchunk > 0, the
 // entry covers K range [z*kchunk, min(K, (z+1)*kchunk)) (split-K partials).
@@ -121,6 +122,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, int kchunk, 
     const int wm = wave & 1, wn = wave >> 1;
     const int m0 = blockIdx.x * ZBM, n0 = blockIdx.y * ZBN;
     if ((MODE & 2) && m0 < n0) return;   // Hermitian result: lower tiles only
+    if ((MODE & 4) && m0 > n0) return;   // upper tiles only
     d4 accR[2][2], accI[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -204,7 +206,7 @@ void zgemm(int M, int N, int K, const double2* A, int lda, const double2* B, int
         hipExtLaunchKernelGGL((k_zgemm<OPA, OPB, MODE>), grid, dim3(256), 0, st, a, e, 0, M, N, K, kchunk, A, lda,
                               sA, B, ldb, sB, C, ldc, sC);
         const double kk = kchunk > 0 ? (double)K : (double)K * batches;
-        const double part = (MODE & 2) ? 0.5 : 1.0;   // lower tiles only
+        const double part = (MODE & 6) ? 0.5 : 1.0;   // one triangle's tiles only
         pf->record(cls, a, e, part * 8.0 * M * N * kk,
                    16.0 * ((double)M * kk + (double)N * kk + part * ((MODE & 1) + 1.0) * M * N * batches));
     } else {
@@ -365,7 +367,10 @@ __global__ __launch_bounds__(256) void k_trd_colnorm(const double2* __restrict__
 //                  ypart: block K's rows collect slot J from tile (K, J), slot
 //                  I from tile (I, K), and slots K and nt from the diagonal
 //                  tile (its strict lower part both ways, the real diagonal
-//                  once), nt + 1 slots in all, summed by k_trd_fin.
+//                  once), nt + 1 slots in all, summed by k_trd_step;
+//   per tile       its part of u^H G0 u (u_I^H G_IJ u_J + u_J^H G_IJ^H u_I,
+//                  the diagonal tile's lower part with its real diagonal) in
+//                  upart[tile].
 constexpr int kHt = 64;   // tile edge of the trailing product
 
 __device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
@@ -377,9 +382,10 @@ __device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
 }
 
 __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G, int ldg, int N, int j,
-                                                  double2* __restrict__ ypart) {
+                                                  double2* __restrict__ ypart, double2* __restrict__ upart) {
     __shared__ double2 uI[kHt], uJ[kHt];
     __shared__ double2 red[4][kHt];
+    __shared__ double2 ured[4];
     const int len = N - j - 1;
     const int nt = (len + kHt - 1) / kHt;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -448,10 +454,27 @@ __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G,
             cacc[cc].y += __shfl_xor(cacc[cc].y, o, 64);
         }
     const size_t ldy = (size_t)N;
+    double2 uu = make_double2(0.0, 0.0);   // this lane's part of u^H G0 u
     if (q == 0) {
 #pragma unroll
-        for (int s8 = 0; s8 < 8; ++s8) red[wave][8 * s8 + p] = racc[s8];
+        for (int s8 = 0; s8 < 8; ++s8) {
+            red[wave][8 * s8 + p] = racc[s8];
+            const double2 t = zcmul(uI[8 * s8 + p], racc[s8]);
+            uu.x += t.x;
+            uu.y += t.y;
+        }
     }
+    if (p == 0) {
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const double2 t = zcmul(uJ[16 * wave + 8 * cc + q], cacc[cc]);
+            uu.x += t.x;
+            uu.y += t.y;
+        }
+    }
+    uu.x = wave_sum(uu.x);
+    uu.y = wave_sum(uu.y);
+    if (lane == 0) ured[wave] = uu;
     if (p == 0) {
         const int slot = I == J ? nt : I;
 #pragma unroll
@@ -467,228 +490,239 @@ __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G,
         for (int w4 = 1; w4 < 4; ++w4) { sr.x += red[w4][tid].x; sr.y += red[w4][tid].y; }
         ypart[(size_t)J * ldy + kHt * I + tid] = sr;
     }
+    if (tid == 0) {
+        double2 su = ured[0];
+        for (int w4 = 1; w4 < 4; ++w4) { su.x += ured[w4].x; su.y += ured[w4].y; }
+        upart[blockIdx.x] = su;
+    }
 }
 
-// Finish of column j, one work-group per 64-row block K of the trailing rows:
-//   reflector      scalars from alpha = G[j+1, j] and the partial sums of
-//                  ||G[j+2:, j]||^2 (the same butterfly in every wave);
-//   y              = G[j+1:, j+1] + scale (the block's nt + 1 slots, summed in
-//                  fixed order) - (V p + W q), p = W^H v and q = V^H v from the
-//                  partial sums the previous kernel left;
-//   out            w~_i = tau_j y_i, the block's partial sum of w~^H v, and v
-//                  into the panel buffers (work-group 0 also the rows above the
-//                  trailing part, tau_j, e_j and d_j).
-// Every load that depends on nothing computed here is issued first.
-constexpr int kFinSlots = (64 * kPart / kHt + 1 + 3) / 4;   // slots per thread (nt + 1 <= 65)
+// The rest of column j in one kernel over kPart row chunks of all N rows, every
+// work-group forming the column's scalars itself (the same sums in the same
+// order in each):
+//   reflector      tau_j, scale s, beta from alpha = G[j+1, j] and the partial
+//                  sums of ||G[j+2:, j]||^2; v = e_0 + s u;
+//   panel dots     p = W^H v, q = V^H v from the partial sums of W^H x and
+//                  V^H x the previous column left;
+//   y              y_i = G[i, j+1] + s (G0 u)_i - (V p + W q)_i, (G0 u)_i the
+//                  sum of row i's slots of the tile product;
+//   alpha          = -|tau|^2 (v^H G_eff v) / 2 (real, G_eff Hermitian) with
+//                  v^H G_eff v = G0[0, 0] + 2 Re(s (G0 u)_0) + |s|^2 u^H G0 u
+//                  - 2 Re(q^H p), u^H G0 u from the tiles' partial sums;
+//   panel column   w = tau y + alpha v into the panel buffers (zero above row
+//                  j+1), v into them and below the diagonal of G (G[j+1, j] =
+//                  1 for the back-transformation);
+// and, if the panel continues, column j+1 brought up to date,
+// G[j+1:, j+1] -= V conj(W[j+1, :]) + W conj(V[j+1, :]) over the panel's
+// first c+1 columns, with the partial sums its reflector needs:
+// ||G[j+3:, j+1]||^2, W^H G[j+3:, j+1] and V^H G[j+3:, j+1].
+// Every global load is issued at the start (the chunk's panel rows go to LDS),
+// so the kernel waits on memory once; the rest is LDS work between barriers.
+constexpr int kStepG = 8;                                  // row groups (waves) of k_trd_step
+constexpr int kStepSlots = (64 * kPart / kHt + 1 + kStepG - 1) / kStepG;   // slots per thread (nt + 1 <= 65)
+constexpr int kUpartPer = 5;   // tile partials per thread: 512 * 5 >= 64 * 65 / 2
 
-__global__ __launch_bounds__(256) void k_trd_fin(const double2* __restrict__ G, int ldg, int N, int j, int c,
-                                                 const double* __restrict__ part,
-                                                 const double2* __restrict__ pdot, double2* __restrict__ VW,
-                                                 double2* __restrict__ WV, const double2* __restrict__ ypart,
-                                                 double2* __restrict__ wt, double2* __restrict__ palpha,
-                                                 double2* __restrict__ tau, double* __restrict__ d,
-                                                 double* __restrict__ e) {
-    __shared__ double2 red[4][kHt];
-    __shared__ double2 pq[2 * kTrdNb];
+__global__ __launch_bounds__(64 * kStepG) void k_trd_step(double2* __restrict__ G, int ldg, int N, int j, int c,
+                                                  int update_next, const double2* __restrict__ ypart,
+                                                  const double2* __restrict__ upart, double2* __restrict__ VW,
+                                                  double2* __restrict__ WV, double* __restrict__ part,
+                                                  double2* __restrict__ pdot, double2* __restrict__ tau,
+                                                  double* __restrict__ d, double* __restrict__ e) {
+    __shared__ double2 Vc[kTrdNb][65];    // V[a + r, q] as Vc[q][r] (q < c)
+    __shared__ double2 Wc[kTrdNb][65];
+    __shared__ double2 red4[kStepG][64];
+    __shared__ double2 row1[2 * kTrdNb];  // V[j+1, q], W[j+1, q] for q < c
+    __shared__ double2 pq[2 * kTrdNb];    // p, then q
+    __shared__ double2 sv[64], sw[64];    // v and w on this chunk's rows
+    __shared__ double2 arow[64];          // updated column j+1 on this chunk's rows (>= j+3; else 0)
+    __shared__ double ured[kStepG];
+    __shared__ double2 sy0;               // (G0 u)_0
     const double2 zero = make_double2(0.0, 0.0);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int len = N - j - 1;
     const int nt = (len + kHt - 1) / kHt;
-    const int K = blockIdx.x;
-    const int nr = min(kHt, len - kHt * K);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r = tid & 63, g = tid >> 6;     // row of the block, slot / panel-column group
-    const int row = kHt * K + r;              // trailing row (G row j + 1 + row)
-    const int i = j + 1 + row;
-    const bool live = r < nr;
+    const int ntiles = nt * (nt + 1) / 2;
+    int a, b;
+    part_rows(0, N, a, b);
+    const int nr = b - a;                 // <= 64
+    const int r = t & 63, g = t >> 6;     // (row, group)
+    const int i = a + r;
+    const bool trow = r < nr && i > j;    // a trailing row
+    const int tr = i - j - 1;             // its index in the trailing part
     const size_t ldy = (size_t)N;
-    // ---- independent loads
-    double2 sl[kFinSlots];
+    // ---- global loads
+    double2 sl[kStepSlots];
 #pragma unroll
-    for (int k = 0; k < kFinSlots; ++k) {
-        const int s = g + 4 * k;
+    for (int k = 0; k < kStepSlots; ++k) {
+        const int s = g + kStepG * k;
         sl[k] = zero;
-        if (live && s <= nt) sl[k] = ypart[(size_t)s * ldy + row];
+        if (trow && s <= nt) sl[k] = ypart[(size_t)s * ldy + tr];
     }
-    double2 cv[kTrdNb / 4], cw[kTrdNb / 4];   // V[i, q], W[i, q] for q = g + 4 k < c
+    // panel rows of the chunk, columns q = g + kStepG k: loaded unconditionally
+    // from clamped (in-bounds) addresses so that every load is in flight at once
+    double2 pv[kTrdNb / kStepG], pw[kTrdNb / kStepG];
+    const int ic = min(i, N - 1);
 #pragma unroll
-    for (int k = 0; k < kTrdNb / 4; ++k) {
-        const int qq = g + 4 * k;
-        cv[k] = zero;
-        cw[k] = zero;
-        if (live && qq < c) {
-            cv[k] = VW[i + (size_t)N * qq];
-            cw[k] = VW[i + (size_t)N * (kTrdNb + qq)];
+    for (int k = 0; k < kTrdNb / kStepG; ++k) {
+        const int q = g + kStepG * k;
+        pv[k] = VW[ic + (size_t)N * q];
+        pw[k] = VW[ic + (size_t)N * (kTrdNb + q)];
+    }
+    // pdot: dot dd = t / 8 (q = dd % c, from W if dd < c else V) summed over the
+    // partials t % 8 + 8 k by this thread
+    const int dd = t >> 3, dsub = t & 7;
+    double2 pd[kPart / 8];
+#pragma unroll
+    for (int k = 0; k < kPart / 8; ++k) {
+        pd[k] = zero;
+        if (dd < 2 * c) {
+            const int qq = dd % c, isv = dd / c;
+            pd[k] = pdot[(size_t)(dsub + 8 * k) * 2 * kTrdNb + isv * kTrdNb + qq];
         }
     }
-    double2 g0 = zero, xi = zero;
-    if (live && g == 0) {
+    double upv[kUpartPer];
+#pragma unroll
+    for (int k = 0; k < kUpartPer; ++k) upv[k] = upart[min(t + 64 * kStepG * k, ntiles - 1)].x;
+    double2 g0 = zero, xi = zero;          // G[i, j+1] (panel start), G[i, j]
+    if (trow && g == 0) {
         g0 = G[i + (size_t)ldg * (j + 1)];
-        if (row == 0) g0.y = 0.0;             // the diagonal is real
         xi = G[i + (size_t)ldg * j];
     }
+    double2 y0s = zero;
+    if (wave == 0) {
+        if (lane <= nt) y0s = ypart[(size_t)lane * ldy];
+        if (lane == 0 && nt == 64) { const double2 v = ypart[(size_t)64 * ldy]; y0s.x += v.x; y0s.y += v.y; }
+    }
+    double2 r1 = zero, rw = zero;          // row j+1 of the panel; this thread's dot's entry of it
+    if (t < 2 * kTrdNb && (t % kTrdNb) < c) r1 = VW[(j + 1) + (size_t)N * t];
+    if (dsub == 0 && dd < 2 * c)
+        rw = VW[(j + 1) + (size_t)N * ((dd / c ? 0 : kTrdNb) + dd % c)];
     const double pt = part[lane];
     const double2 alpha = G[(j + 1) + (size_t)ldg * j];
-    // ---- reflector scalars
+    const double g00 = G[(j + 1) + (size_t)ldg * (j + 1)].x;
+    // ---- reflector scalars, panel dots, (G0 u)_0 and u^H G0 u
+#pragma unroll
+    for (int k = 0; k < kTrdNb / kStepG; ++k) {
+        const int q = g + kStepG * k;
+        double2 v = pv[k], w = pw[k];
+        if (r >= nr) { v = make_double2(0.0, 0.0); w = v; }
+        Vc[q][r] = v;
+        Wc[q][r] = w;
+    }
+    double up = 0.0;
+#pragma unroll
+    for (int k = 0; k < kUpartPer; ++k)
+        if (t + 64 * kStepG * k < ntiles) up += upv[k];
     const House h = house_scalars(alpha, wave_sum(pt));
-    // p_q = conj(W[j+1, q]) + scale (W^H x)_q from the kPart partial sums of
-    // W^H x (likewise q with V): one dot per wave at a time
-    for (int dd = wave; dd < 2 * c; dd += 4) {
-        const int qq = dd % c, isv = dd / c;
-        const double2 t = pdot[(size_t)lane * 2 * kTrdNb + isv * kTrdNb + qq];
-        const double sr = wave_sum(t.x), si = wave_sum(t.y);
-        if (lane == 0) {
-            const double2 rw = VW[(j + 1) + (size_t)N * ((isv ? 0 : kTrdNb) + qq)];
-            const double2 sc = zmul(h.scale, make_double2(sr, si));
+    {
+        double2 sd = zero;
+#pragma unroll
+        for (int k = 0; k < kPart / 8; ++k) { sd.x += pd[k].x; sd.y += pd[k].y; }
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+            sd.x += __shfl_xor(sd.x, o, 64);
+            sd.y += __shfl_xor(sd.y, o, 64);
+        }
+        if (t < 2 * kTrdNb) row1[t] = r1;
+        if (dsub == 0 && dd < 2 * c) {
+            // p_q = conj(W[j+1, q]) + s (W^H x)_q (dd < c), q_q likewise with V
+            const int qq = dd % c, isv = dd / c;
+            const double2 sc = zmul(h.scale, sd);
             pq[isv * kTrdNb + qq] = make_double2(rw.x + sc.x, -rw.y + sc.y);
         }
     }
-    __syncthreads();
-    // ---- this thread's share: scale (its slots) - (its panel columns of V p + W q)
-    double2 acc = zero;
-#pragma unroll
-    for (int k = 0; k < kFinSlots; ++k) { acc.x += sl[k].x; acc.y += sl[k].y; }
-    acc = zmul(h.scale, acc);
-#pragma unroll
-    for (int k = 0; k < kTrdNb / 4; ++k) {
-        const int qq = g + 4 * k;
-        if (qq < c) {
-            const double2 t1 = zmul(cv[k], pq[qq]);
-            const double2 t2 = zmul(cw[k], pq[kTrdNb + qq]);
-            acc.x -= t1.x + t2.x;
-            acc.y -= t1.y + t2.y;
-        }
+    if (wave == 0) {
+        const double2 y0 = make_double2(wave_sum(y0s.x), wave_sum(y0s.y));
+        if (lane == 0) sy0 = y0;
     }
-    red[g][r] = acc;
+    up = wave_sum(up);
+    if (lane == 0) ured[wave] = up;
     __syncthreads();
-    if (tid < 64) {
-        double2 contrib = zero;
-        if (live) {
-            double sr = g0.x, si = g0.y;
+    // ---- column scalars (every thread alike)
+    double uGu = ured[0];
 #pragma unroll
-            for (int w4 = 0; w4 < 4; ++w4) { sr += red[w4][tid].x; si += red[w4][tid].y; }
-            const double2 w = zmul(h.tau, make_double2(sr, si));
-            const double2 vi = row == 0 ? make_double2(1.0, 0.0) : zmul(xi, h.scale);
-            wt[i] = w;
-            VW[i + (size_t)N * c] = vi;
-            WV[i + (size_t)N * (kTrdNb + c)] = vi;
-            contrib = zcmul(w, vi);
-        }
-        contrib.x = wave_sum(contrib.x);
-        contrib.y = wave_sum(contrib.y);
-        if (tid == 0) palpha[K] = contrib;
+    for (int w8 = 1; w8 < kStepG; ++w8) uGu += ured[w8];
+    double corr1r = 0.0, corr1i = 0.0, qpr = 0.0;
+    for (int qq = 0; qq < c; ++qq) {
+        const double2 t1 = zmul(row1[qq], pq[qq]);
+        const double2 t2 = zmul(row1[kTrdNb + qq], pq[kTrdNb + qq]);
+        corr1r += t1.x + t2.x;
+        corr1i += t1.y + t2.y;
+        qpr += pq[kTrdNb + qq].x * pq[qq].x + pq[kTrdNb + qq].y * pq[qq].y;   // Re(conj(q) p)
     }
-    if (K == 0) {
-        // rows 0 .. j of the panel's column c are zero; the reflector's scalars
-        for (int rr = tid; rr <= j; rr += 256) {
-            VW[rr + (size_t)N * c] = zero;
-            WV[rr + (size_t)N * (kTrdNb + c)] = zero;
+    const double2 y0 = sy0;
+    const double2 sy = zmul(h.scale, y0);
+    const double s2 = h.scale.x * h.scale.x + h.scale.y * h.scale.y;
+    const double vgv = g00 + 2.0 * sy.x + s2 * uGu - 2.0 * qpr;
+    const double t2n = h.tau.x * h.tau.x + h.tau.y * h.tau.y;
+    const double al = -0.5 * t2n * vgv;
+    const double2 y1 = make_double2(g00 + sy.x - corr1r, sy.y - corr1i);   // y_{j+1}
+    const double2 w1t = zmul(h.tau, y1);
+    const double2 wj1 = make_double2(w1t.x + al, w1t.y);                     // W[j+1, c] (v_{j+1} = 1)
+    // ---- this thread's share of y_i: s (its slots) - (its panel columns of V p + W q)
+    {
+        double2 acc = zero;
+#pragma unroll
+        for (int k = 0; k < kStepSlots; ++k) { acc.x += sl[k].x; acc.y += sl[k].y; }
+        acc = zmul(h.scale, acc);
+#pragma unroll
+        for (int k = 0; k < kTrdNb / kStepG; ++k) {
+            const int qq = g + kStepG * k;
+            if (qq < c) {
+                const double2 t1 = zmul(Vc[qq][r], pq[qq]);
+                const double2 t2 = zmul(Wc[qq][r], pq[kTrdNb + qq]);
+                acc.x -= t1.x + t2.x;
+                acc.y -= t1.y + t2.y;
+            }
         }
-        if (tid == 0) {
+        red4[g][r] = acc;
+    }
+    __syncthreads();
+    if (t < 64) {
+        double2 v = zero, w = zero;
+        if (trow) {
+            if (tr == 0) {
+                v = make_double2(1.0, 0.0);
+                w = wj1;
+            } else {
+                double sr = g0.x, si = g0.y;
+#pragma unroll
+                for (int w8 = 0; w8 < kStepG; ++w8) { sr += red4[w8][t].x; si += red4[w8][t].y; }
+                v = zmul(xi, h.scale);
+                const double2 wt = zmul(h.tau, make_double2(sr, si));
+                w = make_double2(wt.x + al * v.x, wt.y + al * v.y);
+            }
+            G[i + (size_t)ldg * j] = v;
+        }
+        if (r < nr) {
+            VW[i + (size_t)N * c] = v;
+            WV[i + (size_t)N * (kTrdNb + c)] = v;
+            VW[i + (size_t)N * (kTrdNb + c)] = w;
+            WV[i + (size_t)N * c] = w;
+        }
+        sv[t] = v;
+        sw[t] = w;
+        if (blockIdx.x == 0 && t == 0) {
             tau[j] = h.tau;
             e[j] = h.beta;
             d[j] = G[j + (size_t)ldg * j].x;
         }
     }
-}
-
-// w = w~ + alpha v with alpha = -tau_j (w~^H v) / 2 into the panel buffers
-// (zero above row j+1), the reflector below the diagonal of G (G[j+1, j] = 1
-// for the back-transformation); if the panel continues, column j+1 is brought up to
-// date, G[j+1:, j+1] -= V conj(W[j+1, :]) + W conj(V[j+1, :]), and the
-// partial sums its reflector needs are formed: ||G[j+3:, j+1]||^2, and
-// W^H G[j+3:, j+1], V^H G[j+3:, j+1] over the panel's first c+1 columns.
-__global__ __launch_bounds__(256) void k_trd_next(double2* __restrict__ G, int ldg, int N, int j, int c,
-                                                  int update_next, int gemv_groups,
-                                                  const double2* __restrict__ tau, double2* __restrict__ VW,
-                                                  double2* __restrict__ WV, const double2* __restrict__ wt,
-                                                  const double2* __restrict__ palpha, double* __restrict__ part,
-                                                  double2* __restrict__ pdot) {
-    __shared__ double2 sw[64];            // new W column on this chunk's rows
-    __shared__ double2 arow[64];          // updated column j+1 on this chunk's rows (>= j+3; else 0)
-    __shared__ double2 red4[4][64];
-    __shared__ double2 row1[2 * kTrdNb];  // V[j+1, q], W[j+1, q] for q < c
-    const double2 zero = make_double2(0.0, 0.0);
-    const int t = threadIdx.x, lane = t & 63;
-    int a, b;
-    part_rows(0, N, a, b);
-    const int nr = b - a;                 // <= 64
-    const int r = t & 63, g = t >> 6;     // (row, group) of the update and the dots
-    const int i = a + r;
-    // Loads that depend on nothing computed here go first.
-    double2 v_own = zero, wt_own = zero;
-    if (t < nr && a + t > j) {
-        v_own = VW[(a + t) + (size_t)N * c];
-        wt_own = wt[a + t];
-    }
-    const bool urow = update_next && r < nr && i >= j + 1;
-    double2 gcol = zero, vic = zero, wj1 = zero;
-    double2 uv[8], uw[8];                 // panel columns q = g + 4 k < c of the update
-#pragma unroll
-    for (int k = 0; k < 8; ++k) { uv[k] = zero; uw[k] = zero; }
-    if (update_next) {
-        wj1 = wt[j + 1];
-        if (t < 2 * kTrdNb && (t % kTrdNb) < c) row1[t] = VW[(j + 1) + (size_t)N * t];
-        if (urow) {
-            if (g == 0) gcol = G[i + (size_t)ldg * (j + 1)];
-            vic = VW[i + (size_t)N * c];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int q = g + 4 * k;
-                if (q < c) {
-                    uv[k] = VW[i + (size_t)N * q];
-                    uw[k] = VW[i + (size_t)N * (kTrdNb + q)];
-                }
-            }
-        }
-    }
-    // w~^H v from the trailing product's partials (at most 64): every wave sums
-    // them with the same butterfly
-    double2 pa = zero;
-    if (lane < gemv_groups) pa = palpha[lane];
-    pa.x = wave_sum(pa.x);
-    pa.y = wave_sum(pa.y);
-    const double2 ts = zmul(tau[j], pa);
-    const double2 al = make_double2(-0.5 * ts.x, -0.5 * ts.y);
-    if (t < nr) {
-        double2 w = zero;
-        if (a + t > j) {
-            const double2 av = zmul(al, v_own);
-            w = make_double2(wt_own.x + av.x, wt_own.y + av.y);
-            G[(a + t) + (size_t)ldg * j] = v_own;
-        }
-        VW[(a + t) + (size_t)N * (kTrdNb + c)] = w;
-        WV[(a + t) + (size_t)N * c] = w;
-        sw[t] = w;
-    }
     if (!update_next) return;
     __syncthreads();
-    // dot operands: V columns 0..c and W columns 0..c (column c written above)
-    const int nq = c + 1;
-    double2 dcol[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int rr = g + 4 * k;
-        dcol[k] = zero;
-        if (r < 2 * nq && rr < nr) {
-            const int q = r % nq, isv = r / nq;
-            dcol[k] = VW[(a + rr) + (size_t)N * ((isv ? 0 : kTrdNb) + q)];
-        }
-    }
-    // column j+1 update: thread (row r, group g) sums the panel columns q = g, g+4, ..;
-    // W[j+1, c] = w~[j+1] + alpha (v[j+1] = 1)
-    wj1.x += al.x;
-    wj1.y += al.y;
+    // column j+1 update: thread (row r, group g) sums the panel columns q = g, g+4, ..
     double2 acc = zero;
+    const bool urow = r < nr && i >= j + 1;
     if (urow) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int q = g + 4 * k;
+        for (int k = 0; k <= kTrdNb / kStepG; ++k) {   // q = g + kStepG k <= c <= 31
+            const int q = g + kStepG * k;
             if (q < c) {
-                const double2 t1 = zmulc(uv[k], row1[kTrdNb + q]), t2 = zmulc(uw[k], row1[q]);
+                const double2 t1 = zmulc(Vc[q][r], row1[kTrdNb + q]), t2 = zmulc(Wc[q][r], row1[q]);
                 acc.x += t1.x + t2.x;
                 acc.y += t1.y + t2.y;
             } else if (q == c) {
-                const double2 t1 = zmulc(vic, wj1), t2 = zmulc(sw[r], make_double2(1.0, 0.0));
+                const double2 t1 = zmulc(sv[r], wj1), t2 = sw[r];
                 acc.x += t1.x + t2.x;
                 acc.y += t1.y + t2.y;
             }
@@ -700,8 +734,8 @@ __global__ __launch_bounds__(256) void k_trd_next(double2* __restrict__ G, int l
         double nrm = 0.0;
         double2 gv = zero;
         if (urow) {
-            gv = gcol;
-            for (int q4 = 0; q4 < 4; ++q4) { gv.x -= red4[q4][t].x; gv.y -= red4[q4][t].y; }
+            gv = g0;
+            for (int q8 = 0; q8 < kStepG; ++q8) { gv.x -= red4[q8][t].x; gv.y -= red4[q8][t].y; }
             G[i + (size_t)ldg * (j + 1)] = gv;
             if (i >= j + 3) nrm = gv.x * gv.x + gv.y * gv.y;
         }
@@ -713,14 +747,19 @@ __global__ __launch_bounds__(256) void k_trd_next(double2* __restrict__ G, int l
     }
     __syncthreads();
     // dots over this chunk: thread (dot r, row group g) sums conj(W[i, q]) a_i
-    // (r < c+1) or conj(V[i, q]) a_i (r >= c+1) over rows a + g, a + g + 4, ..
+    // (r < c+1) or conj(V[i, q]) a_i (r >= c+1) over rows a + g, a + g + kStepG, ..
+    const int nq = c + 1;
     double2 dacc = zero;
     if (r < 2 * nq) {
+        const int q = r % nq, isv = r / nq;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int rr = g + 4 * k;
+        for (int k = 0; k < 64 / kStepG; ++k) {
+            const int rr = g + kStepG * k;
             if (rr < nr) {
-                const double2 p = zcmul(dcol[k], arow[rr]);
+                double2 cval;
+                if (q == c) cval = isv ? sv[rr] : sw[rr];
+                else cval = isv ? Vc[q][rr] : Wc[q][rr];
+                const double2 p = zcmul(cval, arow[rr]);
                 dacc.x += p.x;
                 dacc.y += p.y;
             }
@@ -731,7 +770,7 @@ __global__ __launch_bounds__(256) void k_trd_next(double2* __restrict__ G, int l
     if (t < 2 * nq) {
         const int q = t % nq, isv = t / nq;
         double2 sum = zero;
-        for (int q4 = 0; q4 < 4; ++q4) { sum.x += red4[q4][t].x; sum.y += red4[q4][t].y; }
+        for (int q8 = 0; q8 < kStepG; ++q8) { sum.x += red4[q8][t].x; sum.y += red4[q8][t].y; }
         pdot[(size_t)blockIdx.x * 2 * kTrdNb + isv * kTrdNb + q] = sum;
     }
 }
@@ -1352,10 +1391,9 @@ size_t heev_bytes(int m_max, int n_max) {
     b += al((N + 8) * N * sizeof(double2));                     // G
     b += 2 * al(N * 2 * kTrdNb * sizeof(double2));              // VW, WV
     b += al((N / kHt + 2) * N * sizeof(double2));               // slots of the trailing product
-    b += al(N * sizeof(double2));                               // wt
+    b += al((size_t)(N / kHt + 1) * (N / kHt + 2) / 2 * sizeof(double2));   // tiles' parts of u^H G u
     b += al(kPart * sizeof(double));                            // norm partials
     b += al((size_t)kPart * 2 * kTrdNb * sizeof(double2));      // dot partials
-    b += al((N / kHt + 2) * sizeof(double2));                   // partials of w~^H v
     b += al(N * sizeof(double2));                               // tau
     b += 2 * al(N * sizeof(double));                            // d, e
     b += al((N / kBtNb + 1) * kBtNb * kBtNb * sizeof(double2)); // S = Y^H Y of every block
@@ -1381,10 +1419,9 @@ void heev_carve(char* p, int m_max, int n_max, HeevWork& w) {
     w.VW = (double2*)take(N * 2 * kTrdNb * sizeof(double2));
     w.WV = (double2*)take(N * 2 * kTrdNb * sizeof(double2));
     w.ypart = (double2*)take((N / kHt + 2) * N * sizeof(double2));
-    w.wt = (double2*)take(N * sizeof(double2));
+    w.upart = (double2*)take((size_t)(N / kHt + 1) * (N / kHt + 2) / 2 * sizeof(double2));
     w.part = (double*)take(kPart * sizeof(double));
     w.pdot = (double2*)take((size_t)kPart * 2 * kTrdNb * sizeof(double2));
-    w.palpha = (double2*)take((N / kHt + 2) * sizeof(double2));
     w.tau = (double2*)take(N * sizeof(double2));
     w.d = (double*)take(N * sizeof(double));
     w.e = (double*)take(N * sizeof(double));
@@ -1453,17 +1490,15 @@ void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
                       (const double2*)w.G, ldg, N, j0, w.part);
         for (int c = 0; c < nbb; ++c) {
             const int j = j0 + c, len = N - j - 1;
-            const int groups = (len + kHt - 1) / kHt;   // blocks of the trailing product: its partials of w~^H v
+            const int groups = (len + kHt - 1) / kHt;   // 64-row blocks of the trailing part
+            const int ntiles = groups * (groups + 1) / 2;
             launch_booked(pf, K_TRIDIAG, 8.0 * (double)len * len, 8.0 * (double)len * (len + 1), k_trd_hemv,
-                          dim3(groups * (groups + 1) / 2), dim3(256), 0, st, (const double2*)w.G, ldg, N, j,
-                          w.ypart);
-            launch_booked(pf, K_TRDAUX, 16.0 * len * 2 * c, 16.0 * len * (groups + 2.0 * c + 5.0), k_trd_fin,
-                          dim3(groups), dim3(256), 0, st, (const double2*)w.G, ldg, N, j, c, (const double*)w.part,
-                          (const double2*)w.pdot, w.VW, w.WV, (const double2*)w.ypart, w.wt, w.palpha, w.tau, w.d,
+                          dim3(ntiles), dim3(256), 0, st, (const double2*)w.G, ldg, N, j, w.ypart, w.upart);
+            launch_booked(pf, K_TRDAUX, 16.0 * len * (3.0 * c + 4.0),
+                          16.0 * ((double)len * (groups + 1) / kPart * kPart + len * (4.0 * c + 6.0) + ntiles),
+                          k_trd_step, dim3(kPart), dim3(64 * kStepG), 0, st, w.G, ldg, N, j, c, (int)(c + 1 < nbb),
+                          (const double2*)w.ypart, (const double2*)w.upart, w.VW, w.WV, w.part, w.pdot, w.tau, w.d,
                           w.e);
-            launch_booked(pf, K_TRDAUX, 16.0 * len * (c + 1), 16.0 * len * (2.0 * c + 6.0), k_trd_next, dim3(kPart),
-                          dim3(256), 0, st, w.G, ldg, N, j, c, (int)(c + 1 < nbb), groups, (const double2*)w.tau,
-                          w.VW, w.WV, (const double2*)w.wt, (const double2*)w.palpha, w.part, w.pdot);
         }
         const int k0 = j0 + nbb;
         zgemm<0, 1, 3>(N - k0, N - k0, 2 * kTrdNb, w.VW + k0, N, w.WV + k0, N, w.G + k0 + (size_t)ldg * k0, ldg,
@@ -1687,7 +1722,8 @@ bool cholqr3(const C2<T>* A, int m, int r, int lda, C2<T>* Q, int ldq, C2<T>* R,
         trsm(c0 + h, nc - h);
     };
     auto pass_run = [&](int kind) {
-        zgemm<1, 0, 0>(r, r, m, Ad, ldx, Ad, ldx, w.G, ldg, st, 1, 0, 0, 0, 0, &pf, K_QR);
+        // the Cholesky factorisation reads the upper triangle only
+        zgemm<1, 0, 4>(r, r, m, Ad, ldx, Ad, ldx, w.G, ldg, st, 1, 0, 0, 0, 0, &pf, K_QR);
         if (kind == kQrShifted)
             launch_booked(pf, K_QR, 0.0, 16.0 * r, k_qr_shift, dim3(1), dim3(256), 0, st, w.G, ldg, r,
                           11.0 * ((double)m * r + (double)r * (r + 1)) * u, info);
@@ -1702,7 +1738,7 @@ bool cholqr3(const C2<T>* A, int m, int r, int lda, C2<T>* Q, int ldq, C2<T>* R,
                 launch_booked(pf, K_QR, 4.0 * kb * kb * rest, 32.0 * kb * rest, k_chol_row, dim3((rest + 3) / 4),
                               dim3(256), 0, st, w.G, ldg, k0, kb, r);
                 double2* Rrow = w.G + k0 + (size_t)ldg * (k0 + kb);
-                zgemm<1, 0, 1>(rest, rest, kb, Rrow, ldg, Rrow, ldg, w.G + (k0 + kb) + (size_t)ldg * (k0 + kb), ldg,
+                zgemm<1, 0, 5>(rest, rest, kb, Rrow, ldg, Rrow, ldg, w.G + (k0 + kb) + (size_t)ldg * (k0 + kb), ldg,
                                st, 1, 0, 0, 0, 0, &pf, K_QR);
             }
         }

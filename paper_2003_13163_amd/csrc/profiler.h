@@ -23,11 +23,11 @@ enum KernelId {
     K_GEMM,          // plain complex GEMMs (right factor, centre moves)
     K_TRANSFER,      // transfer contraction
     K_HGRAM,         // Gram matrix of the eigen-solver start
-    K_TRIDIAG,       // tridiagonalisation: trailing matrix-vector products (per launch)
-    K_TRDAUX,        // tridiagonalisation: whole reduction including vector kernels and panel updates
+    K_TRIDIAG,       // tridiagonalisation: trailing Hermitian matrix-vector product (tiles)
+    K_TRDAUX,        // tridiagonalisation: per-column step kernel, column norms, panel updates
     K_DC,            // divide and conquer on the tridiagonal
     K_BACK,          // back-transformation: reflector block products X Y, X -= P Y^H
-    K_BTAUX,         // back-transformation: Y, S = Y^H Y, T, P T, FP64 copy of X
+    K_BTAUX,         // back-transformation: reflector mask, S = Y^H Y, P T, FP64 copy of X
     K_HOUT,          // X Q_H times the tridiagonal's eigenvectors (real GEMM)
     K_QR,            // Cholesky QR centre moves
     K_COUNT
@@ -37,7 +37,7 @@ inline const char* kernel_name(int k) {
     static const char* names[K_COUNT] = {"theta_channel", "jacobi_gram", "jacobi_eig64",
                                          "jacobi_update", "norm_sort",    "truncate",
                                          "gather",        "cgemm",        "transfer",
-                                         "heev_gram",     "heev_trd_gemv", "heev_tridiag", "heev_dc",
+                                         "heev_gram",     "heev_trd_hemv", "heev_trd_step", "heev_dc",
                                          "heev_back",     "heev_bt_aux",   "heev_out",      "qr_move"};
     return names[k];
 }
