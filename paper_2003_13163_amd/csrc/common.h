@@ -229,8 +229,8 @@ struct JacobiWork {
 // One-sided block Jacobi on the columns of X (m x N, column stride ld >= m).  On return
 // work.colmap[0..n) lists columns by decreasing norm and work.sig2 holds the
 // sorted squared norms, n = work.n_cols.  n < N only with keep_max > 0 (the
-// caller keeps at most keep_max columns) in FP32 storage with the eigen start:
-// then X holds the n columns of the largest eigenvalues of X^H X and the
+// caller keeps at most keep_max columns) and the eigen start: then X holds
+// the n columns of the largest eigenvalues of X^H X and the
 // weight of the others is info->rest_weight (work.rest_on).  Returns the
 // number of sweeps, or -1 if the sweep limit was reached, -2 on a HIP error.
 template <typename T>

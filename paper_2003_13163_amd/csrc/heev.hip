@@ -518,6 +518,9 @@ __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G,
 // ||G[j+3:, j+1]||^2, W^H G[j+3:, j+1] and V^H G[j+3:, j+1].
 // Every global load is issued at the start (the chunk's panel rows go to LDS),
 // so the kernel waits on memory once; the rest is LDS work between barriers.
+// Nothing another work-group of the same launch reads is written: the partial
+// sums for column j+1 go to the other half of double-buffered arrays, G[j+1, j]
+// and G[j+1, j+1] are left as they are (d[j+1] takes the updated diagonal).
 constexpr int kStepG = 8;                                  // row groups (waves) of k_trd_step
 constexpr int kStepSlots = (64 * kPart / kHt + 1 + kStepG - 1) / kStepG;   // slots per thread (nt + 1 <= 65)
 constexpr int kUpartPer = 5;   // tile partials per thread: 512 * 5 >= 64 * 65 / 2
@@ -525,8 +528,9 @@ constexpr int kUpartPer = 5;   // tile partials per thread: 512 * 5 >= 64 * 65 /
 __global__ __launch_bounds__(64 * kStepG) void k_trd_step(double2* __restrict__ G, int ldg, int N, int j, int c,
                                                   int update_next, const double2* __restrict__ ypart,
                                                   const double2* __restrict__ upart, double2* __restrict__ VW,
-                                                  double2* __restrict__ WV, double* __restrict__ part,
-                                                  double2* __restrict__ pdot, double2* __restrict__ tau,
+                                                  double2* __restrict__ WV, const double* __restrict__ part,
+                                                  const double2* __restrict__ pdot, double* __restrict__ part_next,
+                                                  double2* __restrict__ pdot_next, double2* __restrict__ tau,
                                                   double* __restrict__ d, double* __restrict__ e) {
     __shared__ double2 Vc[kTrdNb][65];    // V[a + r, q] as Vc[q][r] (q < c)
     __shared__ double2 Wc[kTrdNb][65];
@@ -692,7 +696,9 @@ __global__ __launch_bounds__(64 * kStepG) void k_trd_step(double2* __restrict__ 
                 const double2 wt = zmul(h.tau, make_double2(sr, si));
                 w = make_double2(wt.x + al * v.x, wt.y + al * v.y);
             }
-            G[i + (size_t)ldg * j] = v;
+            // G[j+1, j] keeps alpha, which every work-group reads; the
+            // back-transformation's mask stores the reflector's 1 there
+            if (tr > 0) G[i + (size_t)ldg * j] = v;
         }
         if (r < nr) {
             VW[i + (size_t)N * c] = v;
@@ -705,7 +711,7 @@ __global__ __launch_bounds__(64 * kStepG) void k_trd_step(double2* __restrict__ 
         if (blockIdx.x == 0 && t == 0) {
             tau[j] = h.tau;
             e[j] = h.beta;
-            d[j] = G[j + (size_t)ldg * j].x;
+            if (c == 0) d[j] = G[j + (size_t)ldg * j].x;   // else set by the previous column's update
         }
     }
     if (!update_next) return;
@@ -736,14 +742,17 @@ __global__ __launch_bounds__(64 * kStepG) void k_trd_step(double2* __restrict__ 
         if (urow) {
             gv = g0;
             for (int q8 = 0; q8 < kStepG; ++q8) { gv.x -= red4[q8][t].x; gv.y -= red4[q8][t].y; }
-            G[i + (size_t)ldg * (j + 1)] = gv;
+            // G[j+1, j+1] keeps its panel-start value, which every work-group
+            // reads; its update is the next diagonal entry of T
+            if (i == j + 1) d[j + 1] = gv.x;
+            else G[i + (size_t)ldg * (j + 1)] = gv;
             if (i >= j + 3) nrm = gv.x * gv.x + gv.y * gv.y;
         }
         double2 av = zero;
         if (urow && i >= j + 3) av = gv;
         arow[t] = av;
         nrm = wave_sum(nrm);
-        if (t == 0) part[blockIdx.x] = nrm;
+        if (t == 0) part_next[blockIdx.x] = nrm;
     }
     __syncthreads();
     // dots over this chunk: thread (dot r, row group g) sums conj(W[i, q]) a_i
@@ -771,7 +780,7 @@ __global__ __launch_bounds__(64 * kStepG) void k_trd_step(double2* __restrict__ 
         const int q = t % nq, isv = t / nq;
         double2 sum = zero;
         for (int q8 = 0; q8 < kStepG; ++q8) { sum.x += red4[q8][t].x; sum.y += red4[q8][t].y; }
-        pdot[(size_t)blockIdx.x * 2 * kTrdNb + isv * kTrdNb + q] = sum;
+        pdot_next[(size_t)blockIdx.x * 2 * kTrdNb + isv * kTrdNb + q] = sum;
     }
 }
 
@@ -1106,15 +1115,17 @@ __global__ __launch_bounds__(256) void k_dc_perm(const DcMerge* __restrict__ pla
 
 // --------------------------------------------------- back-transformation
 // Y = [v_j0 .. v_j0+nb-1] (N x kBtNb, zero-padded) from the reflectors below the diagonal.
-// The reflectors in place: G[i, j] <- 0 for i <= j, and column j <- 0 where
-// tau_j = 0 (no reflection), so that G's columns j0 .. j0+63 are the block's Y
-// (v_j[j+1] = 1 is stored already).
+// The reflectors in place: G[i, j] <- 0 for i <= j, G[j+1, j] <- 1 (v_j's
+// leading entry; the tridiagonalisation leaves alpha there), and column j <- 0
+// where tau_j = 0 (no reflection), so that G's columns j0 .. j0+63 are the
+// block's Y.
 __global__ __launch_bounds__(256) void k_bt_mask(double2* __restrict__ G, int ldg, int N,
                                                  const double2* __restrict__ tau) {
     const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
     if (i >= N) return;
     const double2 t = j < N - 1 ? tau[j] : make_double2(0.0, 0.0);
     if (i <= j || (t.x == 0.0 && t.y == 0.0)) G[i + (size_t)ldg * j] = make_double2(0.0, 0.0);
+    else if (i == j + 1) G[i + (size_t)ldg * j] = make_double2(1.0, 0.0);
 }
 
 // P = (X Y) T for H_j0 .. H_j0+nb-1 = I - Y T Y^H without forming T: T^{-1} is
@@ -1392,8 +1403,8 @@ size_t heev_bytes(int m_max, int n_max) {
     b += 2 * al(N * 2 * kTrdNb * sizeof(double2));              // VW, WV
     b += al((N / kHt + 2) * N * sizeof(double2));               // slots of the trailing product
     b += al((size_t)(N / kHt + 1) * (N / kHt + 2) / 2 * sizeof(double2));   // tiles' parts of u^H G u
-    b += al(kPart * sizeof(double));                            // norm partials
-    b += al((size_t)kPart * 2 * kTrdNb * sizeof(double2));      // dot partials
+    b += al(2 * kPart * sizeof(double));                        // norm partials (two halves)
+    b += al((size_t)2 * kPart * 2 * kTrdNb * sizeof(double2));  // dot partials (two halves)
     b += al(N * sizeof(double2));                               // tau
     b += 2 * al(N * sizeof(double));                            // d, e
     b += al((N / kBtNb + 1) * kBtNb * kBtNb * sizeof(double2)); // S = Y^H Y of every block
@@ -1420,8 +1431,8 @@ void heev_carve(char* p, int m_max, int n_max, HeevWork& w) {
     w.WV = (double2*)take(N * 2 * kTrdNb * sizeof(double2));
     w.ypart = (double2*)take((N / kHt + 2) * N * sizeof(double2));
     w.upart = (double2*)take((size_t)(N / kHt + 1) * (N / kHt + 2) / 2 * sizeof(double2));
-    w.part = (double*)take(kPart * sizeof(double));
-    w.pdot = (double2*)take((size_t)kPart * 2 * kTrdNb * sizeof(double2));
+    w.part = (double*)take(2 * kPart * sizeof(double));
+    w.pdot = (double2*)take((size_t)2 * kPart * 2 * kTrdNb * sizeof(double2));
     w.tau = (double2*)take(N * sizeof(double2));
     w.d = (double*)take(N * sizeof(double));
     w.e = (double*)take(N * sizeof(double));
@@ -1487,18 +1498,20 @@ void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
         launch_booked(pf, K_TRDAUX, 0.0, 32.0 * pn, k_fill_z, dim3(64), dim3(256), 0, st, w.VW, (size_t)pn);
         launch_booked(pf, K_TRDAUX, 0.0, 32.0 * pn, k_fill_z, dim3(64), dim3(256), 0, st, w.WV, (size_t)pn);
         launch_booked(pf, K_TRDAUX, 0.0, 16.0 * (N - j0), k_trd_colnorm, dim3(kPart), dim3(256), 0, st,
-                      (const double2*)w.G, ldg, N, j0, w.part);
+                      (const double2*)w.G, ldg, N, j0, w.part + (j0 & 1) * kPart);
         for (int c = 0; c < nbb; ++c) {
             const int j = j0 + c, len = N - j - 1;
             const int groups = (len + kHt - 1) / kHt;   // 64-row blocks of the trailing part
             const int ntiles = groups * (groups + 1) / 2;
             launch_booked(pf, K_TRIDIAG, 8.0 * (double)len * len, 8.0 * (double)len * (len + 1), k_trd_hemv,
                           dim3(ntiles), dim3(256), 0, st, (const double2*)w.G, ldg, N, j, w.ypart, w.upart);
+            const int cur = j & 1, nxt = cur ^ 1;   // halves of the double-buffered partial sums
             launch_booked(pf, K_TRDAUX, 16.0 * len * (3.0 * c + 4.0),
                           16.0 * ((double)len * (groups + 1) / kPart * kPart + len * (4.0 * c + 6.0) + ntiles),
                           k_trd_step, dim3(kPart), dim3(64 * kStepG), 0, st, w.G, ldg, N, j, c, (int)(c + 1 < nbb),
-                          (const double2*)w.ypart, (const double2*)w.upart, w.VW, w.WV, w.part, w.pdot, w.tau, w.d,
-                          w.e);
+                          (const double2*)w.ypart, (const double2*)w.upart, w.VW, w.WV,
+                          (const double*)(w.part + cur * kPart), (const double2*)(w.pdot + cur * kPart * 2 * kTrdNb),
+                          w.part + nxt * kPart, w.pdot + nxt * kPart * 2 * kTrdNb, w.tau, w.d, w.e);
         }
         const int k0 = j0 + nbb;
         zgemm<0, 1, 3>(N - k0, N - k0, 2 * kTrdNb, w.VW + k0, N, w.WV + k0, N, w.G + k0 + (size_t)ldg * k0, ldg,

@@ -1361,12 +1361,15 @@ int jacobi_orthogonalize(C2<T>* X, int m, int N, int ld, double tol, int max_swe
     // about the FP64 eigen-solver's accuracy and the sweeps only polish.
     bool started = false;
     if (w.heev && w.precond_min > 0 && N >= w.precond_min && N <= w.heev->cap_n && m <= w.heev->cap_m) {
-        // FP32 storage keeping at most keep_max columns: only the eigenvectors of
-        // the largest keep_max + 64 eigenvalues (rounded up to 64) are applied.
-        // Their span is the leading singular subspace to FP64 accuracy, far
-        // below the storage rounding, and the margin covers ties at the cut.
+        // A caller keeping at most keep_max columns: only the eigenvectors of the
+        // largest keep_max + 64 eigenvalues (rounded up to 64) are applied.  Their
+        // span is the leading singular subspace up to rotations into the left-out
+        // directions of size u ||G|| / (lambda_keep_max - lambda_keep), which the
+        // 64-column margin keeps far from the kept values; those rotations change
+        // the kept singular values only at second order.  Within the span the
+        // certificate (FP32 storage) or the sweeps (FP64) finish the columns.
         int keep = N;
-        if (sizeof(T) == 4 && keep_max > 0) {
+        if (keep_max > 0) {
             const int k2 = (keep_max + 64 + 63) / 64 * 64;
             if (2 * k2 <= N) keep = k2;
         }
