@@ -39,10 +39,32 @@ constexpr int kBtNb = 64;          // reflectors per block of the back-transform
 constexpr int kSplitK = 512;       // K chunk of the split-K products
 
 // ------------------------------------------------------------ wave reductions
+// Lane l's value to the whole wave (l uniform).
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+    const unsigned long long x = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x & 0xffffffffull), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The value of the lane that DPP control CTRL pairs with this one.
+template <int CTRL>
+__device__ __forceinline__ double dpp_pair(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, the same in every lane, in a fixed order: pairs
+// (lane ^ 1), quads (lane ^ 2), then the 8- and 16-lane mirrors within each row
+// of 16 on the DPP network, and the four row sums read from lanes 0, 16, 32,
+// 48.  Every lane of the wave must be active.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_pair<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_pair<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_pair<0x141>(v);   // row_half_mirror
+    v += dpp_pair<0x140>(v);   // row_mirror
+    return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
 }
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -384,7 +406,7 @@ __device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
 __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G, int ldg, int N, int j,
                                                   double2* __restrict__ ypart, double2* __restrict__ upart) {
     __shared__ double2 uI[kHt], uJ[kHt];
-    __shared__ double2 red[4][kHt];
+    __shared__ double2 red[16][kHt];
     __shared__ double2 ured[4];
     const int len = N - j - 1;
     const int nt = (len + kHt - 1) / kHt;
@@ -438,27 +460,29 @@ __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G,
             }
         }
     }
-    // rows: sum over q (lane bits 3..5); columns: sum over p (lane bits 0..2)
+    // rows: sum over q (lane bits 3..5): lane ^ 8 on the DPP network (row_ror:8
+    // within each row of 16 lanes), then the four rows of 16 and the four waves
+    // through LDS; columns: sum over p (lane bits 0..2) on the DPP network
 #pragma unroll
-    for (int s8 = 0; s8 < 8; ++s8)
+    for (int s8 = 0; s8 < 8; ++s8) {
+        racc[s8].x += dpp_pair<0x128>(racc[s8].x);
+        racc[s8].y += dpp_pair<0x128>(racc[s8].y);
+    }
 #pragma unroll
-        for (int o = 8; o < 64; o <<= 1) {
-            racc[s8].x += __shfl_xor(racc[s8].x, o, 64);
-            racc[s8].y += __shfl_xor(racc[s8].y, o, 64);
-        }
-#pragma unroll
-    for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-        for (int o = 1; o < 8; o <<= 1) {
-            cacc[cc].x += __shfl_xor(cacc[cc].x, o, 64);
-            cacc[cc].y += __shfl_xor(cacc[cc].y, o, 64);
-        }
+    for (int cc = 0; cc < 2; ++cc) {
+        cacc[cc].x += dpp_pair<0xB1>(cacc[cc].x);
+        cacc[cc].y += dpp_pair<0xB1>(cacc[cc].y);
+        cacc[cc].x += dpp_pair<0x4E>(cacc[cc].x);
+        cacc[cc].y += dpp_pair<0x4E>(cacc[cc].y);
+        cacc[cc].x += dpp_pair<0x141>(cacc[cc].x);
+        cacc[cc].y += dpp_pair<0x141>(cacc[cc].y);
+    }
     const size_t ldy = (size_t)N;
     double2 uu = make_double2(0.0, 0.0);   // this lane's part of u^H G0 u
-    if (q == 0) {
+    if ((q & 1) == 0) {
 #pragma unroll
         for (int s8 = 0; s8 < 8; ++s8) {
-            red[wave][8 * s8 + p] = racc[s8];
+            red[4 * wave + (q >> 1)][8 * s8 + p] = racc[s8];
             const double2 t = zcmul(uI[8 * s8 + p], racc[s8]);
             uu.x += t.x;
             uu.y += t.y;
@@ -487,7 +511,7 @@ __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G,
     if (tid < rows) {
         double2 sr = red[0][tid];
 #pragma unroll
-        for (int w4 = 1; w4 < 4; ++w4) { sr.x += red[w4][tid].x; sr.y += red[w4][tid].y; }
+        for (int w4 = 1; w4 < 16; ++w4) { sr.x += red[w4][tid].x; sr.y += red[w4][tid].y; }
         ypart[(size_t)J * ldy + kHt * I + tid] = sr;
     }
     if (tid == 0) {
@@ -622,11 +646,13 @@ __global__ __launch_bounds__(64 * kStepG) void k_trd_step(double2* __restrict__ 
         double2 sd = zero;
 #pragma unroll
         for (int k = 0; k < kPart / 8; ++k) { sd.x += pd[k].x; sd.y += pd[k].y; }
-#pragma unroll
-        for (int o = 1; o < 8; o <<= 1) {
-            sd.x += __shfl_xor(sd.x, o, 64);
-            sd.y += __shfl_xor(sd.y, o, 64);
-        }
+        // sum over lane bits 0..2 on the DPP network (pairs, quads, 8-lane mirror)
+        sd.x += dpp_pair<0xB1>(sd.x);
+        sd.y += dpp_pair<0xB1>(sd.y);
+        sd.x += dpp_pair<0x4E>(sd.x);
+        sd.y += dpp_pair<0x4E>(sd.y);
+        sd.x += dpp_pair<0x141>(sd.x);
+        sd.y += dpp_pair<0x141>(sd.y);
         if (t < 2 * kTrdNb) row1[t] = r1;
         if (dsub == 0 && dd < 2 * c) {
             // p_q = conj(W[j+1, q]) + s (W^H x)_q (dd < c), q_q likewise with V
@@ -1137,14 +1163,22 @@ __global__ __launch_bounds__(256) void k_bt_mask(double2* __restrict__ G, int ld
 // strict lower triangle of S (S is Hermitian) with 1/conj(tau_i) on its
 // diagonal, so by backward substitution
 //   p_i = conj(tau_i) ((X Y)_i - sum_{q>i} p_q S[q][i]).
-// One wave per row of X, lane q holding p_q; the split-K partials of X Y are
-// summed on the way.
+// One wave per row of X, lane q holding entry q; the split-K partials of X Y
+// are summed on the way.  Column by column: p_c is final once the earlier
+// (later, for ADJ) columns are subtracted; it is broadcast from lane c and
+// p_c S[c][l] is subtracted from the lanes still to come.
 template <bool ADJ>
 __global__ __launch_bounds__(256) void k_bt_solve(const double2* __restrict__ Ppart, int splits, int m,
                                                   const double2* __restrict__ S, const double2* __restrict__ tau,
                                                   int j0, int nbb, double2* __restrict__ P) {
     __shared__ double2 Ss[kBtNb][kBtNb + 1];
+    __shared__ double2 ts[kBtNb];
     for (int q = threadIdx.x; q < kBtNb * kBtNb; q += 256) Ss[q % kBtNb][q / kBtNb] = S[q];
+    if (threadIdx.x < kBtNb) {
+        double2 tc = (int)threadIdx.x < nbb ? tau[j0 + threadIdx.x] : make_double2(0.0, 0.0);
+        if (ADJ) tc.y = -tc.y;
+        ts[threadIdx.x] = tc;
+    }
     __syncthreads();
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (i >= m) return;
@@ -1154,21 +1188,19 @@ __global__ __launch_bounds__(256) void k_bt_solve(const double2* __restrict__ Pp
         b.x += v.x;
         b.y += v.y;
     }
-    double2 p = make_double2(0.0, 0.0);
     for (int k = 0; k < nbb; ++k) {
         const int c = ADJ ? nbb - 1 - k : k;
-        // sum over the lanes already solved (q < c, or q > c for the adjoint) of p_q S[q][c]
-        const bool done = ADJ ? (lane > c && lane < nbb) : lane < c;
-        double2 t = done ? zmul(p, Ss[lane][c]) : make_double2(0.0, 0.0);
-        t.x = wave_sum(t.x);
-        t.y = wave_sum(t.y);
+        const double2 pc = zmul(ts[c], make_double2(lane_bcast(b.x, c), lane_bcast(b.y, c)));
+        const double2 sc = Ss[c][lane];
         if (lane == c) {
-            double2 tc = tau[j0 + c];
-            if (ADJ) tc.y = -tc.y;
-            p = zmul(tc, make_double2(b.x - t.x, b.y - t.y));
+            b = pc;
+        } else if (ADJ ? lane < c : (lane > c && lane < nbb)) {
+            const double2 t = zmul(pc, sc);
+            b.x -= t.x;
+            b.y -= t.y;
         }
     }
-    P[i + (size_t)m * lane] = lane < nbb ? p : make_double2(0.0, 0.0);
+    P[i + (size_t)m * lane] = lane < nbb ? b : make_double2(0.0, 0.0);
 }
 
 // ------------------------------------------------ Gram check of the start
@@ -1248,6 +1280,11 @@ enum { kQrShifted = 0, kQrAfterShift = 1, kQrFinal = 2, kQrPlain = 3 };
 __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ G, int ldg, int k0, int kb, int pass,
                                                    const double* __restrict__ diag0,
                                                    DevInfo* __restrict__ info) {
+    // Right-looking, one barrier per step: row p of the block belongs to wave
+    // p % 4, lane l holds column l.  At step i the owner of row i (already
+    // brought up to date by itself) forms row i of R; after the barrier every
+    // wave subtracts conj(R[i][p]) R[i][l] from its own rows p > i.  No row is
+    // written by two waves, and row i is not written after its step.
     __shared__ double2 B[64][65];
     for (int q = threadIdx.x; q < kb * kb; q += 256) {
         const int i = q % kb, j = q / kb;
@@ -1257,90 +1294,121 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ G, int 
     const double floor_piv = 1e-300;
     const double bound = pass == kQrShifted ? 0.5 * info->qr_shift
                        : pass == kQrAfterShift ? 1e-14 : pass == kQrFinal ? 0.5 : 0.0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int i = 0; i < kb; ++i) {
-        const double piv = B[i][i].x;
-        const double bi = pass == kQrPlain ? 1e-12 * diag0[k0 + i] : bound;
-        if (threadIdx.x == 0 && !(piv > bi)) info->qr_fail = 1;
-        const double dii = sqrt(fmax(piv, floor_piv));
-        __syncthreads();
-        // row i of R: R[i][j] = B[i][j] / d for j > i
-        for (int j = i + 1 + (int)threadIdx.x; j < kb; j += 256) {
-            B[i][j].x /= dii;
-            B[i][j].y /= dii;
-        }
-        if (threadIdx.x == 0) B[i][i] = make_double2(dii, 0.0);
-        __syncthreads();
-        // trailing upper part: B[p][q] -= conj(R[i][p]) R[i][q] for i < p <= q
-        const int n2 = kb - i - 1;
-        for (int e = threadIdx.x; e < n2 * n2; e += 256) {
-            const int p = i + 1 + e % n2, q = i + 1 + e / n2;
-            if (p <= q) {
-                const double2 t = zcmul(B[i][p], B[i][q]);
-                B[p][q].x -= t.x;
-                B[p][q].y -= t.y;
+        if (w == (i & 3)) {
+            const double piv = B[i][i].x;
+            const double bi = pass == kQrPlain ? 1e-12 * diag0[k0 + i] : bound;
+            if (lane == 0 && !(piv > bi)) info->qr_fail = 1;
+            const double dii = sqrt(fmax(piv, floor_piv));
+            if (lane > i && lane < kb) {
+                B[i][lane].x /= dii;
+                B[i][lane].y /= dii;
+            } else if (lane == i) {
+                B[i][i] = make_double2(dii, 0.0);
             }
         }
         __syncthreads();
+        if (lane > i && lane < kb) {
+            const double2 ril = B[i][lane];
+            for (int p = i + 1 + ((w - i - 1) & 3); p <= lane; p += 4) {
+                const double2 t = zcmul(B[i][p], ril);
+                B[p][lane].x -= t.x;
+                B[p][lane].y -= t.y;
+            }
+        }
     }
+    __syncthreads();
     for (int q = threadIdx.x; q < kb * kb; q += 256) {
         const int i = q % kb, j = q / kb;
         G[(k0 + i) + (size_t)ldg * (k0 + j)] = i <= j ? B[i][j] : make_double2(0.0, 0.0);
     }
 }
 
+// Triangular substitution across the lanes of a wave for NR right-hand sides
+// at once, lane l holding entry l of each (l < kb), R upper triangular with a
+// real diagonal in LDS (R[i][j] = Rk[i][j]), rinv[i] = 1 / R[i][i]:
+//   CONJ = false   x R = b     x_l = (b_l - sum_{c<l} x_c R[c][l]) / R[l][l]
+//   CONJ = true    R^H x = b   x_l = (b_l - sum_{c<l} conj(R[c][l]) x_c) / R[l][l]
+// Column by column: x_c is final once the earlier columns are subtracted; it
+// is broadcast from lane c and subtracted from the later lanes.
+template <bool CONJ, int NR>
+__device__ __forceinline__ void lane_subst(double2 (&b)[NR], const double2 (*Rk)[65], const double* rinv, int kb,
+                                           int lane) {
+    for (int c = 0; c < kb; ++c) {
+        const double2 rc = Rk[c][lane < kb ? lane : 0];
+        const double ri = rinv[c];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const double2 xc = make_double2(lane_bcast(b[k].x, c) * ri, lane_bcast(b[k].y, c) * ri);
+            if (lane == c) {
+                b[k] = xc;
+            } else if (lane > c) {
+                const double2 t = CONJ ? zcmul(rc, xc) : zmul(xc, rc);
+                b[k].x -= t.x;
+                b[k].y -= t.y;
+            }
+        }
+    }
+}
+
+constexpr int kSubstRows = 4;   // right-hand sides per wave of the substitution kernels
+
 // Row block of R right of the diagonal block: R[k, j] = R_kk^{-H} G[k, j] for the
-// columns j in [k0 + kb, r) (one wave per column, forward substitution).
+// columns j in [k0 + kb, r); kSubstRows columns per wave.
 __global__ __launch_bounds__(256) void k_chol_row(double2* __restrict__ G, int ldg, int k0, int kb, int r) {
     __shared__ double2 Rk[64][65];
+    __shared__ double rinv[64];
     for (int q = threadIdx.x; q < kb * kb; q += 256) {
         const int i = q % kb, j = q / kb;
         Rk[i][j] = G[(k0 + i) + (size_t)ldg * (k0 + j)];
     }
+    if (threadIdx.x < kb) rinv[threadIdx.x] = 1.0 / G[(k0 + threadIdx.x) + (size_t)ldg * (k0 + threadIdx.x)].x;
     __syncthreads();
-    const int j = k0 + kb + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (j >= r) return;
-    double2* col = G + (size_t)ldg * j + k0;
-    const double2 g = lane < kb ? col[lane] : make_double2(0.0, 0.0);
-    double2 x = make_double2(0.0, 0.0);
-    for (int i = 0; i < kb; ++i) {
-        // sum_{q<i} conj(R[q][i]) x_q
-        double2 t = lane < i ? zcmul(Rk[lane][i], x) : make_double2(0.0, 0.0);
-        t.x = wave_sum(t.x);
-        t.y = wave_sum(t.y);
-        if (lane == i) {
-            const double rii = Rk[i][i].x;
-            x = make_double2((g.x - t.x) / rii, (g.y - t.y) / rii);
-        }
+    const int lane = threadIdx.x & 63;
+    const int j0 = k0 + kb + (blockIdx.x * 4 + (threadIdx.x >> 6)) * kSubstRows;
+    if (j0 >= r) return;
+    double2 x[kSubstRows];
+#pragma unroll
+    for (int k = 0; k < kSubstRows; ++k) {
+        const int j = j0 + k;
+        x[k] = (lane < kb && j < r) ? G[(k0 + lane) + (size_t)ldg * j] : make_double2(0.0, 0.0);
     }
-    if (lane < kb) col[lane] = x;
+    lane_subst<true, kSubstRows>(x, Rk, rinv, kb, lane);
+#pragma unroll
+    for (int k = 0; k < kSubstRows; ++k) {
+        const int j = j0 + k;
+        if (lane < kb && j < r) G[(k0 + lane) + (size_t)ldg * j] = x[k];
+    }
 }
 
 // Columns k0 .. k0+kb of Q (A is the whole m x r matrix): q_row R_kk = a_row (the
-// earlier blocks already subtracted), one wave per row, forward substitution
-// along the row.
+// earlier blocks already subtracted); kSubstRows rows per wave.
 __global__ __launch_bounds__(256) void k_qr_rowsolve(double2* __restrict__ A, int lda, int m,
                                                      const double2* __restrict__ G, int ldg, int k0, int kb) {
     __shared__ double2 Rk[64][65];
+    __shared__ double rinv[64];
     for (int q = threadIdx.x; q < kb * kb; q += 256) {
         const int i = q % kb, j = q / kb;
         Rk[i][j] = G[(k0 + i) + (size_t)ldg * (k0 + j)];
     }
+    if (threadIdx.x < kb) rinv[threadIdx.x] = 1.0 / G[(k0 + threadIdx.x) + (size_t)ldg * (k0 + threadIdx.x)].x;
     __syncthreads();
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (i >= m) return;
-    double2* row = A + i + (size_t)lda * k0;
-    const double2 b = lane < kb ? row[(size_t)lda * lane] : make_double2(0.0, 0.0);
-    double2 p = make_double2(0.0, 0.0);
-    for (int c = 0; c < kb; ++c) {
-        double2 t = lane < c ? zmul(p, Rk[lane][c]) : make_double2(0.0, 0.0);
-        t.x = wave_sum(t.x);
-        t.y = wave_sum(t.y);
-        if (lane == c) {
-            const double rcc = Rk[c][c].x;
-            p = make_double2((b.x - t.x) / rcc, (b.y - t.y) / rcc);
-        }
+    const int lane = threadIdx.x & 63;
+    const int i0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * kSubstRows;
+    if (i0 >= m) return;
+    double2 x[kSubstRows];
+#pragma unroll
+    for (int k = 0; k < kSubstRows; ++k) {
+        const int i = i0 + k;
+        x[k] = (lane < kb && i < m) ? A[i + (size_t)lda * (k0 + lane)] : make_double2(0.0, 0.0);
     }
-    if (lane < kb) row[(size_t)lda * lane] = p;
+    lane_subst<false, kSubstRows>(x, Rk, rinv, kb, lane);
+#pragma unroll
+    for (int k = 0; k < kSubstRows; ++k) {
+        const int i = i0 + k;
+        if (lane < kb && i < m) A[i + (size_t)lda * (k0 + lane)] = x[k];
+    }
 }
 
 // diag0[i] = G[i][i] (the columns' squared norms, for the plain pass's bounds);
@@ -1725,7 +1793,7 @@ bool cholqr3(const C2<T>* A, int m, int r, int lda, C2<T>* Q, int ldq, C2<T>* R,
     std::function<void(int, int)> trsm = [&](int c0, int nc) {
         if (nc <= 64) {
             launch_booked(pf, K_QR, 4.0 * (double)m * nc * nc, 32.0 * (double)m * nc, k_qr_rowsolve,
-                          dim3((m + 3) / 4), dim3(256), 0, st, Ad, ldx, m, (const double2*)w.G, ldg, c0, nc);
+                          dim3((m + 4 * kSubstRows - 1) / (4 * kSubstRows)), dim3(256), 0, st, Ad, ldx, m, (const double2*)w.G, ldg, c0, nc);
             return;
         }
         const int h = ((nc / 2 + 63) / 64) * 64;
@@ -1748,7 +1816,8 @@ bool cholqr3(const C2<T>* A, int m, int r, int lda, C2<T>* Q, int ldq, C2<T>* R,
             launch_booked(pf, K_QR, 0.0, 32.0 * kb * kb, k_chol_diag, dim3(1), dim3(256), 0, st, w.G, ldg, k0, kb,
                           kind, (const double*)w.dv, info);
             if (rest > 0) {
-                launch_booked(pf, K_QR, 4.0 * kb * kb * rest, 32.0 * kb * rest, k_chol_row, dim3((rest + 3) / 4),
+                launch_booked(pf, K_QR, 4.0 * kb * kb * rest, 32.0 * kb * rest, k_chol_row,
+                              dim3((rest + 4 * kSubstRows - 1) / (4 * kSubstRows)),
                               dim3(256), 0, st, w.G, ldg, k0, kb, r);
                 double2* Rrow = w.G + k0 + (size_t)ldg * (k0 + kb);
                 zgemm<1, 0, 5>(rest, rest, kb, Rrow, ldg, Rrow, ldg, w.G + (k0 + kb) + (size_t)ldg * (k0 + kb), ldg,
