@@ -159,6 +159,7 @@ struct HeevWork {
     double2 *upart, *tau;             // tiles' parts of u^H G u; reflector scalars
     double* part;                     // partial sums of ||column||^2 (row chunks)
     double2* pdot;                    // partial sums of the panel dots
+    double2* pfin;                    // a column's reduced norm and panel dots
     double *d, *e;                    // tridiagonal
     double2 *Sall, *Cpart, *P;        // back-transformation: Y^H Y per block, split-K partials, (X Y) T
     double *Z, *Z2, *U;               // eigenvectors of T and merge scratch (N x N, stride N)

@@ -404,13 +404,49 @@ __device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
 }
 
 __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G, int ldg, int N, int j,
-                                                  double2* __restrict__ ypart, double2* __restrict__ upart) {
+                                                  double2* __restrict__ ypart, double2* __restrict__ upart, int c,
+                                                  const double* __restrict__ part, const double2* __restrict__ pdot,
+                                                  double2* __restrict__ pfin) {
     __shared__ double2 uI[kHt], uJ[kHt];
     __shared__ double2 red[16][kHt];
     __shared__ double2 ured[4];
     const int len = N - j - 1;
     const int nt = (len + kHt - 1) / kHt;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if ((int)blockIdx.x == nt * (nt + 1) / 2) {
+        // the last work-group: the column's sums for k_trd_step from the row
+        // chunks' partials, ||G[j+2:, j]||^2 into pfin[0].x and the panel dots
+        // (W^H x)_q, (V^H x)_q into pfin[1 + q], pfin[1 + kTrdNb + q], q < c;
+        // thread (dot dd, sub) adds partials sub, sub + 8, .., then the eight
+        // subs are summed on the DPP network
+        if (wave == 0) {
+            const double sn = wave_sum(part[lane]);
+            if (lane == 0) pfin[0] = make_double2(sn, 0.0);
+        }
+        const int dsub = tid & 7;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int dd = (tid >> 3) + 32 * hh;          // pfin index - 1: p_q (dd < kTrdNb), q_q
+            const bool live = (dd % kTrdNb) < c;
+            double2 sd = make_double2(0.0, 0.0);
+            if (live) {
+#pragma unroll
+                for (int k = 0; k < kPart / 8; ++k) {
+                    const double2 v = pdot[(size_t)(dsub + 8 * k) * 2 * kTrdNb + dd];
+                    sd.x += v.x;
+                    sd.y += v.y;
+                }
+            }
+            sd.x += dpp_pair<0xB1>(sd.x);
+            sd.y += dpp_pair<0xB1>(sd.y);
+            sd.x += dpp_pair<0x4E>(sd.x);
+            sd.y += dpp_pair<0x4E>(sd.y);
+            sd.x += dpp_pair<0x141>(sd.x);
+            sd.y += dpp_pair<0x141>(sd.y);
+            if (live && dsub == 0) pfin[1 + dd] = sd;
+        }
+        return;
+    }
     int I, J;
     lower_tile((int)blockIdx.x, I, J);
     // lane (p, q) = (lane % 8, lane / 8) takes rows 8 s + p and columns
@@ -524,10 +560,11 @@ __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G,
 // The rest of column j in one kernel over kPart row chunks of all N rows, every
 // work-group forming the column's scalars itself (the same sums in the same
 // order in each):
-//   reflector      tau_j, scale s, beta from alpha = G[j+1, j] and the partial
-//                  sums of ||G[j+2:, j]||^2; v = e_0 + s u;
-//   panel dots     p = W^H v, q = V^H v from the partial sums of W^H x and
-//                  V^H x the previous column left;
+//   reflector      tau_j, scale s, beta from alpha = G[j+1, j] and
+//                  ||G[j+2:, j]||^2; v = e_0 + s u;
+//   panel dots     p = W^H v, q = V^H v from W^H x and V^H x;
+// (the two sums come reduced from the last work-group of k_trd_hemv, which
+// adds up the partials the previous column's kernel left);
 //   y              y_i = G[i, j+1] + s (G0 u)_i - (V p + W q)_i, (G0 u)_i the
 //                  sum of row i's slots of the tile product;
 //   alpha          = -|tau|^2 (v^H G_eff v) / 2 (real, G_eff Hermitian) with
@@ -552,8 +589,8 @@ constexpr int kUpartPer = 5;   // tile partials per thread: 512 * 5 >= 64 * 65 /
 __global__ __launch_bounds__(64 * kStepG) void k_trd_step(double2* __restrict__ G, int ldg, int N, int j, int c,
                                                   int update_next, const double2* __restrict__ ypart,
                                                   const double2* __restrict__ upart, double2* __restrict__ VW,
-                                                  double2* __restrict__ WV, const double* __restrict__ part,
-                                                  const double2* __restrict__ pdot, double* __restrict__ part_next,
+                                                  double2* __restrict__ WV, const double2* __restrict__ pfin,
+                                                  double* __restrict__ part_next,
                                                   double2* __restrict__ pdot_next, double2* __restrict__ tau,
                                                   double* __restrict__ d, double* __restrict__ e) {
     __shared__ double2 Vc[kTrdNb][65];    // V[a + r, q] as Vc[q][r] (q < c)
@@ -586,26 +623,18 @@ __global__ __launch_bounds__(64 * kStepG) void k_trd_step(double2* __restrict__ 
         sl[k] = zero;
         if (trow && s <= nt) sl[k] = ypart[(size_t)s * ldy + tr];
     }
-    // panel rows of the chunk, columns q = g + kStepG k: loaded unconditionally
-    // from clamped (in-bounds) addresses so that every load is in flight at once
+    // panel rows of the chunk, columns q = g + kStepG k < c (a condition that is
+    // the same for the whole wave)
     double2 pv[kTrdNb / kStepG], pw[kTrdNb / kStepG];
     const int ic = min(i, N - 1);
 #pragma unroll
     for (int k = 0; k < kTrdNb / kStepG; ++k) {
         const int q = g + kStepG * k;
-        pv[k] = VW[ic + (size_t)N * q];
-        pw[k] = VW[ic + (size_t)N * (kTrdNb + q)];
-    }
-    // pdot: dot dd = t / 8 (q = dd % c, from W if dd < c else V) summed over the
-    // partials t % 8 + 8 k by this thread
-    const int dd = t >> 3, dsub = t & 7;
-    double2 pd[kPart / 8];
-#pragma unroll
-    for (int k = 0; k < kPart / 8; ++k) {
-        pd[k] = zero;
-        if (dd < 2 * c) {
-            const int qq = dd % c, isv = dd / c;
-            pd[k] = pdot[(size_t)(dsub + 8 * k) * 2 * kTrdNb + isv * kTrdNb + qq];
+        pv[k] = zero;
+        pw[k] = zero;
+        if (q < c) {
+            pv[k] = VW[ic + (size_t)N * q];
+            pw[k] = VW[ic + (size_t)N * (kTrdNb + q)];
         }
     }
     double upv[kUpartPer];
@@ -621,45 +650,40 @@ __global__ __launch_bounds__(64 * kStepG) void k_trd_step(double2* __restrict__ 
         if (lane <= nt) y0s = ypart[(size_t)lane * ldy];
         if (lane == 0 && nt == 64) { const double2 v = ypart[(size_t)64 * ldy]; y0s.x += v.x; y0s.y += v.y; }
     }
-    double2 r1 = zero, rw = zero;          // row j+1 of the panel; this thread's dot's entry of it
-    if (t < 2 * kTrdNb && (t % kTrdNb) < c) r1 = VW[(j + 1) + (size_t)N * t];
-    if (dsub == 0 && dd < 2 * c)
-        rw = VW[(j + 1) + (size_t)N * ((dd / c ? 0 : kTrdNb) + dd % c)];
-    const double pt = part[lane];
+    // row j+1 of the panel (r1: V then W, the layout of row1), the entry of it
+    // that pq[t] needs (rw: W[j+1, q] for p_q, V[j+1, q] for q_q), and the
+    // column's reduced sums from the trailing product's last work-group
+    double2 r1 = zero, rw = zero, fd = zero;
+    const bool pqt = t < 2 * kTrdNb && (t % kTrdNb) < c;
+    if (pqt) {
+        r1 = VW[(j + 1) + (size_t)N * t];
+        rw = VW[(j + 1) + (size_t)N * ((t < kTrdNb ? kTrdNb : 0) + t % kTrdNb)];
+        fd = pfin[1 + t];
+    }
+    const double xnorm2 = pfin[0].x;
     const double2 alpha = G[(j + 1) + (size_t)ldg * j];
     const double g00 = G[(j + 1) + (size_t)ldg * (j + 1)].x;
     // ---- reflector scalars, panel dots, (G0 u)_0 and u^H G0 u
 #pragma unroll
     for (int k = 0; k < kTrdNb / kStepG; ++k) {
         const int q = g + kStepG * k;
-        double2 v = pv[k], w = pw[k];
-        if (r >= nr) { v = make_double2(0.0, 0.0); w = v; }
-        Vc[q][r] = v;
-        Wc[q][r] = w;
+        if (q < c) {
+            double2 v = pv[k], w = pw[k];
+            if (r >= nr) { v = make_double2(0.0, 0.0); w = v; }
+            Vc[q][r] = v;
+            Wc[q][r] = w;
+        }
     }
     double up = 0.0;
 #pragma unroll
     for (int k = 0; k < kUpartPer; ++k)
         if (t + 64 * kStepG * k < ntiles) up += upv[k];
-    const House h = house_scalars(alpha, wave_sum(pt));
-    {
-        double2 sd = zero;
-#pragma unroll
-        for (int k = 0; k < kPart / 8; ++k) { sd.x += pd[k].x; sd.y += pd[k].y; }
-        // sum over lane bits 0..2 on the DPP network (pairs, quads, 8-lane mirror)
-        sd.x += dpp_pair<0xB1>(sd.x);
-        sd.y += dpp_pair<0xB1>(sd.y);
-        sd.x += dpp_pair<0x4E>(sd.x);
-        sd.y += dpp_pair<0x4E>(sd.y);
-        sd.x += dpp_pair<0x141>(sd.x);
-        sd.y += dpp_pair<0x141>(sd.y);
-        if (t < 2 * kTrdNb) row1[t] = r1;
-        if (dsub == 0 && dd < 2 * c) {
-            // p_q = conj(W[j+1, q]) + s (W^H x)_q (dd < c), q_q likewise with V
-            const int qq = dd % c, isv = dd / c;
-            const double2 sc = zmul(h.scale, sd);
-            pq[isv * kTrdNb + qq] = make_double2(rw.x + sc.x, -rw.y + sc.y);
-        }
+    const House h = house_scalars(alpha, xnorm2);
+    if (t < 2 * kTrdNb) row1[t] = r1;
+    if (pqt) {
+        // p_q = conj(W[j+1, q]) + s (W^H x)_q, q_q = conj(V[j+1, q]) + s (V^H x)_q
+        const double2 sc = zmul(h.scale, fd);
+        pq[t] = make_double2(rw.x + sc.x, -rw.y + sc.y);
     }
     if (wave == 0) {
         const double2 y0 = make_double2(wave_sum(y0s.x), wave_sum(y0s.y));
@@ -672,14 +696,17 @@ __global__ __launch_bounds__(64 * kStepG) void k_trd_step(double2* __restrict__ 
     double uGu = ured[0];
 #pragma unroll
     for (int w8 = 1; w8 < kStepG; ++w8) uGu += ured[w8];
-    double corr1r = 0.0, corr1i = 0.0, qpr = 0.0;
-    for (int qq = 0; qq < c; ++qq) {
-        const double2 t1 = zmul(row1[qq], pq[qq]);
-        const double2 t2 = zmul(row1[kTrdNb + qq], pq[kTrdNb + qq]);
-        corr1r += t1.x + t2.x;
-        corr1i += t1.y + t2.y;
-        qpr += pq[kTrdNb + qq].x * pq[qq].x + pq[kTrdNb + qq].y * pq[qq].y;   // Re(conj(q) p)
+    // the panel's correction to y_{j+1} and Re(q^H p): lane qq < c of every wave
+    // takes panel column qq, the wave sums
+    double c1r = 0.0, c1i = 0.0, qp = 0.0;
+    if (lane < c) {
+        const double2 t1 = zmul(row1[lane], pq[lane]);
+        const double2 t2 = zmul(row1[kTrdNb + lane], pq[kTrdNb + lane]);
+        c1r = t1.x + t2.x;
+        c1i = t1.y + t2.y;
+        qp = pq[kTrdNb + lane].x * pq[lane].x + pq[kTrdNb + lane].y * pq[lane].y;   // Re(conj(q) p)
     }
+    const double corr1r = wave_sum(c1r), corr1i = wave_sum(c1i), qpr = wave_sum(qp);
     const double2 y0 = sy0;
     const double2 sy = zmul(h.scale, y0);
     const double s2 = h.scale.x * h.scale.x + h.scale.y * h.scale.y;
@@ -1473,6 +1500,7 @@ size_t heev_bytes(int m_max, int n_max) {
     b += al((size_t)(N / kHt + 1) * (N / kHt + 2) / 2 * sizeof(double2));   // tiles' parts of u^H G u
     b += al(2 * kPart * sizeof(double));                        // norm partials (two halves)
     b += al((size_t)2 * kPart * 2 * kTrdNb * sizeof(double2));  // dot partials (two halves)
+    b += al((1 + 2 * kTrdNb) * sizeof(double2));                // a column's reduced sums
     b += al(N * sizeof(double2));                               // tau
     b += 2 * al(N * sizeof(double));                            // d, e
     b += al((N / kBtNb + 1) * kBtNb * kBtNb * sizeof(double2)); // S = Y^H Y of every block
@@ -1501,6 +1529,7 @@ void heev_carve(char* p, int m_max, int n_max, HeevWork& w) {
     w.upart = (double2*)take((size_t)(N / kHt + 1) * (N / kHt + 2) / 2 * sizeof(double2));
     w.part = (double*)take(2 * kPart * sizeof(double));
     w.pdot = (double2*)take((size_t)2 * kPart * 2 * kTrdNb * sizeof(double2));
+    w.pfin = (double2*)take((1 + 2 * kTrdNb) * sizeof(double2));
     w.tau = (double2*)take(N * sizeof(double2));
     w.d = (double*)take(N * sizeof(double));
     w.e = (double*)take(N * sizeof(double));
@@ -1571,14 +1600,15 @@ void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
             const int j = j0 + c, len = N - j - 1;
             const int groups = (len + kHt - 1) / kHt;   // 64-row blocks of the trailing part
             const int ntiles = groups * (groups + 1) / 2;
-            launch_booked(pf, K_TRIDIAG, 8.0 * (double)len * len, 8.0 * (double)len * (len + 1), k_trd_hemv,
-                          dim3(ntiles), dim3(256), 0, st, (const double2*)w.G, ldg, N, j, w.ypart, w.upart);
             const int cur = j & 1, nxt = cur ^ 1;   // halves of the double-buffered partial sums
+            launch_booked(pf, K_TRIDIAG, 8.0 * (double)len * len, 8.0 * (double)len * (len + 1), k_trd_hemv,
+                          dim3(ntiles + 1), dim3(256), 0, st, (const double2*)w.G, ldg, N, j, w.ypart, w.upart, c,
+                          (const double*)(w.part + cur * kPart), (const double2*)(w.pdot + cur * kPart * 2 * kTrdNb),
+                          w.pfin);
             launch_booked(pf, K_TRDAUX, 16.0 * len * (3.0 * c + 4.0),
                           16.0 * ((double)len * (groups + 1) / kPart * kPart + len * (4.0 * c + 6.0) + ntiles),
                           k_trd_step, dim3(kPart), dim3(64 * kStepG), 0, st, w.G, ldg, N, j, c, (int)(c + 1 < nbb),
-                          (const double2*)w.ypart, (const double2*)w.upart, w.VW, w.WV,
-                          (const double*)(w.part + cur * kPart), (const double2*)(w.pdot + cur * kPart * 2 * kTrdNb),
+                          (const double2*)w.ypart, (const double2*)w.upart, w.VW, w.WV, (const double2*)w.pfin,
                           w.part + nxt * kPart, w.pdot + nxt * kPart * 2 * kTrdNb, w.tau, w.d, w.e);
         }
         const int k0 = j0 + nbb;
