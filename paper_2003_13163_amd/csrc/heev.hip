@@ -152,7 +152,10 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, int kchunk, 
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) { accR[bi][bj][r] = 0.0; accI[bi][bj][r] = 0.0; }
-    for (int k0 = 0; k0 < K; k0 += ZBK) {
+    // the next K tile is loaded into registers while the current one is
+    // multiplied from LDS, so the global latency overlaps the MFMA work
+    double2 ra[4], rb[4];
+    auto load_tiles = [&](int k0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int e = t + 256 * r;
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, int kchunk, 
                 v = OPA == 0 ? A[gi + (size_t)gk * lda] : A[gk + (size_t)gi * lda];
                 if (OPA == 1) v.y = -v.y;
             }
-            As[k][i] = v;
+            ra[r] = v;
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -177,9 +180,21 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, int kchunk, 
                 v = OPB == 0 ? B[gk + (size_t)gj * ldb] : B[gj + (size_t)gk * ldb];
                 if (OPB == 1) v.y = -v.y;
             }
-            Bs[k][j] = v;
+            rb[r] = v;
+        }
+    };
+    load_tiles(0);
+    for (int k0 = 0; k0 < K; k0 += ZBK) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = t + 256 * r;
+            if (OPA == 0) As[e >> 6][e & 63] = ra[r];
+            else As[e & 15][e >> 4] = ra[r];
+            if (OPB == 0) Bs[e & 15][e >> 4] = rb[r];
+            else Bs[e >> 6][e & 63] = rb[r];
         }
         __syncthreads();
+        if (k0 + ZBK < K) load_tiles(k0 + ZBK);
 #pragma unroll
         for (int kk = 0; kk < ZBK; kk += 4) {
             double2 a[2], b[2];
