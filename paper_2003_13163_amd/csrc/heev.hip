@@ -926,6 +926,8 @@ __global__ __launch_bounds__(1024) void k_dc_prep(const DcMerge* __restrict__ pl
     const double r2 = 0.70710678118654752440;
     const double* dl = b.dv + lo;
     const double* dr = b.dv + lo + n1;
+    __shared__ double sds[4096], sdz[4096];
+    __shared__ int sdc[4096];
     for (int t = threadIdx.x; t < n; t += 1024) {
         double val, zt;
         int pos;
@@ -939,18 +941,22 @@ __global__ __launch_bounds__(1024) void k_dc_prep(const DcMerge* __restrict__ pl
             pos = u + count_le(dl, n1, val);
             zt = sg * Z[(lo + n1) + (size_t)N * (lo + t)] * r2;
         }
-        b.ds[lo + pos] = val;
-        b.dz[lo + pos] = zt;
-        b.dcol[lo + pos] = lo + t;
+        sds[pos] = val;
+        sdz[pos] = zt;
+        sdc[pos] = lo + t;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    const double dmax = fmax(fabs(b.ds[lo]), fabs(b.ds[lo + n - 1]));
+    // the scan reads the merged order from LDS and keeps the last kept pole in
+    // registers; its results go to global memory with stores it never reads back
+    const double dmax = fmax(fabs(sds[0]), fabs(sds[n - 1]));
     const double tol = 8.0 * 2.220446049250313e-16 * fmax(dmax, rho);
     int k = 0, nd = 0, nrot = 0;
+    double dlast = 0.0, zlast = 0.0;
+    int clast = 0;
     for (int t = 0; t < n; ++t) {
-        double dt = b.ds[lo + t], zt = b.dz[lo + t];
-        const int ct = b.dcol[lo + t];
+        double dt = sds[t], zt = sdz[t];
+        const int ct = sdc[t];
         if (rho * fabs(zt) <= tol) {
             b.dfv[lo + nd] = dt;
             b.dfc[lo + nd] = ct;
@@ -958,8 +964,6 @@ __global__ __launch_bounds__(1024) void k_dc_prep(const DcMerge* __restrict__ pl
             continue;
         }
         if (k > 0) {
-            const double dlast = b.ndv[lo + k - 1], zlast = b.ndz[lo + k - 1];
-            const int clast = b.ndc[lo + k - 1];
             const double tt = hypot(zlast, zt);
             const double cc = zt / tt, ss = -zlast / tt;
             if (fabs((dt - dlast) * cc * ss) <= tol) {
@@ -979,6 +983,9 @@ __global__ __launch_bounds__(1024) void k_dc_prep(const DcMerge* __restrict__ pl
         b.ndv[lo + k] = dt;
         b.ndz[lo + k] = zt;
         b.ndc[lo + k] = ct;
+        dlast = dt;
+        zlast = zt;
+        clast = ct;
         ++k;
     }
     b.mk[mg.id] = k;
@@ -1233,14 +1240,11 @@ __global__ __launch_bounds__(256) void k_bt_solve(const double2* __restrict__ Pp
     for (int k = 0; k < nbb; ++k) {
         const int c = ADJ ? nbb - 1 - k : k;
         const double2 pc = zmul(ts[c], make_double2(lane_bcast(b.x, c), lane_bcast(b.y, c)));
-        const double2 sc = Ss[c][lane];
-        if (lane == c) {
-            b = pc;
-        } else if (ADJ ? lane < c : (lane > c && lane < nbb)) {
-            const double2 t = zmul(pc, sc);
-            b.x -= t.x;
-            b.y -= t.y;
-        }
+        double2 sc = Ss[c][lane];
+        if (!(ADJ ? lane < c : (lane > c && lane < nbb))) sc = make_double2(0.0, 0.0);
+        const double2 t = zmul(pc, sc);
+        b.x = lane == c ? pc.x : b.x - t.x;
+        b.y = lane == c ? pc.y : b.y - t.y;
     }
     P[i + (size_t)m * lane] = lane < nbb ? b : make_double2(0.0, 0.0);
 }
@@ -1343,17 +1347,31 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ G, int 
             const double bi = pass == kQrPlain ? 1e-12 * diag0[k0 + i] : bound;
             if (lane == 0 && !(piv > bi)) info->qr_fail = 1;
             const double dii = sqrt(fmax(piv, floor_piv));
+            const double inv = 1.0 / dii;
             if (lane > i && lane < kb) {
-                B[i][lane].x /= dii;
-                B[i][lane].y /= dii;
+                B[i][lane].x *= inv;
+                B[i][lane].y *= inv;
             } else if (lane == i) {
                 B[i][i] = make_double2(dii, 0.0);
             }
         }
         __syncthreads();
         if (lane > i && lane < kb) {
+            // rows p = p0, p0 + 4, .. <= lane, four at a time: all loads of a
+            // group before its stores, so their latencies overlap
             const double2 ril = B[i][lane];
-            for (int p = i + 1 + ((w - i - 1) & 3); p <= lane; p += 4) {
+            int p = i + 1 + ((w - i - 1) & 3);
+            for (; p + 12 <= lane; p += 16) {
+                double2 rp[4], bp[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) { rp[u] = B[i][p + 4 * u]; bp[u] = B[p + 4 * u][lane]; }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double2 t = zcmul(rp[u], ril);
+                    B[p + 4 * u][lane] = make_double2(bp[u].x - t.x, bp[u].y - t.y);
+                }
+            }
+            for (; p <= lane; p += 4) {
                 const double2 t = zcmul(B[i][p], ril);
                 B[p][lane].x -= t.x;
                 B[p][lane].y -= t.y;
@@ -1377,19 +1395,18 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ G, int 
 template <bool CONJ, int NR>
 __device__ __forceinline__ void lane_subst(double2 (&b)[NR], const double2 (*Rk)[65], const double* rinv, int kb,
                                            int lane) {
+    // no branches: the row of R is masked to the lanes still to come, and the
+    // solved lane takes x_c by a select
     for (int c = 0; c < kb; ++c) {
-        const double2 rc = Rk[c][lane < kb ? lane : 0];
+        double2 rc = Rk[c][lane < kb ? lane : 0];
+        if (lane <= c) rc = make_double2(0.0, 0.0);
         const double ri = rinv[c];
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const double2 xc = make_double2(lane_bcast(b[k].x, c) * ri, lane_bcast(b[k].y, c) * ri);
-            if (lane == c) {
-                b[k] = xc;
-            } else if (lane > c) {
-                const double2 t = CONJ ? zcmul(rc, xc) : zmul(xc, rc);
-                b[k].x -= t.x;
-                b[k].y -= t.y;
-            }
+            const double2 t = CONJ ? zcmul(rc, xc) : zmul(xc, rc);
+            b[k].x = lane == c ? xc.x : b[k].x - t.x;
+            b[k].y = lane == c ? xc.y : b[k].y - t.y;
         }
     }
 }
