@@ -1222,7 +1222,17 @@ __global__ __launch_bounds__(256) void k_bt_solve(const double2* __restrict__ Pp
                                                   int j0, int nbb, double2* __restrict__ P) {
     __shared__ double2 Ss[kBtNb][kBtNb + 1];
     __shared__ double2 ts[kBtNb];
-    for (int q = threadIdx.x; q < kBtNb * kBtNb; q += 256) Ss[q % kBtNb][q / kBtNb] = S[q];
+    {
+        static_assert(kBtNb == 64, "the block load covers 64 x 64");
+        double2 v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = S[threadIdx.x + 256 * u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int q = (int)threadIdx.x + 256 * u;
+            Ss[q & 63][q >> 6] = v[u];
+        }
+    }
     if (threadIdx.x < kBtNb) {
         double2 tc = (int)threadIdx.x < nbb ? tau[j0 + threadIdx.x] : make_double2(0.0, 0.0);
         if (ADJ) tc.y = -tc.y;
@@ -1322,6 +1332,23 @@ __global__ __launch_bounds__(256) void k_qr_shift(double2* __restrict__ G, int l
 //   kQrPlain    1e-12 of the column's own squared norm (diag0): the column is
 //               independent of the earlier ones to 1e-6 in angle, so one more
 //               pass makes Q orthonormal.
+// The kb x kb block of G at (k0, k0) into LDS (64 x 65), every load issued
+// before the first LDS store so that their latencies overlap.
+__device__ __forceinline__ void load_block64(double2 (*Bs)[65], const double2* __restrict__ G, int ldg, int k0,
+                                             int kb) {
+    double2 v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int q = (int)threadIdx.x + 256 * u, i = q & 63, jj = q >> 6;
+        v[u] = (i < kb && jj < kb) ? G[(k0 + i) + (size_t)ldg * (k0 + jj)] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int q = (int)threadIdx.x + 256 * u;
+        Bs[q & 63][q >> 6] = v[u];
+    }
+}
+
 enum { kQrShifted = 0, kQrAfterShift = 1, kQrFinal = 2, kQrPlain = 3 };
 __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ G, int ldg, int k0, int kb, int pass,
                                                    const double* __restrict__ diag0,
@@ -1332,10 +1359,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ G, int 
     // wave subtracts conj(R[i][p]) R[i][l] from its own rows p > i.  No row is
     // written by two waves, and row i is not written after its step.
     __shared__ double2 B[64][65];
-    for (int q = threadIdx.x; q < kb * kb; q += 256) {
-        const int i = q % kb, j = q / kb;
-        B[i][j] = G[(k0 + i) + (size_t)ldg * (k0 + j)];
-    }
+    load_block64(B, G, ldg, k0, kb);
     __syncthreads();
     const double floor_piv = 1e-300;
     const double bound = pass == kQrShifted ? 0.5 * info->qr_shift
@@ -1418,10 +1442,7 @@ constexpr int kSubstRows = 4;   // right-hand sides per wave of the substitution
 __global__ __launch_bounds__(256) void k_chol_row(double2* __restrict__ G, int ldg, int k0, int kb, int r) {
     __shared__ double2 Rk[64][65];
     __shared__ double rinv[64];
-    for (int q = threadIdx.x; q < kb * kb; q += 256) {
-        const int i = q % kb, j = q / kb;
-        Rk[i][j] = G[(k0 + i) + (size_t)ldg * (k0 + j)];
-    }
+    load_block64(Rk, G, ldg, k0, kb);
     if (threadIdx.x < kb) rinv[threadIdx.x] = 1.0 / G[(k0 + threadIdx.x) + (size_t)ldg * (k0 + threadIdx.x)].x;
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -1447,10 +1468,7 @@ __global__ __launch_bounds__(256) void k_qr_rowsolve(double2* __restrict__ A, in
                                                      const double2* __restrict__ G, int ldg, int k0, int kb) {
     __shared__ double2 Rk[64][65];
     __shared__ double rinv[64];
-    for (int q = threadIdx.x; q < kb * kb; q += 256) {
-        const int i = q % kb, j = q / kb;
-        Rk[i][j] = G[(k0 + i) + (size_t)ldg * (k0 + j)];
-    }
+    load_block64(Rk, G, ldg, k0, kb);
     if (threadIdx.x < kb) rinv[threadIdx.x] = 1.0 / G[(k0 + threadIdx.x) + (size_t)ldg * (k0 + threadIdx.x)].x;
     __syncthreads();
     const int lane = threadIdx.x & 63;

@@ -714,3 +714,62 @@ def test_vidal_update_vs_oracle_appendix_a(pm, n, depth, chi, p):
     assert dS <= 1e-10 and dL <= 1e-10
     assert dD <= 1e-12
     assert dZ <= 1e-6
+
+
+def _haar_unitary(rng, n):
+    z = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))[None, :]
+
+
+@pytest.mark.parametrize("n,chi_max,prec,tol", [(4, 5, "fp64", 1e-10), (10, 600, "fp64", 1e-10),
+                                                (10, 600, "fp32", MIXED_TOL), (10, 600, "bf16x3", MIXED_TOL)])
+def test_cut_inside_degenerate_spectrum(pm, n, chi_max, prec, tol):
+    """A split whose Schmidt spectrum has an exactly degenerate block across
+    the cut: several truncations are equally correct (which of the equal
+    values are kept is a matter of rounding), so the test compares what is
+    unique -- the kept count, the sorted kept values, the entropy over the
+    kept values and the discarded weight -- with the oracle and with the
+    closed form of the spectrum the state was built with.  The state is in
+    mixed canonical form with the centre at the gate's left site, its
+    two-site block theta = U diag(s) V^H with Haar U, V; the identity channel
+    leaves it as it is.  n = 4: a 16 x 16 block (one-sided Jacobi); n = 10: a
+    1024 x 1024 block (Gram eigen start)."""
+    rng = np.random.default_rng(77 + n)
+    s0 = n // 2 - 1
+    dims = [min(4 ** (b + 1), 4 ** (n - b - 1)) for b in range(n - 1)]
+    chi_m = dims[s0]
+    lam = np.exp(-np.arange(chi_m) / (chi_m / 6.8))
+    blk = slice(chi_max - 2, chi_max + 2) if n == 4 else slice(chi_max - 5, chi_max + 4)
+    lam[blk] = lam[blk.start]
+    ts = []
+    for s in range(n):
+        cl = 1 if s == 0 else dims[s - 1]
+        cr = 1 if s == n - 1 else dims[s]
+        if s < s0:       # left isometry: (cl*4) x cr, orthonormal columns
+            ts.append(_haar_unitary(rng, cl * 4)[:, :cr].reshape(cl, 4, cr))
+        elif s == s0:    # U diag(lam)
+            ts.append((_haar_unitary(rng, cl * 4)[:, :cr] * lam[None, :]).reshape(cl, 4, cr))
+        else:            # right isometry: cl x (4*cr), orthonormal rows
+            ts.append(_haar_unitary(rng, 4 * cr)[:cl, :].reshape(cl, 4, cr))
+    ident = np.eye(16, dtype=np.complex128)
+    say(f"case degenerate cut n={n} chi_max={chi_max} {prec}: block of {blk.stop - blk.start} equal values")
+    ref = oracle_from(ts)
+    rinfo = ref.apply_gate(s0, ident, chi_max, 1e-12)
+    st = pm.Mpo(n, max(dims), prec, "pauli")
+    st.import_state(pm.tensors_to_snapshot(ts, "pauli", centre=s0))
+    info = st.apply(s0, ident, chi_max, 1e-12)
+    got = st.singular_values(s0)
+    st.close()
+    w = lam ** 2
+    disc_cf = float(w[chi_max:].sum())
+    wk = w[:chi_max] / w[:chi_max].sum()
+    S_cf = float(-(wk * np.log2(wk)).sum())
+    say(f"  kept {info.kept} dS(oracle) {info.entropy - rinfo.entropy:.3e} dS(closed form) {info.entropy - S_cf:.3e}")
+    assert info.kept == rinfo.kept == chi_max
+    assert abs(rinfo.entropy - S_cf) <= 1e-12
+    assert abs(info.entropy - rinfo.entropy) <= tol
+    assert abs(info.entropy - S_cf) <= tol
+    assert abs(info.discarded_weight - rinfo.discarded_weight) <= tol * rinfo.total_weight
+    assert abs(info.discarded_weight - disc_cf) <= tol * w.sum()
+    assert np.abs(np.sort(got[:chi_max])[::-1] - lam[:chi_max]).max() <= tol * lam[0]
