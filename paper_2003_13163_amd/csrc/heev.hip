@@ -410,12 +410,19 @@ __global__ __launch_bounds__(256) void k_trd_colnorm(const double2* __restrict__
 //                  upart[tile].
 constexpr int kHt = 64;   // tile edge of the trailing product
 
-__device__ __forceinline__ void lower_tile(int t, int& I, int& J) {
-    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
-    while (i * (i + 1) / 2 > t) --i;
-    I = i;
-    J = t - i * (i + 1) / 2;
+// Tile t of the lower triangle of an nt x nt tile grid, numbered down the
+// tile columns (J = 0: I = 0 .. nt-1, then J = 1: I = 1 .. nt-1, ..), so that
+// work-groups with neighbouring numbers read neighbouring kilobytes of each
+// column of G.
+__device__ __forceinline__ void lower_tile(int t, int nt, int& I, int& J) {
+    // columns before J hold J nt - J (J - 1) / 2 tiles
+    const double b = 2.0 * nt + 1.0;
+    int jj = (int)((b - sqrt(b * b - 8.0 * t)) * 0.5);
+    jj = max(0, min(jj, nt - 1));
+    while (jj > 0 && jj * nt - jj * (jj - 1) / 2 > t) --jj;
+    while (jj + 1 < nt && (jj + 1) * nt - (jj + 1) * jj / 2 <= t) ++jj;
+    J = jj;
+    I = jj + (t - (jj * nt - jj * (jj - 1) / 2));
 }
 
 __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G, int ldg, int N, int j,
@@ -463,7 +470,7 @@ __global__ __launch_bounds__(256) void k_trd_hemv(const double2* __restrict__ G,
         return;
     }
     int I, J;
-    lower_tile((int)blockIdx.x, I, J);
+    lower_tile((int)blockIdx.x, nt, I, J);
     // lane (p, q) = (lane % 8, lane / 8) takes rows 8 s + p and columns
     // 16 wave + 8 cc + q, so each load instruction reads eight 128-byte row runs
     const int p = lane & 7, q = lane >> 3;
@@ -1349,15 +1356,33 @@ __device__ __forceinline__ void load_block64(double2 (*Bs)[65], const double2* _
     }
 }
 
+// G[i, j] = sum over z of P_z[i, j] (P_z r x r, stride r, one after the other),
+// on the 64 x 64 tiles on or above the diagonal, partials added in order.
+__global__ __launch_bounds__(256) void k_sum_upper(const double2* __restrict__ P, int splits, int r,
+                                                   double2* __restrict__ G, int ldg) {
+    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    if (i >= r || (i >> 6) > (j >> 6)) return;
+    const size_t rr = (size_t)r * r;
+    double2 acc = P[i + (size_t)r * j];
+    for (int z = 1; z < splits; ++z) {
+        const double2 v = P[rr * z + i + (size_t)r * j];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    G[i + (size_t)ldg * j] = acc;
+}
+
 enum { kQrShifted = 0, kQrAfterShift = 1, kQrFinal = 2, kQrPlain = 3 };
 __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ G, int ldg, int k0, int kb, int pass,
                                                    const double* __restrict__ diag0,
                                                    DevInfo* __restrict__ info) {
-    // Right-looking, one barrier per step: row p of the block belongs to wave
-    // p % 4, lane l holds column l.  At step i the owner of row i (already
-    // brought up to date by itself) forms row i of R; after the barrier every
-    // wave subtracts conj(R[i][p]) R[i][l] from its own rows p > i.  No row is
-    // written by two waves, and row i is not written after its step.
+    // Right-looking, one barrier per step, the trailing rows in registers: row
+    // p lives in wave p % 4 (slot p / 4), lane l holding column l.  At step i
+    // the owner of row i reads it from LDS, where it published it in the step
+    // before, forms row i of R and stores it there for good; after the barrier
+    // every wave subtracts conj(R[i][p]) R[i][l] from its rows i < p <= l and
+    // the owner of row i+1 publishes that row.  Register slots are only ever
+    // addressed by compile-time indices.
     __shared__ double2 B[64][65];
     load_block64(B, G, ldg, k0, kb);
     __syncthreads();
@@ -1365,41 +1390,29 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ G, int 
     const double bound = pass == kQrShifted ? 0.5 * info->qr_shift
                        : pass == kQrAfterShift ? 1e-14 : pass == kQrFinal ? 0.5 : 0.0;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double2 b[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) b[u] = B[w + 4 * u][lane];
     for (int i = 0; i < kb; ++i) {
         if (w == (i & 3)) {
-            const double piv = B[i][i].x;
+            double2 r = B[i][lane];
+            const double piv = lane_bcast(r.x, i);
             const double bi = pass == kQrPlain ? 1e-12 * diag0[k0 + i] : bound;
             if (lane == 0 && !(piv > bi)) info->qr_fail = 1;
             const double dii = sqrt(fmax(piv, floor_piv));
             const double inv = 1.0 / dii;
-            if (lane > i && lane < kb) {
-                B[i][lane].x *= inv;
-                B[i][lane].y *= inv;
-            } else if (lane == i) {
-                B[i][i] = make_double2(dii, 0.0);
-            }
+            if (lane > i) r = make_double2(r.x * inv, r.y * inv);
+            else if (lane == i) r = make_double2(dii, 0.0);
+            B[i][lane] = r;
         }
         __syncthreads();
-        if (lane > i && lane < kb) {
-            // rows p = p0, p0 + 4, .. <= lane, four at a time: all loads of a
-            // group before its stores, so their latencies overlap
-            const double2 ril = B[i][lane];
-            int p = i + 1 + ((w - i - 1) & 3);
-            for (; p + 12 <= lane; p += 16) {
-                double2 rp[4], bp[4];
+        const double2 ril = B[i][lane];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) { rp[u] = B[i][p + 4 * u]; bp[u] = B[p + 4 * u][lane]; }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const double2 t = zcmul(rp[u], ril);
-                    B[p + 4 * u][lane] = make_double2(bp[u].x - t.x, bp[u].y - t.y);
-                }
-            }
-            for (; p <= lane; p += 4) {
-                const double2 t = zcmul(B[i][p], ril);
-                B[p][lane].x -= t.x;
-                B[p][lane].y -= t.y;
-            }
+        for (int u = 0; u < 16; ++u) {
+            const int p = w + 4 * u;
+            const double2 t = zcmul(B[i][p], ril);
+            if (p > i && p <= lane) b[u] = make_double2(b[u].x - t.x, b[u].y - t.y);
+            if (p == i + 1) B[p][lane] = b[u];
         }
     }
     __syncthreads();
@@ -1642,8 +1655,13 @@ void heev_run(int N, HeevWork& w, Profiler& pf, hipStream_t st) {
     for (int j0 = 0; j0 < N - 1; j0 += kTrdNb) {
         const int nbb = std::min(kTrdNb, N - 1 - j0);
         const double pn = (double)N * 2 * kTrdNb;
-        launch_booked(pf, K_TRDAUX, 0.0, 32.0 * pn, k_fill_z, dim3(64), dim3(256), 0, st, w.VW, (size_t)pn);
-        launch_booked(pf, K_TRDAUX, 0.0, 32.0 * pn, k_fill_z, dim3(64), dim3(256), 0, st, w.WV, (size_t)pn);
+        // every step kernel writes its panel column of V and W on all N rows
+        // (zero above the reflector), so only a last, partial panel leaves
+        // columns of the buffers that the rank update reads unwritten
+        if (nbb < kTrdNb) {
+            launch_booked(pf, K_TRDAUX, 0.0, 32.0 * pn, k_fill_z, dim3(64), dim3(256), 0, st, w.VW, (size_t)pn);
+            launch_booked(pf, K_TRDAUX, 0.0, 32.0 * pn, k_fill_z, dim3(64), dim3(256), 0, st, w.WV, (size_t)pn);
+        }
         launch_booked(pf, K_TRDAUX, 0.0, 16.0 * (N - j0), k_trd_colnorm, dim3(kPart), dim3(256), 0, st,
                       (const double2*)w.G, ldg, N, j0, w.part + (j0 & 1) * kPart);
         for (int c = 0; c < nbb; ++c) {
@@ -1882,9 +1900,23 @@ bool cholqr3(const C2<T>* A, int m, int r, int lda, C2<T>* Q, int ldq, C2<T>* R,
                        Ad + (size_t)ldx * (c0 + h), ldx, st, 1, 0, 0, 0, 0, &pf, K_QR);
         trsm(c0 + h, nc - h);
     };
+    // the Gram of a wide block has few output tiles (136 for r = 1024): its K
+    // range is split over up to four launches' worth of work-groups, whose
+    // partials go to whichever of Z, U holds no R factor, and summed in order
+    const int gsplit = r >= 512 ? (int)std::min<size_t>(4, (size_t)w.cap_n * w.cap_n / (2 * (size_t)r * r)) : 1;
     auto pass_run = [&](int kind) {
         // the Cholesky factorisation reads the upper triangle only
-        zgemm<1, 0, 4>(r, r, m, Ad, ldx, Ad, ldx, w.G, ldg, st, 1, 0, 0, 0, 0, &pf, K_QR);
+        if (gsplit >= 2) {
+            double2* part = Rt == (double2*)w.Z ? (double2*)w.U : (double2*)w.Z;
+            const int kchunk = (((m + gsplit - 1) / gsplit) + 15) & ~15;
+            const int nz = (m + kchunk - 1) / kchunk;
+            zgemm<1, 0, 4>(r, r, m, Ad, ldx, Ad, ldx, part, r, st, nz, kchunk, (size_t)kchunk, (size_t)kchunk,
+                           (size_t)r * r, &pf, K_QR);
+            launch_booked(pf, K_QR, 0.0, 16.0 * (nz + 1.0) * r * r / 2, k_sum_upper, dim3((r + 255) / 256, r),
+                          dim3(256), 0, st, (const double2*)part, nz, r, w.G, ldg);
+        } else {
+            zgemm<1, 0, 4>(r, r, m, Ad, ldx, Ad, ldx, w.G, ldg, st, 1, 0, 0, 0, 0, &pf, K_QR);
+        }
         if (kind == kQrShifted)
             launch_booked(pf, K_QR, 0.0, 16.0 * r, k_qr_shift, dim3(1), dim3(256), 0, st, w.G, ldg, r,
                           11.0 * ((double)m * r + (double)r * (r + 1)) * u, info);
