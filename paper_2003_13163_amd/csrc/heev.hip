@@ -1390,6 +1390,9 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ G, int 
     const double bound = pass == kQrShifted ? 0.5 * info->qr_shift
                        : pass == kQrAfterShift ? 1e-14 : pass == kQrFinal ? 0.5 : 0.0;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the plain pass's per-column bounds, loaded once (lane l: column l), so
+    // that no step waits on global memory
+    const double d0 = (pass == kQrPlain && lane < kb) ? diag0[k0 + lane] : 0.0;
     double2 b[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) b[u] = B[w + 4 * u][lane];
@@ -1397,7 +1400,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ G, int 
         if (w == (i & 3)) {
             double2 r = B[i][lane];
             const double piv = lane_bcast(r.x, i);
-            const double bi = pass == kQrPlain ? 1e-12 * diag0[k0 + i] : bound;
+            const double bi = pass == kQrPlain ? 1e-12 * lane_bcast(d0, i) : bound;
             if (lane == 0 && !(piv > bi)) info->qr_fail = 1;
             const double dii = sqrt(fmax(piv, floor_piv));
             const double inv = 1.0 / dii;
