@@ -2,7 +2,8 @@
 (Sec. IV.A-B; N_s = 24 realizations, bond entropies averaged over
 realizations, then maximised over the cut): at p = 0.15 with chi = 80 the
 optimal depth is D* = 4 and S*_max is about 2.75 for n >= 8, with at least
-99.5% of the total probability kept; at p = 0 on 8 qubits (chi = 256, exact)
+99.5% of the total probability kept; at p = 0.1 with chi = 150, D* = 6 and
+S*_max is about 4, with at least 99.7% kept; at p = 0 on 8 qubits (chi = 256, exact)
 S_max approaches 6.56 at large depth.  Our realizations are our own draws, so
 S* is held to the spread of a 24-sample mean (0.1)."""
 import pytest
@@ -27,6 +28,16 @@ def test_optimal_depth_p015(ens):
     assert r["D_star"] == 4
     assert abs(r["S_star"] - 2.75) <= 0.1
     assert r["trace_at_D_star"] >= 0.995
+
+
+def test_optimal_depth_p010(ens):
+    # Sec. IV.B: at p = 0.1 with chi = 150, D* = 6 and S*_max is about 4 for
+    # n >= 8, with at least 99.7% of the total probability kept
+    r = ens(8, 0.10, 150, 10, 24, 1000)
+    print(f"p=0.10 n=8: D* {r['D_star']} S* {r['S_star']:.3f} Tr {r['trace_at_D_star']:.4f}", flush=True)
+    assert r["D_star"] == 6
+    assert abs(r["S_star"] - 4.0) <= 0.1
+    assert r["trace_at_D_star"] >= 0.997
 
 
 def test_noiseless_saturation_n8(ens):
