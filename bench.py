@@ -152,9 +152,57 @@ def per_gate_roofline(prof, prec, chi, ms_per_gate, gates):
             "bytes_ratio_to_fused_min": alg_bytes / w["fused_min_bytes"]}
 
 
+def source_digest(spec):
+    """sha256 over named pieces of source files, spec = {relative path: [names]}:
+    a function is taken from its name at its definition (the name followed by
+    its parameter list and an opening brace) through its closing brace, a
+    constant from `constexpr int NAME =` through the semicolon.  None if a file
+    or a name is missing."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for rel in sorted(spec):
+        try:
+            text = open(os.path.join(ROOT, rel)).read()
+        except OSError:
+            return None
+        for name in spec[rel]:
+            piece = None
+            m = re.search(r"constexpr\s+int\s+" + re.escape(name) + r"\s*=[^;]*;", text)
+            if m:
+                piece = m.group(0)
+            for m in re.finditer(r"\b" + re.escape(name) + r"\s*\(", text):
+                if piece is not None:
+                    break
+                i, depth = m.end() - 1, 0
+                while i < len(text):           # the parameter list
+                    depth += {"(": 1, ")": -1}.get(text[i], 0)
+                    i += 1
+                    if depth == 0:
+                        break
+                k = i
+                while k < len(text) and text[k] in " \t\n":
+                    k += 1
+                if k >= len(text) or text[k] != "{":
+                    continue                    # a call or a declaration
+                depth = 0
+                while k < len(text):           # the body
+                    depth += {"{": 1, "}": -1}.get(text[k], 0)
+                    k += 1
+                    if depth == 0:
+                        break
+                piece = text[m.start():k]
+            if piece is None:
+                return None
+            h.update(rel.encode() + b"\0" + name.encode() + b"\0" + piece.encode() + b"\0")
+    return h.hexdigest()
+
+
 def measured_traffic(kernel, prec):
     """HBM bytes per launch from the committed rocprofv3 counter runs, or None
-    when the kernel source changed since they were taken."""
+    when the kernel's source changed since they were taken: the record names
+    either whole files (sha256 of each) or the kernel's own functions and
+    constants (one digest over them, `source_digest`)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -167,6 +215,9 @@ def measured_traffic(kernel, prec):
                 return None
         except OSError:
             return None
+    dig = rec.get("source_digest")
+    if dig is not None and source_digest(dig.get("spec", {})) != dig.get("sha256"):
+        return None
     if rec.get("precision") != prec or kernel not in rec.get("kernels", {}):
         return None
     return rec["kernels"][kernel]["bytes_per_launch"]

@@ -82,3 +82,30 @@ def test_nominal_gate_work_and_per_gate_fraction():
     assert r["frac"] == pytest.approx(w32["t_roof_ms"] / 500.0)
     assert r["counted_flops_per_gate"] == pytest.approx(3.1e11)
     assert r["algorithmic_bytes_per_gate"] == pytest.approx(1.1e10)
+
+
+def test_traffic_digest_follows_the_kernel_only(tmp_path, monkeypatch):
+    """A record keyed by the kernel's own functions and constants stays valid
+    when another function of the file changes and is dropped when the kernel,
+    a helper it names or a constant it names changes."""
+    src = tmp_path / "paper_2003_13163_amd" / "csrc"
+    src.mkdir(parents=True)
+    (tmp_path / "profiles").mkdir()
+    body = ("constexpr int kTile = 64;\n"
+            "__device__ double helper(double v) { return v * 2.0; }\n"
+            "__global__ void k_main(const double* x, double* y) {\n    y[0] = helper(x[0]) + kTile;\n}\n"
+            "__global__ void k_other(double* y) { y[0] = 1.0; }\n")
+    (src / "k.hip").write_text(body)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    spec = {"paper_2003_13163_amd/csrc/k.hip": ["k_main", "helper", "kTile"]}
+    rec = {"source_digest": {"spec": spec, "sha256": bench.source_digest(spec)}, "precision": "fp32",
+           "kernels": {"main": {"bytes_per_launch": 3.0e7}}}
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    assert bench.measured_traffic("main", "fp32") == pytest.approx(3.0e7)
+    (src / "k.hip").write_text(body.replace("y[0] = 1.0", "y[0] = 2.0"))       # another kernel
+    assert bench.measured_traffic("main", "fp32") == pytest.approx(3.0e7)
+    for old, new in (("v * 2.0", "v * 3.0"), ("kTile = 64", "kTile = 32"), ("+ kTile", "- kTile")):
+        (src / "k.hip").write_text(body.replace(old, new))
+        assert bench.measured_traffic("main", "fp32") is None
+    (src / "k.hip").write_text(body.replace("k_main", "k_renamed"))            # the kernel is gone
+    assert bench.measured_traffic("main", "fp32") is None
