@@ -348,10 +348,14 @@ mpo_status mpo_set_default_tuning(mpo_precision prec, int chi_upto, int block, i
  * G = theta'^H theta' (FP64), its eigenvectors V (Householder
  * tridiagonalisation, divide and conquer on the tridiagonal), and hands
  * theta' V, whose columns are orthogonal to about the FP64 eigen-solver's
- * accuracy relative to their own norms, to the one-sided Jacobi sweeps, which
- * then only polish (they still decide convergence, the values and the
- * isometries).  Every mode computes this start in FP64.  min_cols = 0 turns
- * it off.  Default 1024 (environment override MPO_PRECOND_MIN).  Handles with
+ * accuracy relative to their own norms, to the one-sided Jacobi.  In FP64
+ * storage all N columns are formed and the sweeps polish them (they still
+ * decide convergence, the values and the isometries); in FP32 storage only
+ * the columns of the chi_max + 64 largest eigenvalues are formed, one FP64
+ * Gram of them certifies their orthogonality to the sweeps' tolerance (the
+ * sweeps run only if it does not), and the weight of the other columns (the
+ * sum of their eigenvalues) enters the truncation as discarded weight.  Every
+ * mode computes this start in FP64.  min_cols = 0 turns it off.  Default 1024 (environment override MPO_PRECOND_MIN).  Handles with
  * 4 chi_cap < 512 have no eigen workspace: min_cols > 0 is MPO_ERR_ARG there. */
 mpo_status mpo_set_precond(mpo_handle *h, int min_cols);
 
